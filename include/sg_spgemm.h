@@ -1,0 +1,246 @@
+/*
+ * sg_spgemm.h - C ABI of the MI355X (gfx950) local sparse product library.
+ *
+ * The library computes C = A (x) B over a semiring for sparse operands held
+ * in device memory: the local product that every processor of Sparse SUMMA
+ * runs on its 2D blocks at each stage (paper, Sections 2.4, 3.2 and 3.5),
+ * column by column, C(:, j) = (+)_k A(:, k) (x) B(k, j) (the column-by-column
+ * formulation of Section 2.1, Figure 3), together with the accumulation of
+ * the stage partial products C_ij = (+)_k A_ik B_kj (Section 3.2). Products
+ * that share an output (a "group") are accumulated into it directly, so the
+ * stage partials are never materialised.
+ *
+ * Conventions for every entry point:
+ *  - Ids are 0-based (the paper is 1-based).
+ *  - Every array pointer inside sg_mat / sg_mat_out is a DEVICE pointer owned
+ *    by the caller; the library never frees or reallocates them.
+ *  - `ws` is a caller-owned DEVICE workspace of the size the matching
+ *    *_workspace_size call reports; the library allocates no device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Status codes are returned, never thrown; no entry point exits the
+ *    process. A call that returns an error leaves its outputs undefined.
+ *  - Operands must be canonical: ptr non-decreasing from 0, minor ids in
+ *    [0, minor dim) strictly increasing inside each vector, and for the
+ *    doubly compressed formats vid strictly increasing and every stored
+ *    vector non-empty (Section 2.3). sg_validate checks this on the device.
+ */
+#ifndef SG_SPGEMM_H
+#define SG_SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SG_OK = 0,
+    SG_ERR_INVALID_ARG = -1,   /* NULL pointer, negative size, bad enum        */
+    SG_ERR_DIM_MISMATCH = -2,  /* inner dimensions or group shapes differ      */
+    SG_ERR_NOT_CANONICAL = -3, /* sg_validate found an unsorted/duplicate id   */
+    SG_ERR_UNSUPPORTED = -4,   /* format/orientation combination not handled   */
+    SG_ERR_WORKSPACE = -5,     /* workspace smaller than the reported size     */
+    SG_ERR_CAPACITY = -6,      /* output arrays smaller than the exact result  */
+    SG_ERR_HIP = -7,           /* a HIP runtime call failed                    */
+    SG_ERR_OOM = -8            /* host allocation failed                       */
+} sg_status;
+
+/*
+ * Semiring descriptor (Section 1: the product is defined over an arbitrary
+ * semiring). The kind fixes the value type, add (+), multiply (x) and the
+ * additive identity:
+ *   SG_PLUS_TIMES_F64  double, +, *, 0
+ *   SG_PLUS_TIMES_F32  float,  +, *, 0 (accumulates in float)
+ *   SG_MIN_PLUS_I32    int32, min, saturating + (INT32_MAX is +infinity and
+ *                      absorbs), INT32_MAX
+ *   SG_OR_AND_BOOL     pattern only (val arrays are NULL), or, and
+ * Every position produced by at least one multiplication is stored, even if
+ * its value equals the additive identity (a structural product).
+ */
+typedef enum {
+    SG_PLUS_TIMES_F64 = 0,
+    SG_PLUS_TIMES_F32 = 1,
+    SG_MIN_PLUS_I32 = 2,
+    SG_OR_AND_BOOL = 3
+} sg_semiring_kind;
+
+typedef struct {
+    int32_t kind; /* sg_semiring_kind */
+} sg_semiring;
+
+/*
+ * Storage formats (Sections 2.2 and 2.3). CSR/CSC: ptr has major_dim + 1
+ * entries and vid is NULL. DCSR/DCSC (doubly compressed): vid lists the nvec
+ * non-empty major ids (the paper's JC for DCSC) and ptr has nvec + 1 entries
+ * (the paper's CP); idx/val are the paper's IR/NUM.
+ */
+typedef enum { SG_CSR = 0, SG_CSC = 1, SG_DCSR = 2, SG_DCSC = 3 } sg_format;
+
+typedef struct {
+    int32_t fmt;        /* sg_format                                         */
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nvec;       /* stored vectors: nrows (CSR), ncols (CSC), nzc/nzr  */
+    int64_t nnz;
+    const int64_t *ptr; /* device, nvec + 1                                  */
+    const int32_t *vid; /* device, nvec (doubly compressed) or NULL          */
+    const int32_t *idx; /* device, nnz                                       */
+    const void *val;    /* device, nnz values; NULL for SG_OR_AND_BOOL       */
+} sg_mat;
+
+/* Output matrix. Capacities come from sg_sym_info (exact sizes). */
+typedef struct {
+    int32_t fmt;        /* must have the operands' orientation               */
+    int64_t nrows;
+    int64_t ncols;
+    int64_t cap_nnz;    /* entries available in idx/val                      */
+    int64_t cap_vec;    /* entries available in vid (doubly compressed only) */
+    int64_t *ptr;       /* device: major_dim + 1 (CSR/CSC) or cap_vec + 1    */
+    int32_t *vid;       /* device, doubly compressed only, else NULL         */
+    int32_t *idx;       /* device                                            */
+    void *val;          /* device; NULL for SG_OR_AND_BOOL                   */
+} sg_mat_out;
+
+/*
+ * Tuning knobs of the flops-binned numeric tiers. sg_tuning_default fills
+ * the values the library uses when a NULL tuning pointer is passed.
+ *   tiny_max_flops   vectors with at most this many multiplications run on
+ *                    one wavefront with a register sort/merge (<= 64)
+ *   mid_max_ub       vectors whose size bound min(flops, minor dim) is at
+ *                    most this use one workgroup with an LDS-resident
+ *                    accumulator (bitmap-rank or open-addressing hash)
+ *   mid_kind         0 = bitmap-rank accumulator, 1 = LDS hash accumulator
+ *   lds_bytes        LDS budget of one workgroup of the mid/heavy tiers
+ *   block_threads    threads per workgroup of the mid/heavy tiers (64..1024)
+ *   chunk_width      heavy tier: output-index window of one dense LDS
+ *                    accumulator (0 = the largest that fits lds_bytes)
+ *   heavy_kind       0 = windowed dense accumulator reading the operand in
+ *                    place, 1 = expand-sort-compress through global memory
+ *   force_tier       -1 = bin by size; 0/1/2 = route every vector with
+ *                    work to the tiny / mid / heavy tier where it is legal
+ *                    (tiny needs flops <= 64, mid needs the bound to fit)
+ *   blocks_per_cu    workgroups per compute unit of the persistent launches
+ *   validate         non-zero: run sg_validate on every operand first
+ */
+typedef struct {
+    int32_t tiny_max_flops;
+    int32_t mid_max_ub;
+    int32_t mid_kind;
+    int32_t lds_bytes;
+    int32_t block_threads;
+    int32_t chunk_width;
+    int32_t heavy_kind;
+    int32_t force_tier;
+    int32_t blocks_per_cu;
+    int32_t validate;
+} sg_tuning;
+
+/* Host-side sizes of one output, valid when sg_spgemm_symbolic returns. */
+typedef struct {
+    int64_t flops;       /* multiplications (Section 1's flops)              */
+    int64_t nnz_ub;      /* sum over output vectors of min(flops_j, minor)   */
+    int64_t nnz;         /* exact nnz(C)                                     */
+    int64_t nvec;        /* stored vectors of C for its format               */
+    int64_t max_vec_flops;
+    int64_t n_out_vec;   /* output vectors with at least one stored input   */
+    int64_t n_tiny;      /* vectors per tier                                 */
+    int64_t n_mid;
+    int64_t n_heavy;
+    int64_t n_heavy_items; /* (vector, window) work items of the heavy tier  */
+} sg_sym_info;
+
+typedef struct sg_plan sg_plan;
+
+/* Defaults for a semiring (see sg_tuning). */
+void sg_tuning_default(int32_t semiring_kind, sg_tuning *tuning);
+
+/* Static text for a status code. */
+const char *sg_status_string(int32_t status);
+
+/*
+ * Device workspace needed by sg_spgemm_symbolic for the same arguments.
+ * Host-only: reads no device memory. Arguments as in sg_spgemm_symbolic.
+ */
+sg_status sg_spgemm_workspace_size(const sg_semiring *sr, int32_t nprod,
+                                   const sg_mat *A, const sg_mat *B,
+                                   const int32_t *group, int32_t ngroup,
+                                   int32_t out_fmt, const sg_tuning *tuning,
+                                   size_t *ws_bytes);
+
+/*
+ * Symbolic phase of C_g = (+)_{p : group[p] = g} A_p (x) B_p.
+ *
+ * nprod products (host arrays A[nprod], B[nprod] of descriptors of device
+ * data) are accumulated into ngroup outputs; group[p] in [0, ngroup) (host
+ * array; NULL means group[p] = p and ngroup = nprod). All operands share one
+ * orientation: column-major (CSC/DCSC; C is column-major, the columns of B
+ * are streamed and the columns of A gathered, Section 2.1) or row-major
+ * (CSR/DCSR; rows of A streamed, rows of B gathered). Within a group all
+ * products have the same m x n output shape and inner dimensions must agree
+ * per product. out_fmt is the format of every C_g.
+ *
+ * The phase computes flops per output vector and the bound min(flops,
+ * minor dim) (the symbolic pass), bins vectors into the tiny / mid / heavy
+ * tiers, counts the exact size of every output vector and builds the output
+ * pointers. For doubly compressed gathered operands the column lookup uses
+ * the AUX index of Section 2.3. It ends with one stream synchronisation and
+ * fills info[g] (host array of ngroup) for each group.
+ *
+ * *plan receives a library-owned handle (host memory only) that refers to
+ * ws and to the operand arrays: both must stay alive and structurally
+ * unchanged until sg_plan_destroy; the operand VALUES may change between
+ * numeric calls. Errors: INVALID_ARG, DIM_MISMATCH, UNSUPPORTED, WORKSPACE,
+ * NOT_CANONICAL (when tuning->validate), HIP.
+ */
+sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod,
+                             const sg_mat *A, const sg_mat *B,
+                             const int32_t *group, int32_t ngroup,
+                             int32_t out_fmt, const sg_tuning *tuning,
+                             void *ws, size_t ws_bytes, sg_plan **plan,
+                             sg_sym_info *info, void *stream);
+
+/*
+ * Numeric phase: writes every C_g (host array C[ngroup] of descriptors of
+ * caller-allocated device arrays with capacities >= info[g].nnz / .nvec).
+ * Stream-ordered and asynchronous, with one kernel launch per tier. Output
+ * is canonical (ids ascending inside each vector; doubly compressed output
+ * elides empty vectors). Errors: INVALID_ARG, CAPACITY, HIP.
+ */
+sg_status sg_spgemm_numeric(sg_plan *plan, sg_mat_out *C, void *stream);
+
+/*
+ * Batched numeric phase: the same result as sg_spgemm_numeric, computed by
+ * ONE persistent launch whose workgroups pull (output vector, tier) work
+ * items of every product and group from a device queue, heaviest first. It
+ * records no memset and no host synchronisation, so it can be captured in a
+ * hipGraph and replayed; a replay recomputes C from the current operand
+ * values. Errors: as sg_spgemm_numeric.
+ */
+sg_status sg_spgemm_batched(sg_plan *plan, sg_mat_out *C, void *stream);
+
+/* Release a plan (host memory only; the workspace stays the caller's). */
+sg_status sg_plan_destroy(sg_plan *plan);
+
+/*
+ * Check that one operand is canonical (see the conventions above) on the
+ * device. `ws` needs 64 bytes of device memory. Synchronises the stream.
+ * Returns SG_OK or SG_ERR_NOT_CANONICAL.
+ */
+sg_status sg_validate(const sg_mat *M, void *ws, void *stream);
+
+/*
+ * Build the AUX column index of a doubly compressed matrix (Section 2.3):
+ * with chunk = ceil(major_dim / nvec) columns, aux[c] is the position in vid
+ * of the first stored vector whose id is >= c * chunk, for c in
+ * [0, nchunks), and aux[nchunks] = nvec, where nchunks = ceil(major_dim /
+ * chunk). `aux` is a device array of nchunks + 1 entries; *nchunks_out
+ * (host) receives nchunks. Asynchronous.
+ */
+sg_status sg_build_aux(const sg_mat *M, int32_t *aux, int64_t *nchunks_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_SPGEMM_H */

@@ -1,0 +1,371 @@
+"""ctypes binding of the C ABI in include/sg_spgemm.h (argument marshalling only).
+
+PyTorch supplies device memory and the stream; every step of the product
+runs in the library's HIP kernels. There is no CPU fallback: if the shared
+library is missing, loading fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgspgemm.so")
+
+SEMIRINGS = {"plus_times_f64": 0, "plus_times_f32": 1, "min_plus_i32": 2, "or_and_bool": 3}
+FORMATS = {"csr": 0, "csc": 1, "dcsr": 2, "dcsc": 3}
+FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID_ARG", -2: "SG_ERR_DIM_MISMATCH", -3: "SG_ERR_NOT_CANONICAL",
+          -4: "SG_ERR_UNSUPPORTED", -5: "SG_ERR_WORKSPACE", -6: "SG_ERR_CAPACITY", -7: "SG_ERR_HIP",
+          -8: "SG_ERR_OOM"}
+
+EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
+           "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_destroy", "sg_validate", "sg_build_aux"]
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class sg_semiring(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32)]
+
+
+class sg_mat(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64),
+                ("nvec", ctypes.c_int64), ("nnz", ctypes.c_int64), ("ptr", ctypes.c_void_p),
+                ("vid", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class sg_mat_out(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64),
+                ("cap_nnz", ctypes.c_int64), ("cap_vec", ctypes.c_int64), ("ptr", ctypes.c_void_p),
+                ("vid", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class sg_tuning(ctypes.Structure):
+    _fields_ = [("tiny_max_flops", ctypes.c_int32), ("mid_max_ub", ctypes.c_int32), ("mid_kind", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("chunk_width", ctypes.c_int32),
+                ("heavy_kind", ctypes.c_int32), ("force_tier", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("validate", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class sg_sym_info(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("flops", "nnz_ub", "nnz", "nvec", "max_vec_flops", "n_out_vec",
+                                              "n_tiny", "n_mid", "n_heavy", "n_heavy_items")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (no compute). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing; build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.sg_tuning_default.restype = None
+    lib.sg_tuning_default.argtypes = [ctypes.c_int32, P(sg_tuning)]
+    lib.sg_status_string.restype = ctypes.c_char_p
+    lib.sg_status_string.argtypes = [ctypes.c_int32]
+    lib.sg_spgemm_workspace_size.restype = ctypes.c_int
+    lib.sg_spgemm_workspace_size.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_int32, P(sg_tuning), P(ctypes.c_size_t)]
+    lib.sg_spgemm_symbolic.restype = ctypes.c_int
+    lib.sg_spgemm_symbolic.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.c_int32, P(sg_tuning), ctypes.c_void_p, ctypes.c_size_t,
+                                       P(ctypes.c_void_p), P(sg_sym_info), ctypes.c_void_p]
+    lib.sg_spgemm_numeric.restype = ctypes.c_int
+    lib.sg_spgemm_numeric.argtypes = [ctypes.c_void_p, P(sg_mat_out), ctypes.c_void_p]
+    lib.sg_spgemm_batched.restype = ctypes.c_int
+    lib.sg_spgemm_batched.argtypes = [ctypes.c_void_p, P(sg_mat_out), ctypes.c_void_p]
+    lib.sg_plan_destroy.restype = ctypes.c_int
+    lib.sg_plan_destroy.argtypes = [ctypes.c_void_p]
+    lib.sg_validate.restype = ctypes.c_int
+    lib.sg_validate.argtypes = [P(sg_mat), ctypes.c_void_p, ctypes.c_void_p]
+    lib.sg_build_aux.restype = ctypes.c_int
+    lib.sg_build_aux.argtypes = [P(sg_mat), ctypes.c_void_p, P(ctypes.c_int64), ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise SgError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _value_dtype(semiring: str):
+    torch = _torch()
+    return {"plus_times_f64": torch.float64, "plus_times_f32": torch.float32,
+            "min_plus_i32": torch.int32, "or_and_bool": None}[semiring]
+
+
+def default_tuning(semiring: str) -> sg_tuning:
+    t = sg_tuning()
+    load_library().sg_tuning_default(SEMIRINGS[semiring], ctypes.byref(t))
+    return t
+
+
+def make_tuning(semiring: str, **kw) -> sg_tuning:
+    t = default_tuning(semiring)
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+class DevMat:
+    """A sparse operand or result whose arrays are torch tensors on the GPU."""
+
+    def __init__(self, fmt: str, nrows: int, ncols: int, ptr, idx, val=None, vid=None):
+        self.fmt = fmt
+        self.nrows = int(nrows)
+        self.ncols = int(ncols)
+        self.ptr = ptr
+        self.idx = idx
+        self.val = val
+        self.vid = vid
+
+    @property
+    def nnz(self) -> int:
+        return int(self.idx.numel())
+
+    @property
+    def nvec(self) -> int:
+        return int(self.ptr.numel() - 1)
+
+    @classmethod
+    def from_host(cls, M, device="cuda", semiring: Optional[str] = None):
+        """Copy a host matrix (numpy arrays: fmt, nrows, ncols, ptr, idx, val, vid) to the device."""
+        torch = _torch()
+        ptr = torch.as_tensor(np.ascontiguousarray(M.ptr, dtype=np.int64)).to(device)
+        idx = torch.as_tensor(np.ascontiguousarray(M.idx, dtype=np.int32)).to(device)
+        val = None
+        if M.val is not None and semiring != "or_and_bool":
+            val = torch.as_tensor(np.ascontiguousarray(M.val)).to(device)
+        vid = None
+        if M.fmt in ("dcsr", "dcsc"):
+            vid = torch.as_tensor(np.ascontiguousarray(M.vid, dtype=np.int32)).to(device)
+        return cls(M.fmt, M.nrows, M.ncols, ptr, idx, val, vid)
+
+    def to_host(self):
+        """numpy copy (a simple namespace with the same fields)."""
+        import types
+        return types.SimpleNamespace(
+            fmt=self.fmt, nrows=self.nrows, ncols=self.ncols, ptr=self.ptr.cpu().numpy(),
+            idx=self.idx.cpu().numpy(), val=None if self.val is None else self.val.cpu().numpy(),
+            vid=None if self.vid is None else self.vid.cpu().numpy())
+
+    def desc(self) -> sg_mat:
+        d = sg_mat()
+        d.fmt = FORMATS[self.fmt]
+        d.nrows = self.nrows
+        d.ncols = self.ncols
+        d.nvec = self.nvec
+        d.nnz = self.nnz
+        d.ptr = self.ptr.data_ptr()
+        d.vid = self.vid.data_ptr() if self.vid is not None and self.vid.numel() else None
+        d.idx = self.idx.data_ptr() if self.idx.numel() else None
+        d.val = self.val.data_ptr() if self.val is not None and self.val.numel() else None
+        return d
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A symbolic plan: the library handle, its workspace and the operands it refers to."""
+
+    def __init__(self, semiring, As, Bs, group, ngroup, out_fmt, tuning, handle, ws, infos):
+        self.semiring = semiring
+        self.As, self.Bs = list(As), list(Bs)
+        self.group = group
+        self.ngroup = ngroup
+        self.out_fmt = out_fmt
+        self.tuning = tuning
+        self.handle = handle
+        self.ws = ws
+        self.infos = infos
+
+    def destroy(self):
+        if self.handle:
+            load_library().sg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def out_shapes(self):
+        shapes = []
+        for g in range(self.ngroup):
+            p = self.group.index(g) if self.group is not None else g
+            shapes.append((self.As[p].nrows, self.Bs[p].ncols))
+        return shapes
+
+    def alloc_outputs(self, device="cuda") -> List[DevMat]:
+        """Exactly sized output matrices (torch allocations) for every group."""
+        torch = _torch()
+        vdt = _value_dtype(self.semiring)
+        outs = []
+        for g, (m, n) in enumerate(self.out_shapes()):
+            info = self.infos[g]
+            nnz = info["nnz"]
+            doubly = self.out_fmt in ("dcsr", "dcsc")
+            nvec = info["nvec"]
+            ptr = torch.empty(nvec + 1, dtype=torch.int64, device=device)
+            vid = torch.empty(nvec, dtype=torch.int32, device=device) if doubly else None
+            idx = torch.empty(nnz, dtype=torch.int32, device=device)
+            val = torch.empty(nnz, dtype=vdt, device=device) if vdt is not None else None
+            outs.append(DevMat(self.out_fmt, m, n, ptr, idx, val, vid))
+        return outs
+
+
+def _out_descs(Cs: Sequence[DevMat]):
+    arr = (sg_mat_out * len(Cs))()
+    for i, C in enumerate(Cs):
+        d = arr[i]
+        d.fmt = FORMATS[C.fmt]
+        d.nrows = C.nrows
+        d.ncols = C.ncols
+        d.cap_nnz = C.idx.numel()
+        d.cap_vec = C.vid.numel() if C.vid is not None else 0
+        d.ptr = C.ptr.data_ptr()
+        d.vid = C.vid.data_ptr() if C.vid is not None and C.vid.numel() else None
+        d.idx = C.idx.data_ptr() if C.idx.numel() else None
+        d.val = C.val.data_ptr() if C.val is not None and C.val.numel() else None
+    return arr
+
+
+def _descs(Ms: Sequence[DevMat]):
+    arr = (sg_mat * len(Ms))()
+    for i, M in enumerate(Ms):
+        arr[i] = M.desc()
+    return arr
+
+
+def workspace_size(semiring, As, Bs, group=None, ngroup=None, out_fmt=None, tuning=None) -> int:
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    out_fmt = out_fmt or As[0].fmt
+    A = _descs(As)
+    B = _descs(Bs)
+    g, ng = _groups(group, ngroup, len(As))
+    sz = ctypes.c_size_t(0)
+    _check(lib.sg_spgemm_workspace_size(ctypes.byref(sr), len(As), A, B, g, ng, FORMATS[out_fmt],
+                                        ctypes.byref(tuning) if tuning is not None else None, ctypes.byref(sz)),
+           "sg_spgemm_workspace_size")
+    return int(sz.value)
+
+
+def _groups(group, ngroup, nprod):
+    if group is None:
+        return None, nprod
+    arr = (ctypes.c_int32 * nprod)(*[int(x) for x in group])
+    return ctypes.cast(arr, ctypes.c_void_p), int(ngroup if ngroup is not None else max(group) + 1)
+
+
+def spgemm_symbolic(semiring: str, As: Sequence[DevMat], Bs: Sequence[DevMat], group=None, ngroup=None,
+                    out_fmt: Optional[str] = None, tuning: Optional[sg_tuning] = None, stream=None,
+                    ws=None) -> Plan:
+    """Symbolic phase (sizes, tiers, exact counts) of C_g = sum over group g of A_p B_p."""
+    torch = _torch()
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    out_fmt = out_fmt or As[0].fmt
+    A = _descs(As)
+    B = _descs(Bs)
+    garr, ng = _groups(group, ngroup, len(As))
+    sz = ctypes.c_size_t(0)
+    tptr = ctypes.byref(tuning) if tuning is not None else None
+    _check(lib.sg_spgemm_workspace_size(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], tptr,
+                                        ctypes.byref(sz)), "sg_spgemm_workspace_size")
+    if ws is None or ws.numel() < sz.value:
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=As[0].ptr.device)
+    handle = ctypes.c_void_p(0)
+    infos = (sg_sym_info * ng)()
+    _check(lib.sg_spgemm_symbolic(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], tptr,
+                                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ctypes.byref(handle),
+                                  infos, _stream(stream)), "sg_spgemm_symbolic")
+    glist = None if group is None else [int(x) for x in group]
+    return Plan(semiring, As, Bs, glist, ng, out_fmt, tuning, handle, ws, [infos[i].as_dict() for i in range(ng)])
+
+
+def spgemm_numeric(plan: Plan, Cs: Sequence[DevMat], stream=None):
+    arr = _out_descs(Cs)
+    _check(load_library().sg_spgemm_numeric(plan.handle, arr, _stream(stream)), "sg_spgemm_numeric")
+
+
+def spgemm_batched(plan: Plan, Cs: Sequence[DevMat], stream=None):
+    arr = _out_descs(Cs)
+    _check(load_library().sg_spgemm_batched(plan.handle, arr, _stream(stream)), "sg_spgemm_batched")
+
+
+def spgemm(semiring: str, A: DevMat, B: DevMat, out_fmt: Optional[str] = None, tuning=None, batched=False,
+           stream=None) -> DevMat:
+    """C = A (x) B in one call (symbolic, allocation, numeric)."""
+    plan = spgemm_symbolic(semiring, [A], [B], out_fmt=out_fmt, tuning=tuning, stream=stream)
+    C = plan.alloc_outputs(A.ptr.device)
+    (spgemm_batched if batched else spgemm_numeric)(plan, C, stream)
+    plan.destroy()
+    return C[0]
+
+
+def spgemm_grouped(semiring: str, As, Bs, group, ngroup, out_fmt=None, tuning=None, batched=True, stream=None):
+    """C_g = (+) over p with group[p] = g of A_p (x) B_p, every product in one plan."""
+    plan = spgemm_symbolic(semiring, As, Bs, group, ngroup, out_fmt=out_fmt, tuning=tuning, stream=stream)
+    C = plan.alloc_outputs(As[0].ptr.device)
+    (spgemm_batched if batched else spgemm_numeric)(plan, C, stream)
+    plan.destroy()
+    return C
+
+
+def validate(M: DevMat, stream=None) -> bool:
+    torch = _torch()
+    ws = torch.empty(64, dtype=torch.uint8, device=M.ptr.device)
+    d = M.desc()
+    st = load_library().sg_validate(ctypes.byref(d), ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+    if st == -3:
+        return False
+    _check(st, "sg_validate")
+    return True
+
+
+def build_aux(M: DevMat, stream=None):
+    """AUX column index of a doubly compressed matrix (device int32 tensor)."""
+    torch = _torch()
+    maj = M.nrows if M.fmt == "dcsr" else M.ncols
+    nvec = M.nvec
+    chunk = -(-maj // nvec) if nvec > 0 else max(maj, 1)
+    chunk = max(chunk, 1)
+    nchunks = -(-maj // chunk)
+    aux = torch.empty(nchunks + 1, dtype=torch.int32, device=M.ptr.device)
+    n = ctypes.c_int64(0)
+    d = M.desc()
+    _check(load_library().sg_build_aux(ctypes.byref(d), ctypes.c_void_p(aux.data_ptr()), ctypes.byref(n),
+                                       _stream(stream)), "sg_build_aux")
+    assert n.value == nchunks
+    return aux

@@ -1,0 +1,309 @@
+// Device-side types and wavefront helpers of the local sparse product library.
+//
+// Terminology used throughout the kernels (column-major view; the row-major
+// case is the same on the transposes):
+//   S  the streamed operand, whose vectors define the output vectors
+//      (B for C = A B in CSC/DCSC, A in CSR/DCSR),
+//   G  the gathered operand, whose vector k is fetched for every stored
+//      entry (k, s) of an S vector (A in CSC/DCSC, B in CSR/DCSR).
+// C(:, j) = (+)_{(k, s) in S(:, j)} G(:, k) (x) s, the column-by-column
+// formulation (paper, Section 2.1). The four semirings' multiplies are all
+// commutative, so g (x) s equals the paper's A(i,k) (x) B(k,j) in both
+// orientations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sg_spgemm.h"
+
+namespace sg {
+
+constexpr int kWave = 64;
+constexpr int kMaxWaves = 16;  // 1024 threads per workgroup at most
+
+// One product A_p (x) B_p, in S/G terms, as the kernels see it.
+struct ProdDev {
+  const int64_t *s_ptr;
+  const int32_t *s_vid;  // major ids of S vectors (doubly compressed) or null
+  const int32_t *s_idx;
+  const void *s_val;
+  int64_t s_nvec;
+  const int64_t *g_ptr;
+  const int32_t *g_vid;  // doubly compressed G: ids of stored vectors, else null
+  const int32_t *g_idx;
+  const void *g_val;
+  int64_t g_nvec;
+  int64_t g_major;       // number of vectors of G as a matrix (its major dimension)
+  const int32_t *aux;    // AUX index of a doubly compressed G (Section 2.3), else null
+  int64_t aux_chunk;     // columns per AUX chunk
+  int64_t aux_n;         // number of AUX chunks
+  int32_t *gres;         // per S entry: resolved G vector (doubly compressed G only)
+  int32_t *wsplit;       // per G vector: nwin + 1 offsets of the output windows, or null
+  int32_t group;
+  int32_t nwin;          // output windows of this product's group
+};
+
+// One output C_g.
+struct GroupDev {
+  int64_t minor;         // minor dimension of C_g (its output id range)
+  int64_t major;         // major dimension of C_g
+  int32_t nwin;          // heavy-tier windows covering [0, minor)
+  int32_t mid_ok;        // largest mid-tier vector of this group (0: the mid tier does not fit)
+  int64_t ov_begin;      // first output vector of this group (device-filled)
+  int64_t ov_end;
+  int64_t nnz_base;      // global exclusive offset of the group's first entry
+  int64_t nz_base;       // global count of non-empty vectors before the group
+};
+
+struct OutDev {
+  int64_t *ptr;
+  int32_t *vid;
+  int32_t *idx;
+  void *val;
+  int32_t fmt;
+  int32_t pad;
+};
+
+// Per-group statistics written by the symbolic kernels (int64 each).
+enum GroupStat {
+  kStFlops = 0,
+  kStUb,
+  kStMaxFlops,
+  kStTiny,
+  kStMid,
+  kStHeavy,
+  kStItems,
+  kStNnz,
+  kStNvec,
+  kStOutVec,
+  kStCount
+};
+
+// Global device counters (int64 each).
+enum Counter {
+  kCtNov = 0,      // output vectors
+  kCtNseg,         // segments
+  kCtTiny,         // tiny-tier vectors
+  kCtMid,          // mid-tier vectors
+  kCtHeavy,        // heavy-tier vectors
+  kCtItems,        // heavy-tier (vector, window) items
+  kCtQueue,        // work queue head of the persistent launch
+  kCtQueueCount,   // work queue head of the persistent count launch
+  kCtBad,          // validation failures
+  kCtNum
+};
+
+// Everything a numeric or count kernel reads, passed by value.
+struct Plan {
+  const ProdDev *prods;
+  const GroupDev *groups;
+  const OutDev *outs;
+  const int32_t *ov_id;
+  const int32_t *ov_group;
+  const int64_t *ov_seg;
+  const int32_t *seg_prod;
+  const int32_t *seg_svec;
+  int64_t *ov_flops;
+  int64_t *ov_cnt;
+  const int64_t *ov_off;   // global exclusive scan of ov_cnt
+  const int64_t *counters;
+  const int32_t *tiny_list;
+  const int32_t *mid_list;
+  const int32_t *heavy_list;
+  const int32_t *item_vec;   // heavy item -> position in heavy_list
+  const int32_t *item_win;   // heavy item -> window
+  int32_t *item_cnt;
+  int64_t *item_off;         // exclusive, relative to the group's first entry
+  int32_t win;               // window width of the heavy tier
+  int32_t mid_cap;           // max entries of a mid-tier vector
+  int32_t mid_kind;          // 0 bitmap-rank, 1 hash
+  int32_t lds_words;         // dynamic LDS size in 32-bit words
+};
+
+// ---------------------------------------------------------------------------
+// Semiring traits. Every accumulator slot in LDS starts as all-zero bits,
+// which must encode the additive identity: 0.0 for (+,*), and for (min,+)
+// the slot holds INT32_MAX - v as an unsigned word, so the identity
+// (INT32_MAX) is 0 and min becomes an unsigned max.
+template <int K>
+struct Sr;
+
+template <>
+struct Sr<SG_PLUS_TIMES_F64> {
+  typedef double T;      // value type
+  typedef double Slot;   // accumulator slot in LDS
+  static constexpr bool kVal = true;
+  __device__ static T mul(T s, T g) { return s * g; }
+  __device__ static T add(T a, T b) { return a + b; }
+  __device__ static Slot enc(T v) { return v; }
+  __device__ static T dec(Slot v) { return v; }
+  __device__ static void acc(Slot *p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+template <>
+struct Sr<SG_PLUS_TIMES_F32> {
+  typedef float T;
+  typedef float Slot;
+  static constexpr bool kVal = true;
+  __device__ static T mul(T s, T g) { return s * g; }
+  __device__ static T add(T a, T b) { return a + b; }
+  __device__ static Slot enc(T v) { return v; }
+  __device__ static T dec(Slot v) { return v; }
+  __device__ static void acc(Slot *p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+template <>
+struct Sr<SG_MIN_PLUS_I32> {
+  typedef int32_t T;
+  typedef uint32_t Slot;
+  static constexpr bool kVal = true;
+  __device__ static T mul(T s, T g) {
+    if (s == INT32_MAX || g == INT32_MAX) return INT32_MAX;
+    int64_t r = (int64_t)s + (int64_t)g;
+    if (r > INT32_MAX) return INT32_MAX;
+    if (r < INT32_MIN) return INT32_MIN;
+    return (T)r;
+  }
+  __device__ static T add(T a, T b) { return a < b ? a : b; }
+  __device__ static Slot enc(T v) { return (uint32_t)INT32_MAX - (uint32_t)v; }
+  __device__ static T dec(Slot u) { return (T)((uint32_t)INT32_MAX - u); }
+  __device__ static void acc(Slot *p, T v) {
+    __hip_atomic_fetch_max(p, enc(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+template <>
+struct Sr<SG_OR_AND_BOOL> {
+  typedef uint32_t T;  // unused: pattern only
+  typedef uint32_t Slot;
+  static constexpr bool kVal = false;
+  __device__ static T mul(T, T) { return 1u; }
+  __device__ static T add(T, T) { return 1u; }
+  __device__ static Slot enc(T v) { return v; }
+  __device__ static T dec(Slot v) { return v; }
+  __device__ static void acc(Slot *, T) {}
+};
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int l = lane();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int t = __shfl_up(x, d, kWave);
+    if (l >= d) x += t;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
+  const int l = lane();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int64_t t = __shfl_up(x, d, kWave);
+    if (l >= d) x += t;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_max64(int64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    int64_t t = __shfl_xor(x, d, kWave);
+    x = t > x ? t : x;
+  }
+  return x;
+}
+
+// Uniform read of lane o's value (o is wave-uniform).
+__device__ __forceinline__ int read_lane(int x, int o) { return __builtin_amdgcn_readlane(x, o); }
+__device__ __forceinline__ int64_t read_lane64(int64_t x, int o) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, o);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), o);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double read_lane_f64(double x, int o) {
+  return __longlong_as_double(read_lane64(__double_as_longlong(x), o));
+}
+__device__ __forceinline__ float read_lane_f32(float x, int o) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), o));
+}
+__device__ __forceinline__ int32_t read_lane_val(int32_t x, int o) { return read_lane(x, o); }
+__device__ __forceinline__ uint32_t read_lane_val(uint32_t x, int o) { return (uint32_t)read_lane((int)x, o); }
+__device__ __forceinline__ double read_lane_val(double x, int o) { return read_lane_f64(x, o); }
+__device__ __forceinline__ float read_lane_val(float x, int o) { return read_lane_f32(x, o); }
+
+// Smallest lane l with P[l] > f, for an inclusive prefix P held one per lane
+// (every lane must execute this call).
+__device__ __forceinline__ int owner_of(int P, int f) {
+  int lo = 0;
+#pragma unroll
+  for (int step = kWave / 2; step > 0; step >>= 1) {
+    int pc = __shfl(P, lo + step - 1, kWave);
+    if (pc <= f) lo += step;
+  }
+  return lo;
+}
+
+// Exclusive scan across the workgroup; `scratch` holds kMaxWaves + 1 int64.
+__device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *scratch, int64_t *total) {
+  const int l = lane();
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  int64_t inc = wave_incl_scan64(x);
+  if (l == kWave - 1) scratch[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < nw; ++i) {
+      int64_t t = scratch[i];
+      scratch[i] = run;
+      run += t;
+    }
+    scratch[nw] = run;
+  }
+  __syncthreads();
+  int64_t r = scratch[w] + inc - x;
+  *total = scratch[nw];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int64_t block_sum(int64_t x, int64_t *scratch) {
+  int64_t total;
+  block_excl_scan(x, scratch, &total);
+  return total;
+}
+
+// Locate vector k of a doubly compressed G via its AUX index; -1 if absent.
+__device__ __forceinline__ int32_t aux_find(const ProdDev &d, int64_t k) {
+  if (k < 0 || k >= d.g_major) return -1;
+  int64_t c = k / d.aux_chunk;
+  int32_t lo = d.aux[c], hi = d.aux[c + 1];
+  while (lo < hi) {
+    int32_t mid = lo + ((hi - lo) >> 1);
+    if (d.g_vid[mid] < k) lo = mid + 1; else hi = mid;
+  }
+  return (lo < d.aux[c + 1] && d.g_vid[lo] == k) ? lo : -1;
+}
+
+}  // namespace sg

@@ -1,0 +1,876 @@
+// Host side of the C ABI declared in include/sg_spgemm.h: argument checks,
+// workspace layout, and the launch sequences of the symbolic, numeric and
+// batched phases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sg_device.h"
+#include "sg_symbolic.h"
+#include "sg_tiers.h"
+
+using namespace sg;
+
+namespace {
+
+#define SG_HIP(call)                          \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return SG_ERR_HIP;  \
+  } while (0)
+
+#define SG_TRY(call)                \
+  do {                              \
+    sg_status s_ = (call);          \
+    if (s_ != SG_OK) return s_;     \
+  } while (0)
+
+constexpr int kFillThreads = 256;
+constexpr int64_t kMaxGrid = 65536;
+
+int64_t grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  return g < kMaxGrid ? g : kMaxGrid;
+}
+
+bool row_major(int32_t fmt) { return fmt == SG_CSR || fmt == SG_DCSR; }
+bool doubly(int32_t fmt) { return fmt == SG_DCSR || fmt == SG_DCSC; }
+bool fmt_ok(int32_t fmt) { return fmt >= SG_CSR && fmt <= SG_DCSC; }
+
+int slot_bytes(int32_t kind) {
+  switch (kind) {
+    case SG_PLUS_TIMES_F64: return 8;
+    case SG_PLUS_TIMES_F32: return 4;
+    case SG_MIN_PLUS_I32: return 4;
+    default: return 0;
+  }
+}
+
+int64_t major_of(const sg_mat &M) { return row_major(M.fmt) ? M.nrows : M.ncols; }
+int64_t minor_of(const sg_mat &M) { return row_major(M.fmt) ? M.ncols : M.nrows; }
+
+// Bump allocator over the caller's workspace (256-byte alignment).
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base((char *)b) {}
+  template <class T>
+  T *take(int64_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += (size_t)(n > 0 ? n : 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Derived sizes of the mid and heavy tiers for one output id range.
+struct TierGeom {
+  int win;      // heavy window width (ids)
+  int lds;      // LDS bytes per workgroup
+  int threads;  // threads per workgroup
+};
+
+int heavy_window(const sg_tuning &t, int32_t kind) {
+  const int sb = slot_bytes(kind);
+  int64_t w = ((int64_t)t.lds_bytes * 8) / (8 * sb + 1);
+  // flags live at the front in whole 64-bit units; keep the value array aligned
+  while (w > 32 && 4 * (((w + 31) / 32 + 1) & ~1ll) + (int64_t)w * sb > t.lds_bytes) w -= 32;
+  w &= ~31ll;
+  if (t.chunk_width > 0 && t.chunk_width < w) w = t.chunk_width & ~31;
+  if (w < 32) w = 32;
+  return (int)w;
+}
+
+// Largest mid-tier vector (entries) for a group with `minor` output ids; 0 = mid tier unusable.
+int64_t mid_capacity(const sg_tuning &t, int32_t kind, int64_t minor) {
+  const int sb = slot_bytes(kind);
+  int64_t cap;
+  if (t.mid_kind == 0) {
+    int64_t nw32 = (minor + 31) / 32;
+    int64_t words = sb ? ((nw32 + (nw32 + 1) / 2 + 1) & ~1ll) : nw32;
+    int64_t left = (int64_t)t.lds_bytes - 4 * words;
+    if (left < 0) return 0;
+    if (sb == 0) return minor;  // the bitmap alone is the accumulator
+    cap = left / sb;
+    if (cap > 65535) cap = 65535;  // ranks are kept in 16 bits
+  } else {
+    int64_t ts = 1;
+    while (ts * 2 * (4 + sb) <= t.lds_bytes) ts *= 2;
+    cap = ts / 2;
+  }
+  if (cap > t.mid_max_ub) cap = t.mid_max_ub;
+  return cap < 0 ? 0 : cap;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct sg_plan {
+  int32_t kind = 0;
+  int32_t nprod = 0, ngroup = 0;
+  int32_t out_fmt = 0;
+  sg_tuning tune{};
+  int win = 0;
+  int ncu = 0;
+  bool dense_path = false;
+  int64_t nov_max = 0;
+  int64_t items_max = 0;
+  int64_t ndense_ptr = 0;
+  std::vector<sg_sym_info> info;
+  std::vector<int64_t> out_minor, out_major;
+  Plan P{};
+  // device pieces outside Plan
+  int64_t *counters = nullptr;
+  int64_t *gstat = nullptr;
+  int64_t *nzpos = nullptr;
+  int64_t *pbase = nullptr;
+  OutDev *outs_dev = nullptr;
+  OutDev *outs_host = nullptr;  // pinned staging of the output table
+  int64_t *host_stats = nullptr;  // pinned
+};
+
+namespace {
+
+struct Layout {
+  ProdDev *prods;
+  GroupDev *groups;
+  OutDev *outs;
+  int64_t *vbase;
+  int64_t *counters;
+  int64_t *gstat;
+  int32_t *ov_id, *ov_group, *seg_prod, *seg_svec;
+  int64_t *ov_seg, *ov_flops, *ov_cnt, *ov_off, *nzflag, *nzpos;
+  int32_t *tiny, *mid, *heavy;
+  int64_t *heavy_nwin, *ibase;
+  int32_t *item_vec, *item_win, *item_cnt;
+  int64_t *item_off;
+  std::vector<int32_t *> gres, aux, wsplit;
+  std::vector<int64_t> aux_chunk, aux_n;
+  int64_t *dbase, *dcnt, *dflag, *vpos, *spos, *dfill;
+  int64_t *pbase;
+  int64_t *part;
+  size_t bytes;
+};
+
+struct Shape {
+  int64_t nov_max = 0;
+  int64_t ndense = 0;        // sum of output major dims (multi-product groups)
+  int64_t ndense_ptr = 0;    // sum of (major + 1) for dense output pointers
+  int32_t max_nwin = 1;
+  bool dense_path = false;
+  std::vector<int32_t> nwin;  // per group
+  std::vector<int64_t> minor, major;
+  std::vector<int32_t> gres_src, wsplit_src, aux_src;  // dedupe: product sharing the table
+};
+
+struct ProdView {
+  const sg_mat *S, *G;
+};
+
+ProdView view(const sg_mat &A, const sg_mat &B) {
+  // column-major: B streamed, A gathered; row-major: A streamed, B gathered
+  return row_major(A.fmt) ? ProdView{&A, &B} : ProdView{&B, &A};
+}
+
+sg_status check_mat(const sg_mat &M, int32_t kind) {
+  if (!fmt_ok(M.fmt)) return SG_ERR_INVALID_ARG;
+  if (M.nrows < 0 || M.ncols < 0 || M.nnz < 0 || M.nvec < 0) return SG_ERR_INVALID_ARG;
+  if (M.nrows >= INT32_MAX || M.ncols >= INT32_MAX || M.nnz >= ((int64_t)1 << 40)) return SG_ERR_UNSUPPORTED;
+  const int64_t maj = major_of(M);
+  if (doubly(M.fmt)) {
+    if (M.nvec > maj) return SG_ERR_INVALID_ARG;
+    if (M.nvec > 0 && !M.vid) return SG_ERR_INVALID_ARG;
+  } else if (M.nvec != maj) {
+    return SG_ERR_INVALID_ARG;
+  }
+  if (!M.ptr) return SG_ERR_INVALID_ARG;
+  if (M.nnz > 0 && !M.idx) return SG_ERR_INVALID_ARG;
+  if (kind != SG_OR_AND_BOOL && M.nnz > 0 && !M.val) return SG_ERR_INVALID_ARG;
+  return SG_OK;
+}
+
+sg_status check_args(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B, const int32_t *group,
+                     int32_t ngroup, int32_t out_fmt, Shape &sh, std::vector<int32_t> &grp) {
+  if (!sr || sr->kind < SG_PLUS_TIMES_F64 || sr->kind > SG_OR_AND_BOOL) return SG_ERR_INVALID_ARG;
+  if (nprod < 1 || !A || !B) return SG_ERR_INVALID_ARG;
+  if (!group) ngroup = nprod;
+  if (ngroup < 1) return SG_ERR_INVALID_ARG;
+  if (!fmt_ok(out_fmt)) return SG_ERR_INVALID_ARG;
+  const bool rm = row_major(A[0].fmt);
+  if (row_major(out_fmt) != rm) return SG_ERR_UNSUPPORTED;
+  grp.resize(nprod);
+  sh.minor.assign(ngroup, -1);
+  sh.major.assign(ngroup, -1);
+  std::vector<int32_t> per_group(ngroup, 0);
+  for (int32_t p = 0; p < nprod; ++p) {
+    SG_TRY(check_mat(A[p], sr->kind));
+    SG_TRY(check_mat(B[p], sr->kind));
+    if (row_major(A[p].fmt) != rm || row_major(B[p].fmt) != rm) return SG_ERR_UNSUPPORTED;
+    if (A[p].ncols != B[p].nrows) return SG_ERR_DIM_MISMATCH;
+    const int32_t g = group ? group[p] : p;
+    if (g < 0 || g >= ngroup) return SG_ERR_INVALID_ARG;
+    grp[p] = g;
+    per_group[g]++;
+    const int64_t omaj = rm ? A[p].nrows : B[p].ncols;
+    const int64_t omin = rm ? B[p].ncols : A[p].nrows;
+    if (sh.minor[g] < 0) {
+      sh.minor[g] = omin;
+      sh.major[g] = omaj;
+    } else if (sh.minor[g] != omin || sh.major[g] != omaj) {
+      return SG_ERR_DIM_MISMATCH;
+    }
+  }
+  for (int32_t g = 0; g < ngroup; ++g) {
+    if (per_group[g] > 1) sh.dense_path = true;
+    if (sh.minor[g] < 0) {  // a group with no product: empty output of unknown shape
+      return SG_ERR_INVALID_ARG;
+    }
+  }
+  return SG_OK;
+}
+
+void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, const std::vector<int32_t> &grp,
+                int32_t ngroup, const sg_tuning &t, int win, Shape &sh) {
+  sh.nov_max = 0;
+  for (int32_t p = 0; p < nprod; ++p) sh.nov_max += view(A[p], B[p]).S->nvec;
+  sh.nwin.resize(ngroup);
+  sh.max_nwin = 1;
+  sh.ndense = 0;
+  sh.ndense_ptr = 0;
+  for (int32_t g = 0; g < ngroup; ++g) {
+    int64_t nw = (sh.minor[g] + win - 1) / win;
+    if (nw < 1) nw = 1;
+    sh.nwin[g] = (int32_t)nw;
+    sh.max_nwin = std::max<int32_t>(sh.max_nwin, (int32_t)nw);
+    sh.ndense += sh.major[g];
+    sh.ndense_ptr += sh.major[g] + 1;
+  }
+  // products whose gathered operand is the same arrays (and window count)
+  // share the AUX, resolution-free split tables
+  sh.wsplit_src.assign(nprod, -1);
+  sh.aux_src.assign(nprod, -1);
+  for (int32_t p = 0; p < nprod; ++p) {
+    const sg_mat *G = view(A[p], B[p]).G;
+    for (int32_t q = 0; q < p; ++q) {
+      const sg_mat *H = view(A[q], B[q]).G;
+      if (H->ptr == G->ptr && H->idx == G->idx && H->vid == G->vid && H->nvec == G->nvec) {
+        if (sh.aux_src[p] < 0) sh.aux_src[p] = q;
+        if (sh.wsplit_src[p] < 0 && sh.nwin[grp[q]] == sh.nwin[grp[p]]) sh.wsplit_src[p] = q;
+      }
+    }
+  }
+  (void)kind;
+  (void)t;
+}
+
+Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t ngroup, const Shape &sh,
+             const std::vector<int32_t> &grp) {
+  Layout L{};
+  Carve c(ws);
+  const int64_t nov = sh.nov_max;
+  L.prods = c.take<ProdDev>(nprod);
+  L.groups = c.take<GroupDev>(ngroup);
+  L.outs = c.take<OutDev>(ngroup);
+  L.vbase = c.take<int64_t>(nprod + 1);
+  L.counters = c.take<int64_t>(kCtNum + 8);
+  L.gstat = c.take<int64_t>((int64_t)ngroup * kStCount);
+  L.ov_id = c.take<int32_t>(nov);
+  L.ov_group = c.take<int32_t>(nov);
+  L.seg_prod = c.take<int32_t>(nov);
+  L.seg_svec = c.take<int32_t>(nov);
+  L.ov_seg = c.take<int64_t>(nov + 1);
+  L.ov_flops = c.take<int64_t>(nov);
+  L.ov_cnt = c.take<int64_t>(nov + 1);
+  L.ov_off = c.take<int64_t>(nov + 1);
+  L.nzflag = c.take<int64_t>(nov + 1);
+  L.nzpos = c.take<int64_t>(nov + 1);
+  L.tiny = c.take<int32_t>(nov);
+  L.mid = c.take<int32_t>(nov);
+  L.heavy = c.take<int32_t>(nov);
+  L.heavy_nwin = c.take<int64_t>(nov + 1);
+  L.ibase = c.take<int64_t>(nov + 1);
+  const int64_t items = nov * (int64_t)sh.max_nwin;
+  L.item_vec = c.take<int32_t>(items);
+  L.item_win = c.take<int32_t>(items);
+  L.item_cnt = c.take<int32_t>(items);
+  L.item_off = c.take<int64_t>(items);
+  L.gres.assign(nprod, nullptr);
+  L.aux.assign(nprod, nullptr);
+  L.wsplit.assign(nprod, nullptr);
+  L.aux_chunk.assign(nprod, 0);
+  L.aux_n.assign(nprod, 0);
+  for (int32_t p = 0; p < nprod; ++p) {
+    ProdView pv = view(A[p], B[p]);
+    const sg_mat &G = *pv.G;
+    if (doubly(G.fmt)) {
+      L.gres[p] = c.take<int32_t>(pv.S->nnz);
+      const int64_t maj = major_of(G);
+      int64_t chunk = G.nvec > 0 ? (maj + G.nvec - 1) / G.nvec : (maj > 0 ? maj : 1);
+      if (chunk < 1) chunk = 1;
+      int64_t nchunks = (maj + chunk - 1) / chunk;
+      L.aux_chunk[p] = chunk;
+      L.aux_n[p] = nchunks;
+      if (sh.aux_src[p] >= 0) L.aux[p] = L.aux[sh.aux_src[p]];
+      else L.aux[p] = c.take<int32_t>(nchunks + 1);
+    }
+    const int32_t nw = sh.nwin[grp[p]];
+    if (nw > 1) {
+      if (sh.wsplit_src[p] >= 0) L.wsplit[p] = L.wsplit[sh.wsplit_src[p]];
+      else L.wsplit[p] = c.take<int32_t>(G.nvec * (int64_t)(nw + 1));
+    }
+  }
+  int64_t scan_max = std::max<int64_t>(nov + 1, sh.ndense + 1);
+  L.dbase = c.take<int64_t>(ngroup + 1);
+  if (sh.dense_path) {
+    L.dcnt = c.take<int64_t>(sh.ndense + 1);
+    L.dflag = c.take<int64_t>(sh.ndense + 1);
+    L.vpos = c.take<int64_t>(sh.ndense + 1);
+    L.spos = c.take<int64_t>(sh.ndense + 1);
+    L.dfill = c.take<int64_t>(sh.ndense + 1);
+  } else {
+    L.dcnt = L.dflag = L.vpos = L.spos = L.dfill = nullptr;
+  }
+  L.pbase = c.take<int64_t>(ngroup + 1);
+  L.part = c.take<int64_t>(scan_max / kScanTile + 4);
+  L.bytes = c.off + 256;
+  return L;
+}
+
+sg_status fill64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
+  if (n <= 0) return SG_OK;
+  hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)grid_for(n, kFillThreads)), dim3(kFillThreads), 0, st, p, n, v);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+// out[0..n] = exclusive scan of in[0..n), out[n] = total.
+sg_status scan64(const int64_t *in, int64_t n, int64_t *out, int64_t *part, hipStream_t st) {
+  if (n <= 0) return fill64(out, 1, 0, st);
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, part, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, part, nb, out);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+void normalise(sg_tuning &t, int32_t kind) {
+  sg_tuning d;
+  sg_tuning_default(kind, &d);
+  if (t.tiny_max_flops < 0 || t.tiny_max_flops > 64) t.tiny_max_flops = d.tiny_max_flops;
+  if (t.mid_max_ub < 0) t.mid_max_ub = d.mid_max_ub;
+  if (t.mid_kind != 0 && t.mid_kind != 1) t.mid_kind = 0;
+  if (t.lds_bytes < 4096 || t.lds_bytes > 160 * 1024) t.lds_bytes = d.lds_bytes;
+  t.lds_bytes &= ~7;
+  if (t.block_threads < 64 || t.block_threads > 1024 || t.block_threads % 64) t.block_threads = d.block_threads;
+  if (t.chunk_width < 0) t.chunk_width = 0;
+  if (t.heavy_kind != 0) t.heavy_kind = 0;
+  if (t.force_tier < -1 || t.force_tier > 2) t.force_tier = -1;
+  if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) t.blocks_per_cu = d.blocks_per_cu;
+}
+
+template <int K>
+sg_status set_lds_attr(int bytes) {
+  SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  return SG_OK;
+}
+
+template <int K>
+sg_status launch_counts(sg_plan *pl, hipStream_t st) {
+  const Plan &P = pl->P;
+  const int nt = pl->tune.block_threads;
+  const int lds = pl->tune.lds_bytes;
+  const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
+  const int64_t tiny_blocks = std::min<int64_t>(std::max<int64_t>(1, (pl->nov_max + 3) / 4), persist * 8);
+  hipLaunchKernelGGL((k_tiny<K, true>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, P);
+  SG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_mid<K, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 0);
+  SG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_heavy<K, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 1);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+template <int K>
+sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
+  const Plan &P = pl->P;
+  const int nt = pl->tune.block_threads;
+  const int lds = pl->tune.lds_bytes;
+  const sg_sym_info &I = pl->info[0];
+  const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
+  SG_TRY(fill64(pl->counters + kCtNum + 2, 2, 0, st));
+  if (I.n_heavy_items > 0) {
+    hipLaunchKernelGGL((k_heavy<K, false>), dim3((unsigned)std::min<int64_t>(persist, I.n_heavy_items)), dim3(nt), lds, st,
+                       P, pl->counters + kCtNum + 2);
+    SG_HIP(hipGetLastError());
+  }
+  if (I.n_mid > 0) {
+    hipLaunchKernelGGL((k_mid<K, false>), dim3((unsigned)std::min<int64_t>(persist, I.n_mid)), dim3(nt), lds, st, P,
+                       pl->counters + kCtNum + 3);
+    SG_HIP(hipGetLastError());
+  }
+  if (I.n_tiny > 0) {
+    hipLaunchKernelGGL((k_tiny<K, false>), dim3((unsigned)std::min<int64_t>((I.n_tiny + 3) / 4, persist * 8)), dim3(256), 0,
+                       st, P);
+    SG_HIP(hipGetLastError());
+  }
+  return SG_OK;
+}
+
+template <int K>
+sg_status launch_batched(sg_plan *pl, hipStream_t st) {
+  const Plan &P = pl->P;
+  const int nt = pl->tune.block_threads;
+  const int lds = pl->tune.lds_bytes;
+  const sg_sym_info &I = pl->info[0];
+  const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
+  SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
+  hipLaunchKernelGGL((k_batched<K>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
+                     (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+template <template <int> class F, class... Args>
+sg_status dispatch(int32_t kind, Args... a) {
+  switch (kind) {
+    case SG_PLUS_TIMES_F64: return F<SG_PLUS_TIMES_F64>::run(a...);
+    case SG_PLUS_TIMES_F32: return F<SG_PLUS_TIMES_F32>::run(a...);
+    case SG_MIN_PLUS_I32: return F<SG_MIN_PLUS_I32>::run(a...);
+    case SG_OR_AND_BOOL: return F<SG_OR_AND_BOOL>::run(a...);
+    default: return SG_ERR_INVALID_ARG;
+  }
+}
+template <int K>
+struct RunCounts {
+  static sg_status run(sg_plan *pl, hipStream_t st) { return launch_counts<K>(pl, st); }
+};
+template <int K>
+struct RunNumeric {
+  static sg_status run(sg_plan *pl, hipStream_t st) { return launch_numeric<K>(pl, st); }
+};
+template <int K>
+struct RunBatched {
+  static sg_status run(sg_plan *pl, hipStream_t st) { return launch_batched<K>(pl, st); }
+};
+template <int K>
+struct RunAttr {
+  static sg_status run(int bytes) { return set_lds_attr<K>(bytes); }
+};
+
+sg_status emit_outputs(sg_plan *pl, sg_mat_out *C, hipStream_t st) {
+  if (!C) return SG_ERR_INVALID_ARG;
+  const bool rm = row_major(pl->out_fmt);
+  for (int32_t g = 0; g < pl->ngroup; ++g) {
+    const sg_mat_out &O = C[g];
+    const sg_sym_info &I = pl->info[g];
+    if (O.fmt != pl->out_fmt) return SG_ERR_INVALID_ARG;
+    const int64_t omaj = pl->out_major[g], omin = pl->out_minor[g];
+    if ((rm ? O.nrows : O.ncols) != omaj || (rm ? O.ncols : O.nrows) != omin) return SG_ERR_DIM_MISMATCH;
+    if (O.cap_nnz < I.nnz) return SG_ERR_CAPACITY;
+    if (!O.ptr) return SG_ERR_INVALID_ARG;
+    if (I.nnz > 0 && !O.idx) return SG_ERR_INVALID_ARG;
+    if (I.nnz > 0 && pl->kind != SG_OR_AND_BOOL && !O.val) return SG_ERR_INVALID_ARG;
+    if (doubly(pl->out_fmt)) {
+      if (O.cap_vec < I.nvec) return SG_ERR_CAPACITY;
+      if (I.nvec > 0 && !O.vid) return SG_ERR_INVALID_ARG;
+    }
+    OutDev &D = pl->outs_host[g];
+    D.ptr = O.ptr;
+    D.vid = O.vid;
+    D.idx = O.idx;
+    D.val = O.val;
+    D.fmt = O.fmt;
+    D.pad = 0;
+  }
+  SG_HIP(hipMemcpyAsync(pl->outs_dev, pl->outs_host, sizeof(OutDev) * pl->ngroup, hipMemcpyHostToDevice, st));
+  if (doubly(pl->out_fmt)) {
+    hipLaunchKernelGGL(k_emit_ptr_doubly, dim3((unsigned)grid_for(pl->nov_max + 1, kFillThreads)), dim3(kFillThreads), 0,
+                       st, pl->P, pl->nzpos, pl->ngroup);
+  } else {
+    hipLaunchKernelGGL(k_emit_ptr_dense, dim3((unsigned)grid_for(pl->ndense_ptr, kFillThreads)), dim3(kFillThreads), 0,
+                       st, pl->P, pl->pbase, pl->ngroup, pl->ndense_ptr);
+  }
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void sg_tuning_default(int32_t kind, sg_tuning *t) {
+  if (!t) return;
+  t->tiny_max_flops = 64;
+  t->mid_max_ub = 65535;
+  t->mid_kind = 0;
+  t->lds_bytes = (kind == SG_OR_AND_BOOL) ? 72 * 1024 : 64 * 1024;
+  t->block_threads = 512;
+  t->chunk_width = 0;
+  t->heavy_kind = 0;
+  t->force_tier = -1;
+  t->blocks_per_cu = 2;
+  t->validate = 0;
+}
+
+const char *sg_status_string(int32_t s) {
+  switch (s) {
+    case SG_OK: return "ok";
+    case SG_ERR_INVALID_ARG: return "invalid argument";
+    case SG_ERR_DIM_MISMATCH: return "dimension mismatch";
+    case SG_ERR_NOT_CANONICAL: return "operand not canonical";
+    case SG_ERR_UNSUPPORTED: return "unsupported format or size";
+    case SG_ERR_WORKSPACE: return "workspace too small";
+    case SG_ERR_CAPACITY: return "output capacity too small";
+    case SG_ERR_HIP: return "HIP runtime error";
+    case SG_ERR_OOM: return "host allocation failed";
+    default: return "unknown status";
+  }
+}
+
+sg_status sg_spgemm_workspace_size(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B,
+                                   const int32_t *group, int32_t ngroup, int32_t out_fmt, const sg_tuning *tuning,
+                                   size_t *ws_bytes) {
+  if (!ws_bytes) return SG_ERR_INVALID_ARG;
+  Shape sh;
+  std::vector<int32_t> grp;
+  SG_TRY(check_args(sr, nprod, A, B, group, ngroup, out_fmt, sh, grp));
+  if (!group) ngroup = nprod;
+  sg_tuning t;
+  if (tuning) t = *tuning; else sg_tuning_default(sr->kind, &t);
+  normalise(t, sr->kind);
+  const int win = heavy_window(t, sr->kind);
+  make_shape(sr->kind, nprod, A, B, grp, ngroup, t, win, sh);
+  Layout L = carve(nullptr, nprod, A, B, ngroup, sh, grp);
+  *ws_bytes = L.bytes;
+  return SG_OK;
+}
+
+sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B,
+                             const int32_t *group, int32_t ngroup, int32_t out_fmt, const sg_tuning *tuning, void *ws,
+                             size_t ws_bytes, sg_plan **plan_out, sg_sym_info *info, void *stream) {
+  if (!plan_out || !info || !ws) return SG_ERR_INVALID_ARG;
+  *plan_out = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  Shape sh;
+  std::vector<int32_t> grp;
+  SG_TRY(check_args(sr, nprod, A, B, group, ngroup, out_fmt, sh, grp));
+  if (!group) ngroup = nprod;
+  sg_tuning t;
+  if (tuning) t = *tuning; else sg_tuning_default(sr->kind, &t);
+  normalise(t, sr->kind);
+  const int win = heavy_window(t, sr->kind);
+  make_shape(sr->kind, nprod, A, B, grp, ngroup, t, win, sh);
+  Layout L = carve(ws, nprod, A, B, ngroup, sh, grp);
+  if (ws_bytes < L.bytes) return SG_ERR_WORKSPACE;
+  if (((uintptr_t)ws & 255) != 0) return SG_ERR_INVALID_ARG;
+
+  if (t.validate) {
+    for (int32_t p = 0; p < nprod; ++p) {
+      SG_TRY(sg_validate(&A[p], L.counters, stream));
+      SG_TRY(sg_validate(&B[p], L.counters, stream));
+    }
+  }
+
+  sg_plan *pl = new (std::nothrow) sg_plan();
+  if (!pl) return SG_ERR_OOM;
+  struct Guard {
+    sg_plan *p;
+    ~Guard() {
+      if (p) sg_plan_destroy(p);
+    }
+  } guard{pl};
+  pl->kind = sr->kind;
+  pl->nprod = nprod;
+  pl->ngroup = ngroup;
+  pl->out_fmt = out_fmt;
+  pl->tune = t;
+  pl->win = win;
+  pl->ncu = device_cus();
+  pl->dense_path = sh.dense_path;
+  pl->nov_max = sh.nov_max;
+  pl->ndense_ptr = sh.ndense_ptr;
+  pl->out_minor = sh.minor;
+  pl->out_major = sh.major;
+  pl->info.assign(ngroup, sg_sym_info{});
+  SG_HIP(hipHostMalloc((void **)&pl->outs_host, sizeof(OutDev) * ngroup, hipHostMallocDefault));
+  SG_HIP(hipHostMalloc((void **)&pl->host_stats, sizeof(int64_t) * ((size_t)ngroup * kStCount + kCtNum),
+                       hipHostMallocDefault));
+  SG_TRY(dispatch<RunAttr>(sr->kind, t.lds_bytes));
+
+  // host tables: products (ordered as given; output vectors follow group order)
+  std::vector<int32_t> order(nprod);
+  for (int32_t p = 0; p < nprod; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return grp[a] < grp[b]; });
+  std::vector<ProdDev> prods(nprod);
+  std::vector<int64_t> vbase(nprod + 1, 0);
+  for (int32_t q = 0; q < nprod; ++q) {
+    const int32_t p = order[q];
+    ProdView pv = view(A[p], B[p]);
+    ProdDev &d = prods[q];
+    d.s_ptr = pv.S->ptr;
+    d.s_vid = doubly(pv.S->fmt) ? pv.S->vid : nullptr;
+    d.s_idx = pv.S->idx;
+    d.s_val = pv.S->val;
+    d.s_nvec = pv.S->nvec;
+    d.g_ptr = pv.G->ptr;
+    d.g_vid = doubly(pv.G->fmt) ? pv.G->vid : nullptr;
+    d.g_idx = pv.G->idx;
+    d.g_val = pv.G->val;
+    d.g_nvec = pv.G->nvec;
+    d.g_major = major_of(*pv.G);
+    d.aux = L.aux[p];
+    d.aux_chunk = L.aux_chunk[p];
+    d.aux_n = L.aux_n[p];
+    d.gres = L.gres[p];
+    d.wsplit = L.wsplit[p];
+    d.group = grp[p];
+    d.nwin = sh.nwin[grp[p]];
+    vbase[q + 1] = vbase[q] + pv.S->nvec;
+  }
+  std::vector<GroupDev> groups(ngroup);
+  std::vector<int64_t> dbase(ngroup + 1, 0), pbase(ngroup + 1, 0);
+  for (int32_t g = 0; g < ngroup; ++g) {
+    GroupDev &G = groups[g];
+    G.minor = sh.minor[g];
+    G.major = sh.major[g];
+    G.nwin = sh.nwin[g];
+    const int64_t cap = mid_capacity(t, sr->kind, G.minor);
+    G.mid_ok = cap > 0 ? (int32_t)std::min<int64_t>(cap, INT32_MAX) : 0;
+    G.ov_begin = G.ov_end = G.nnz_base = G.nz_base = 0;
+    dbase[g + 1] = dbase[g] + sh.major[g];
+    pbase[g + 1] = pbase[g] + sh.major[g] + 1;
+  }
+  SG_HIP(hipMemcpyAsync(L.prods, prods.data(), sizeof(ProdDev) * nprod, hipMemcpyHostToDevice, st));
+  SG_HIP(hipMemcpyAsync(L.groups, groups.data(), sizeof(GroupDev) * ngroup, hipMemcpyHostToDevice, st));
+  SG_HIP(hipMemcpyAsync(L.vbase, vbase.data(), sizeof(int64_t) * (nprod + 1), hipMemcpyHostToDevice, st));
+  SG_HIP(hipMemcpyAsync(L.dbase, dbase.data(), sizeof(int64_t) * (ngroup + 1), hipMemcpyHostToDevice, st));
+  SG_HIP(hipMemcpyAsync(L.pbase, pbase.data(), sizeof(int64_t) * (ngroup + 1), hipMemcpyHostToDevice, st));
+  SG_TRY(fill64(L.counters, kCtNum + 8, 0, st));
+  SG_TRY(fill64(L.gstat, (int64_t)ngroup * kStCount, 0, st));
+  SG_TRY(fill64(L.ov_cnt, sh.nov_max + 1, 0, st));
+  SG_TRY(fill64(L.ov_flops, sh.nov_max, 0, st));
+
+  // AUX indexes of doubly compressed gathered operands
+  for (int32_t q = 0; q < nprod; ++q) {
+    const int32_t p = order[q];
+    const ProdDev &d = prods[q];
+    if (d.g_vid && sh.aux_src[p] < 0) {
+      hipLaunchKernelGGL(k_build_aux, dim3((unsigned)grid_for(d.aux_n + 1, kFillThreads)), dim3(kFillThreads), 0, st,
+                         d.g_vid, d.g_nvec, d.aux_chunk, d.aux_n, (int32_t *)d.aux);
+      SG_HIP(hipGetLastError());
+    }
+  }
+
+  // output vectors and their segments
+  if (!sh.dense_path) {
+    SG_TRY(fill64(L.counters + kCtNov, 1, sh.nov_max, st));
+    SG_TRY(fill64(L.counters + kCtNseg, 1, sh.nov_max, st));
+    SG_TRY(fill64(L.ov_seg, 1, 0, st));
+    if (sh.nov_max > 0) {
+      hipLaunchKernelGGL(k_ov_simple, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.prods, L.vbase, nprod, sh.nov_max, L.ov_id, L.ov_group, L.ov_seg, L.seg_prod, L.seg_svec);
+      SG_HIP(hipGetLastError());
+    }
+  } else {
+    SG_TRY(fill64(L.dcnt, sh.ndense + 1, 0, st));
+    SG_TRY(fill64(L.dfill, sh.ndense + 1, 0, st));
+    if (sh.nov_max > 0) {
+      hipLaunchKernelGGL(k_dense_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.prods, L.vbase, nprod, sh.nov_max, L.dbase, L.dcnt);
+      SG_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(sh.ndense, kFillThreads)), dim3(kFillThreads), 0, st,
+                       L.dcnt, sh.ndense, L.dflag);
+    SG_HIP(hipGetLastError());
+    SG_TRY(scan64(L.dflag, sh.ndense, L.vpos, L.part, st));
+    SG_TRY(scan64(L.dcnt, sh.ndense, L.spos, L.part, st));
+    if (sh.ndense > 0) {
+      hipLaunchKernelGGL(k_dense_emit, dim3((unsigned)grid_for(sh.ndense, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.dcnt, L.vpos, L.spos, sh.ndense, L.dbase, ngroup, L.ov_id, L.ov_group, L.ov_seg, L.counters);
+      SG_HIP(hipGetLastError());
+    } else {
+      SG_TRY(fill64(L.ov_seg, 1, 0, st));
+    }
+    if (sh.nov_max > 0) {
+      hipLaunchKernelGGL(k_dense_segs, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.prods, L.vbase, nprod, sh.nov_max, L.dbase, L.spos, L.dfill, L.seg_prod, L.seg_svec);
+      hipLaunchKernelGGL(k_sort_segs, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.ov_seg, L.counters, L.seg_prod, L.seg_svec);
+      SG_HIP(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(k_group_ranges, dim3((unsigned)grid_for(ngroup, 64)), dim3(64), 0, st, L.ov_group, L.counters,
+                     L.groups, ngroup);
+  SG_HIP(hipGetLastError());
+
+  Plan &P = pl->P;
+  P.prods = L.prods;
+  P.groups = L.groups;
+  P.outs = L.outs;
+  P.ov_id = L.ov_id;
+  P.ov_group = L.ov_group;
+  P.ov_seg = L.ov_seg;
+  P.seg_prod = L.seg_prod;
+  P.seg_svec = L.seg_svec;
+  P.ov_flops = L.ov_flops;
+  P.ov_cnt = L.ov_cnt;
+  P.ov_off = L.ov_off;
+  P.counters = L.counters;
+  P.tiny_list = L.tiny;
+  P.mid_list = L.mid;
+  P.heavy_list = L.heavy;
+  P.item_vec = L.item_vec;
+  P.item_win = L.item_win;
+  P.item_cnt = L.item_cnt;
+  P.item_off = L.item_off;
+  P.win = win;
+  P.mid_cap = t.mid_max_ub;
+  P.mid_kind = t.mid_kind;
+  P.lds_words = t.lds_bytes / 4;
+  pl->counters = L.counters;
+  pl->gstat = L.gstat;
+  pl->nzpos = L.nzpos;
+  pl->pbase = L.pbase;
+  pl->outs_dev = L.outs;
+
+  // flops per output vector, then the tiers
+  if (sh.nov_max > 0) {
+    const int64_t waves = std::min<int64_t>(sh.nov_max, (int64_t)pl->ncu * 64);
+    hipLaunchKernelGGL(k_flops, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, L.gstat);
+    SG_HIP(hipGetLastError());
+    BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier};
+    hipLaunchKernelGGL(k_bin, dim3((unsigned)grid_for(sh.nov_max, 256)), dim3(256), 0, st, P, bp, L.counters, L.tiny,
+                       L.mid, L.heavy);
+    SG_HIP(hipGetLastError());
+  }
+  for (int32_t q = 0; q < nprod; ++q) {
+    const int32_t p = order[q];
+    const ProdDev &d = prods[q];
+    if (d.nwin > 1 && sh.wsplit_src[p] < 0 && d.g_nvec > 0) {
+      const int64_t n = d.g_nvec * (int64_t)(d.nwin + 1);
+      hipLaunchKernelGGL(k_wsplit, dim3((unsigned)grid_for(n, kFillThreads)), dim3(kFillThreads), 0, st, d.g_ptr,
+                         d.g_idx, d.g_nvec, d.nwin, win, d.wsplit);
+      SG_HIP(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(k_heavy_nwin, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                     sh.nov_max, L.heavy_nwin);
+  SG_HIP(hipGetLastError());
+  SG_TRY(scan64(L.heavy_nwin, sh.nov_max, L.ibase, L.part, st));
+  hipLaunchKernelGGL(k_heavy_items, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                     L.ibase, sh.nov_max, L.item_vec, L.item_win, L.counters);
+  SG_HIP(hipGetLastError());
+
+  // exact sizes
+  SG_TRY(dispatch<RunCounts>(sr->kind, pl, st));
+  hipLaunchKernelGGL(k_heavy_totals, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                     L.ibase);
+  SG_HIP(hipGetLastError());
+  SG_TRY(scan64(L.ov_cnt, sh.nov_max, L.ov_off, L.part, st));
+  hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                     L.ov_cnt, sh.nov_max, L.nzflag);
+  SG_HIP(hipGetLastError());
+  SG_TRY(scan64(L.nzflag, sh.nov_max, L.nzpos, L.part, st));
+  hipLaunchKernelGGL(k_group_totals, dim3((unsigned)grid_for(ngroup, 64)), dim3(64), 0, st, L.groups, ngroup,
+                     L.ov_off, L.nzpos, L.gstat);
+  SG_HIP(hipGetLastError());
+
+  SG_HIP(hipMemcpyAsync(pl->host_stats, L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount, hipMemcpyDeviceToHost,
+                        st));
+  SG_HIP(hipMemcpyAsync(pl->host_stats + (size_t)ngroup * kStCount, L.counters, sizeof(int64_t) * kCtNum,
+                        hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+
+  const int64_t *cnt = pl->host_stats + (size_t)ngroup * kStCount;
+  for (int32_t g = 0; g < ngroup; ++g) {
+    const int64_t *s = pl->host_stats + (size_t)g * kStCount;
+    sg_sym_info &I = pl->info[g];
+    I.flops = s[kStFlops];
+    I.nnz_ub = s[kStUb];
+    I.nnz = s[kStNnz];
+    I.max_vec_flops = s[kStMaxFlops];
+    I.n_out_vec = s[kStOutVec];
+    I.nvec = doubly(out_fmt) ? s[kStNvec] : sh.major[g];
+    I.n_tiny = cnt[kCtTiny];
+    I.n_mid = cnt[kCtMid];
+    I.n_heavy = cnt[kCtHeavy];
+    I.n_heavy_items = cnt[kCtItems];
+    info[g] = I;
+  }
+  guard.p = nullptr;
+  *plan_out = pl;
+  return SG_OK;
+}
+
+sg_status sg_spgemm_numeric(sg_plan *pl, sg_mat_out *C, void *stream) {
+  if (!pl) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  SG_TRY(emit_outputs(pl, C, st));
+  return dispatch<RunNumeric>(pl->kind, pl, st);
+}
+
+sg_status sg_spgemm_batched(sg_plan *pl, sg_mat_out *C, void *stream) {
+  if (!pl) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  SG_TRY(emit_outputs(pl, C, st));
+  return dispatch<RunBatched>(pl->kind, pl, st);
+}
+
+sg_status sg_plan_destroy(sg_plan *pl) {
+  if (!pl) return SG_ERR_INVALID_ARG;
+  if (pl->outs_host) (void)hipHostFree(pl->outs_host);
+  if (pl->host_stats) (void)hipHostFree(pl->host_stats);
+  delete pl;
+  return SG_OK;
+}
+
+sg_status sg_validate(const sg_mat *M, void *ws, void *stream) {
+  if (!M || !ws) return SG_ERR_INVALID_ARG;
+  const int32_t kind = M->val ? SG_PLUS_TIMES_F64 : SG_OR_AND_BOOL;
+  SG_TRY(check_mat(*M, kind));
+  hipStream_t st = (hipStream_t)stream;
+  int64_t *bad = (int64_t *)ws;
+  SG_TRY(fill64(bad, 1, 0, st));
+  if (M->nvec > 0) {
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)grid_for(M->nvec, kFillThreads)), dim3(kFillThreads), 0, st, M->ptr,
+                       M->vid, M->idx, M->nvec, M->nnz, major_of(*M), minor_of(*M), (int32_t)doubly(M->fmt), bad);
+    SG_HIP(hipGetLastError());
+  }
+  int64_t h = 0;
+  SG_HIP(hipMemcpyAsync(&h, bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  return h == 0 ? SG_OK : SG_ERR_NOT_CANONICAL;
+}
+
+sg_status sg_build_aux(const sg_mat *M, int32_t *aux, int64_t *nchunks_out, void *stream) {
+  if (!M || !aux || !nchunks_out || !doubly(M->fmt)) return SG_ERR_INVALID_ARG;
+  const int64_t maj = major_of(*M);
+  int64_t chunk = M->nvec > 0 ? (maj + M->nvec - 1) / M->nvec : (maj > 0 ? maj : 1);
+  if (chunk < 1) chunk = 1;
+  const int64_t nchunks = (maj + chunk - 1) / chunk;
+  *nchunks_out = nchunks;
+  hipLaunchKernelGGL(k_build_aux, dim3((unsigned)grid_for(nchunks + 1, kFillThreads)), dim3(kFillThreads), 0,
+                     (hipStream_t)stream, M->vid, M->nvec, chunk, nchunks, aux);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,450 @@
+// Symbolic-phase kernels: output vector lists, AUX lookup, flops per output
+// vector, tier binning, window split points and device-wide scans.
+#pragma once
+
+#include "sg_device.h"
+
+namespace sg {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---- exclusive scan of int64 (out[n] = total), three passes -----------------
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int64_t *in, int64_t n, int64_t *part) {
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t x = base + (int64_t)threadIdx.x * kScanItems + i;
+    if (x < n) s += in[x];
+  }
+  int64_t tot = block_sum(s, scratch);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_partials(int64_t *part, int64_t nb) {
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+    int64_t x = b0 + threadIdx.x;
+    int64_t v = x < nb ? part[x] : 0;
+    int64_t tot;
+    int64_t ex = block_excl_scan(v, scratch, &tot);
+    if (x < nb) part[x] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[nb] = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(const int64_t *in, int64_t n, const int64_t *part,
+                                                           int64_t nb, int64_t *out) {
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan(s, scratch, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = part[nb];
+}
+
+// ---- AUX index of a doubly compressed matrix (Section 2.3) -----------------
+__global__ void k_build_aux(const int32_t *vid, int64_t nvec, int64_t chunk, int64_t nchunks, int32_t *aux) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c > nchunks) return;
+  if (c == nchunks) {
+    aux[c] = (int32_t)nvec;
+    return;
+  }
+  int64_t key = c * chunk;
+  int64_t lo = 0, hi = nvec;
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (vid[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  aux[c] = (int32_t)lo;
+}
+
+// ---- output vectors when every group holds a single product ---------------
+// Output vector v is stored vector t of product p's S, v = vbase[p] + t.
+__global__ void k_ov_simple(const ProdDev *prods, const int64_t *vbase, int32_t nprod, int64_t nov,
+                            int32_t *ov_id, int32_t *ov_group, int64_t *ov_seg, int32_t *seg_prod,
+                            int32_t *seg_svec) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nov; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nprod - 1;
+    while (lo < hi) {  // last p with vbase[p] <= v
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (vbase[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    const ProdDev &d = prods[lo];
+    int64_t t = v - vbase[lo];
+    ov_id[v] = d.s_vid ? d.s_vid[t] : (int32_t)t;
+    ov_group[v] = d.group;
+    ov_seg[v] = v;
+    seg_prod[v] = lo;
+    seg_svec[v] = (int32_t)t;
+    if (v == nov - 1) ov_seg[nov] = nov;
+  }
+}
+
+// ---- output vectors of groups with several products (stage merge) ---------
+// A dense count per output major id of each group (dbase[g] + j), then two
+// scans give the output vector numbering and the segment offsets.
+__global__ void k_dense_count(const ProdDev *prods, const int64_t *vbase, int32_t nprod, int64_t nvec_all,
+                              const int64_t *dbase, int64_t *dcnt) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nvec_all; x += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nprod - 1;
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (vbase[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    const ProdDev &d = prods[lo];
+    int64_t t = x - vbase[lo];
+    int64_t j = d.s_vid ? d.s_vid[t] : t;
+    if (d.s_ptr[t + 1] > d.s_ptr[t])
+      atomicAdd((unsigned long long *)&dcnt[dbase[d.group] + j], 1ull);
+  }
+}
+
+__global__ void k_nonzero_flag(const int64_t *in, int64_t n, int64_t *out) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    out[x] = in[x] > 0 ? 1 : 0;
+}
+
+__global__ void k_dense_emit(const int64_t *dcnt, const int64_t *vpos, const int64_t *spos, int64_t ndense,
+                             const int64_t *dbase, int32_t ngroup, int32_t *ov_id, int32_t *ov_group,
+                             int64_t *ov_seg, int64_t *counters) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < ndense; x += (int64_t)gridDim.x * blockDim.x) {
+    if (x == ndense - 1) {
+      counters[kCtNov] = vpos[ndense];
+      counters[kCtNseg] = spos[ndense];
+      ov_seg[vpos[ndense]] = spos[ndense];
+    }
+    if (dcnt[x] == 0) continue;
+    int32_t lo = 0, hi = ngroup - 1;
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (dbase[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    int64_t v = vpos[x];
+    ov_id[v] = (int32_t)(x - dbase[lo]);
+    ov_group[v] = lo;
+    ov_seg[v] = spos[x];
+  }
+}
+
+__global__ void k_dense_segs(const ProdDev *prods, const int64_t *vbase, int32_t nprod, int64_t nvec_all,
+                             const int64_t *dbase, const int64_t *spos, int64_t *dfill, int32_t *seg_prod,
+                             int32_t *seg_svec) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nvec_all; x += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nprod - 1;
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (vbase[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    const ProdDev &d = prods[lo];
+    int64_t t = x - vbase[lo];
+    if (d.s_ptr[t + 1] == d.s_ptr[t]) continue;
+    int64_t j = d.s_vid ? d.s_vid[t] : t;
+    int64_t dx = dbase[d.group] + j;
+    int64_t slot = spos[dx] + (int64_t)atomicAdd((unsigned long long *)&dfill[dx], 1ull);
+    seg_prod[slot] = lo;
+    seg_svec[slot] = (int32_t)t;
+  }
+}
+
+// Order the segments of each output vector by product (deterministic order).
+__global__ void k_sort_segs(const int64_t *ov_seg, const int64_t *counters, int32_t *seg_prod, int32_t *seg_svec) {
+  int64_t nov = counters[kCtNov];
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nov; v += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = ov_seg[v], b = ov_seg[v + 1];
+    for (int64_t i = a + 1; i < b; ++i) {
+      int32_t p = seg_prod[i], t = seg_svec[i];
+      int64_t j = i - 1;
+      while (j >= a && seg_prod[j] > p) {
+        seg_prod[j + 1] = seg_prod[j];
+        seg_svec[j + 1] = seg_svec[j];
+        --j;
+      }
+      seg_prod[j + 1] = p;
+      seg_svec[j + 1] = t;
+    }
+  }
+}
+
+// Group ranges of output vectors (ov ids are ordered by group).
+__global__ void k_group_ranges(const int32_t *ov_group, const int64_t *counters, GroupDev *groups, int32_t ngroup) {
+  int64_t nov = counters[kCtNov];
+  int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroup) return;
+  int64_t lo = 0, hi = nov;  // first v with ov_group[v] >= g
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (ov_group[mid] < g) lo = mid + 1; else hi = mid;
+  }
+  int64_t b = lo;
+  hi = nov;
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (ov_group[mid] <= g) lo = mid + 1; else hi = mid;
+  }
+  groups[g].ov_begin = b;
+  groups[g].ov_end = lo;
+}
+
+// ---- flops per output vector (one wavefront per vector) --------------------
+// flops_j = sum over stored (k, s) of S(:, j) of nnz(G(:, k)); a k with an
+// empty G vector contributes nothing (the Isect observation, Section 2.4).
+// For a doubly compressed G the resolved vector is kept per S entry.
+__global__ void k_flops(Plan P, int64_t *gstat) {
+  const int l = lane();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t nov = P.counters[kCtNov];
+  int32_t cur_g = -1;
+  int64_t acc_f = 0, acc_ub = 0, acc_max = 0;
+  for (int64_t v = wave; v < nov; v += nwaves) {
+    int64_t f = 0;
+    for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
+      const ProdDev &d = P.prods[P.seg_prod[s]];
+      int32_t t = P.seg_svec[s];
+      int64_t e0 = d.s_ptr[t], e1 = d.s_ptr[t + 1];
+      for (int64_t e = e0 + l; e < e1; e += kWave) {
+        int32_t k = d.s_idx[e];
+        int32_t gt;
+        if (d.g_vid) {
+          gt = aux_find(d, k);
+          d.gres[e] = gt;
+        } else {
+          gt = (k >= 0 && k < d.g_nvec) ? k : -1;
+        }
+        if (gt >= 0) f += d.g_ptr[gt + 1] - d.g_ptr[gt];
+      }
+    }
+    f = wave_sum64(f);
+    int32_t g = P.ov_group[v];
+    if (l == 0) P.ov_flops[v] = f;
+    if (g != cur_g) {
+      if (cur_g >= 0 && l == 0) {
+        atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)acc_f);
+        atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStUb], (unsigned long long)acc_ub);
+        atomicMax((unsigned long long *)&gstat[cur_g * kStCount + kStMaxFlops], (unsigned long long)acc_max);
+      }
+      cur_g = g;
+      acc_f = acc_ub = acc_max = 0;
+    }
+    int64_t minor = P.groups[g].minor;
+    acc_f += f;
+    acc_ub += f < minor ? f : minor;
+    acc_max = f > acc_max ? f : acc_max;
+  }
+  if (cur_g >= 0 && l == 0) {
+    atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)acc_f);
+    atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStUb], (unsigned long long)acc_ub);
+    atomicMax((unsigned long long *)&gstat[cur_g * kStCount + kStMaxFlops], (unsigned long long)acc_max);
+  }
+}
+
+// ---- tier binning -----------------------------------------------------------
+// Wave-aggregated append of this lane's vector to list `which` if `take`.
+__device__ __forceinline__ void append(bool take, int32_t v, int32_t *list, int64_t *counter) {
+  uint64_t m = __ballot(take);
+  if (m == 0) return;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  int64_t base = 0;
+  if (lane() == leader) base = (int64_t)atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, kWave);
+  uint64_t below = m & ((1ull << lane()) - 1ull);
+  if (take) list[base + __popcll(below)] = v;
+}
+
+struct BinParams {
+  int32_t tiny_max;
+  int32_t mid_cap;
+  int32_t force;
+};
+
+__global__ void k_bin(Plan P, BinParams bp, int64_t *counters, int32_t *tiny, int32_t *mid, int32_t *heavy) {
+  const int64_t nov = counters[kCtNov];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // loop bound is uniform per wave so the ballots see the whole wave
+  for (int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & ~(int64_t)(kWave - 1); v0 < nov; v0 += stride) {
+    int64_t v = v0 + lane();
+    int tier = -1;
+    if (v < nov) {
+      int64_t f = P.ov_flops[v];
+      const GroupDev &g = P.groups[P.ov_group[v]];
+      int64_t ub = f < g.minor ? f : g.minor;
+      bool tiny_ok = f <= bp.tiny_max;
+      bool mid_fit = g.mid_ok > 0 && ub <= (int64_t)g.mid_ok && ub <= (int64_t)bp.mid_cap;
+      // with a single window the heavy tier's dense accumulator covers the
+      // whole id range, which beats the mid tier unless it is forced
+      bool mid_ok = mid_fit && g.nwin > 1;
+      if (f == 0) tier = -1;
+      else if (bp.force == 2) tier = 2;
+      else if (bp.force == 1) tier = mid_fit ? 1 : 2;
+      else if (tiny_ok) tier = 0;
+      else if (mid_ok) tier = 1;
+      else tier = 2;
+    }
+    append(tier == 0, (int32_t)v, tiny, &counters[kCtTiny]);
+    append(tier == 1, (int32_t)v, mid, &counters[kCtMid]);
+    append(tier == 2, (int32_t)v, heavy, &counters[kCtHeavy]);
+  }
+}
+
+// Number of windows of each heavy vector (0 past the end), for the item scan.
+__global__ void k_heavy_nwin(Plan P, int64_t cap, int64_t *out) {
+  int64_t nh = P.counters[kCtHeavy];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x)
+    out[q] = q < nh ? P.groups[P.ov_group[P.heavy_list[q]]].nwin : 0;
+}
+
+__global__ void k_heavy_items(Plan P, const int64_t *ibase, int64_t cap, int32_t *item_vec, int32_t *item_win,
+                              int64_t *counters) {
+  int64_t nh = counters[kCtHeavy];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t b = ibase[q], e = ibase[q + 1];
+    for (int64_t i = b; i < e; ++i) {
+      item_vec[i] = (int32_t)q;
+      item_win[i] = (int32_t)(i - b);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCtItems] = ibase[cap];
+}
+
+// Window split points of every G vector: wsplit[t * (nwin + 1) + c] is the
+// offset inside G(:, t) of the first id >= c * win.
+__global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_nvec, int32_t nwin, int32_t win,
+                         int32_t *wsplit) {
+  int64_t n = g_nvec * (nwin + 1);
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t t = x / (nwin + 1);
+    int64_t c = x - t * (nwin + 1);
+    int64_t a = g_ptr[t], b = g_ptr[t + 1];
+    int64_t lo = a, hi = b;
+    int64_t key = c * (int64_t)win;
+    while (lo < hi) {
+      int64_t mid = lo + ((hi - lo) >> 1);
+      if (g_idx[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    wsplit[x] = (int32_t)(lo - a);
+  }
+}
+
+// Heavy vector totals from their window counts; item_off becomes the offset
+// of each window inside its vector's output.
+__global__ void k_heavy_totals(Plan P, const int64_t *ibase) {
+  int64_t nh = P.counters[kCtHeavy];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t run = 0;
+    for (int64_t i = ibase[q]; i < ibase[q + 1]; ++i) {
+      P.item_off[i] = run;
+      run += P.item_cnt[i];
+    }
+    P.ov_cnt[P.heavy_list[q]] = run;
+  }
+}
+
+// Per-group totals after the scans of counts (ov_off) and non-empty flags (nzpos).
+__global__ void k_group_totals(GroupDev *groups, int32_t ngroup, const int64_t *ov_off, const int64_t *nzpos,
+                               int64_t *gstat) {
+  int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroup) return;
+  GroupDev &G = groups[g];
+  G.nnz_base = ov_off[G.ov_begin];
+  G.nz_base = nzpos[G.ov_begin];
+  gstat[g * kStCount + kStNnz] = ov_off[G.ov_end] - G.nnz_base;
+  gstat[g * kStCount + kStNvec] = nzpos[G.ov_end] - G.nz_base;
+  gstat[g * kStCount + kStOutVec] = G.ov_end - G.ov_begin;
+}
+
+// ---- output pointers --------------------------------------------------------
+// CSR/CSC output: ptr[j] for every major id j of every group (dense range
+// dbase[g] .. dbase[g] + major_g inclusive).
+__global__ void k_emit_ptr_dense(Plan P, const int64_t *pbase, int32_t ngroup, int64_t ntot) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < ntot; x += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = ngroup - 1;
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (pbase[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    const GroupDev &G = P.groups[lo];
+    const OutDev &O = P.outs[lo];
+    int64_t j = x - pbase[lo];
+    int64_t a = G.ov_begin, b = G.ov_end;  // first v with ov_id >= j
+    while (a < b) {
+      int64_t mid = a + ((b - a) >> 1);
+      if (P.ov_id[mid] < j) a = mid + 1; else b = mid;
+    }
+    O.ptr[j] = P.ov_off[a] - G.nnz_base;
+  }
+}
+
+// Doubly compressed output: JC/CP of the non-empty vectors.
+__global__ void k_emit_ptr_doubly(Plan P, const int64_t *nzpos, int32_t ngroup) {
+  const int64_t nov = P.counters[kCtNov];
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= nov; v += (int64_t)gridDim.x * blockDim.x) {
+    if (v == nov) {
+      for (int32_t g = 0; g < ngroup; ++g) {
+        const GroupDev &G = P.groups[g];
+        P.outs[g].ptr[nzpos[G.ov_end] - G.nz_base] = P.ov_off[G.ov_end] - G.nnz_base;
+      }
+      continue;
+    }
+    if (P.ov_cnt[v] == 0) continue;
+    int32_t g = P.ov_group[v];
+    const GroupDev &G = P.groups[g];
+    int64_t pos = nzpos[v] - G.nz_base;
+    P.outs[g].vid[pos] = P.ov_id[v];
+    P.outs[g].ptr[pos] = P.ov_off[v] - G.nnz_base;
+  }
+}
+
+// ---- operand validation -----------------------------------------------------
+__global__ void k_validate(const int64_t *ptr, const int32_t *vid, const int32_t *idx, int64_t nvec, int64_t nnz,
+                           int64_t major, int64_t minor, int32_t doubly, int64_t *bad) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nvec; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = ptr[t], b = ptr[t + 1];
+    bool ok = a >= 0 && b >= a && b <= nnz;
+    if (t == 0) ok = ok && a == 0;
+    if (t == nvec - 1) ok = ok && b == nnz;
+    if (doubly) {
+      ok = ok && b > a && vid[t] >= 0 && vid[t] < major;
+      if (t > 0) ok = ok && vid[t - 1] < vid[t];
+    }
+    if (ok) {
+      for (int64_t e = a; e < b; ++e) {
+        int32_t i = idx[e];
+        if (i < 0 || i >= minor || (e > a && idx[e - 1] >= i)) {
+          ok = false;
+          break;
+        }
+      }
+    }
+    if (!ok) atomicAdd((unsigned long long *)bad, 1ull);
+  }
+}
+
+}  // namespace sg

@@ -1,0 +1,522 @@
+// Numeric tiers of the flops-binned local product, each in a count variant
+// (exact size of an output vector or window) and a numeric variant (writes
+// the sorted ids and accumulated values):
+//
+//   tiny   one wavefront per output vector with at most 64 multiplications:
+//          the products are placed one per lane, sorted by id with a
+//          register bitonic network, and equal ids are merged by a
+//          segmented reduction (the multiway merge of Section 2.4, done on
+//          64 lanes instead of a heap);
+//   mid    one workgroup per vector whose size bound fits in LDS:
+//          bitmap-rank accumulator (a bit per output id marks the pattern,
+//          a prefix count per 32-bit word turns an id into its rank, so the
+//          values are accumulated densely and emitted already sorted), or
+//          an open-addressing LDS hash followed by an in-LDS bitonic sort;
+//   heavy  one workgroup per (vector, window): the output id range is cut
+//          into windows of `win` ids, and each window is accumulated in a
+//          dense LDS sparse accumulator (the SPA of Section 3.3, a flag bit
+//          and a value per id); the gathered operand is read in place
+//          through per-vector window split points.
+//
+// Every workgroup keeps its dynamic LDS at all-zero bits between items; the
+// semiring traits encode the additive identity as zero bits.
+#pragma once
+
+#include "sg_device.h"
+
+namespace sg {
+
+// ---------------------------------------------------------------------------
+// Products of one batch of (up to) 64 stored entries of S, one per lane: the
+// lane holds `len` products in G positions [gb, gb + len) with S value sv.
+// act(id, value) is called once per product. Long G vectors are walked one
+// owner at a time with all lanes striding the vector (coalesced, no lane
+// search); short ones are flattened so that every lane gets a product.
+template <class SR, class Act>
+__device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
+                                          const typename SR::T *__restrict__ gval, Act &act) {
+  typedef typename SR::T T;
+  const int l = lane();
+  const int P = wave_incl_scan(len);
+  const int tot = read_lane(P, kWave - 1);
+  if (tot == 0) return;
+  const int steps_owner = wave_sum((len + kWave - 1) / kWave);
+  const int steps_flat = (tot + kWave - 1) / kWave;
+  if (steps_owner <= 2 * steps_flat) {
+    uint64_t m = __ballot(len > 0);
+    while (m) {
+      const int o = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int L = read_lane(len, o);
+      const int64_t b = read_lane64(gb, o);
+      const T s = read_lane_val(sv, o);
+      for (int f = l; f < L; f += kWave) {
+        const int64_t g = b + f;
+        if (SR::kVal) act(gidx[g], SR::mul(s, gval[g]));
+        else act(gidx[g], T());
+      }
+    }
+  } else {
+    const int64_t start = gb - (int64_t)(P - len);
+    for (int base = 0; base < tot; base += kWave) {
+      const int f = base + l;
+      const int o = owner_of(P, f < tot ? f : tot - 1);
+      const int64_t st = __shfl(start, o, kWave);
+      const T s = __shfl(sv, o, kWave);
+      if (f < tot) {
+        const int64_t g = st + f;
+        if (SR::kVal) act(gidx[g], SR::mul(s, gval[g]));
+        else act(gidx[g], T());
+      }
+    }
+  }
+}
+
+// Load the lane's stored S entry e of product d and describe its products:
+// the whole G vector (win_c < 0) or only the part inside window win_c.
+template <class SR>
+__device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t e1, int win_c, int &len, int64_t &gb,
+                                           typename SR::T &sv) {
+  typedef typename SR::T T;
+  len = 0;
+  gb = 0;
+  sv = T();
+  if (e >= e1) return;
+  const int32_t k = d.s_idx[e];
+  const int32_t gt = d.gres ? d.gres[e] : ((k >= 0 && k < d.g_nvec) ? k : -1);
+  if (gt < 0) return;
+  const int64_t p0 = d.g_ptr[gt];
+  if (win_c >= 0 && d.wsplit) {
+    const int32_t *ws = d.wsplit + (int64_t)gt * (d.nwin + 1) + win_c;
+    gb = p0 + ws[0];
+    len = ws[1] - ws[0];
+  } else {
+    gb = p0;
+    len = (int)(d.g_ptr[gt + 1] - p0);
+  }
+  if (SR::kVal) sv = ((const T *)d.s_val)[e];
+}
+
+// All products of output vector v (restricted to window win_c if >= 0),
+// shared among the nw wavefronts of the caller (wave wid takes every nw-th
+// batch of 64 S entries, counted across the vector's segments).
+template <class SR, class Act>
+__device__ __forceinline__ void for_products(const Plan &P, int64_t v, int win_c, int wid, int nw, Act &act) {
+  typedef typename SR::T T;
+  const int64_t s0 = P.ov_seg[v], s1 = P.ov_seg[v + 1];
+  int64_t gbatch = 0;
+  for (int64_t s = s0; s < s1; ++s) {
+    const ProdDev &d = P.prods[P.seg_prod[s]];
+    const int32_t t = P.seg_svec[s];
+    const int64_t e0 = d.s_ptr[t], e1 = d.s_ptr[t + 1];
+    const int64_t nb = (e1 - e0 + kWave - 1) / kWave;
+    int64_t b = (int64_t)(((wid - gbatch) % nw + nw) % nw);
+    for (; b < nb; b += nw) {
+      int len;
+      int64_t gb;
+      T sv;
+      load_entry<SR>(d, e0 + b * kWave + lane(), e1, win_c, len, gb, sv);
+      run_batch<SR>(len, gb, sv, d.g_idx, (const T *)d.g_val, act);
+    }
+    gbatch += nb;
+  }
+}
+
+__device__ __forceinline__ int64_t out_offset(const Plan &P, int64_t v) {
+  return P.ov_off[v] - P.groups[P.ov_group[v]].nnz_base;
+}
+
+// ---------------------------------------------------------------------------
+// Tiny tier: one wavefront, at most 64 products.
+template <int K, bool COUNT>
+__device__ void tiny_vector(const Plan &P, int64_t v) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  const int l = lane();
+  int key = INT32_MAX;
+  T val = T();
+  int filled = 0;
+  const int64_t s0 = P.ov_seg[v], s1 = P.ov_seg[v + 1];
+  for (int64_t s = s0; s < s1; ++s) {
+    const ProdDev &d = P.prods[P.seg_prod[s]];
+    const int32_t t = P.seg_svec[s];
+    const int64_t e1 = d.s_ptr[t + 1];
+    for (int64_t eb = d.s_ptr[t]; eb < e1; eb += kWave) {
+      int len;
+      int64_t gb;
+      T sv;
+      load_entry<SR>(d, eb + l, e1, -1, len, gb, sv);
+      const int Pp = wave_incl_scan(len);
+      const int tot = read_lane(Pp, kWave - 1);
+      if (tot == 0) continue;
+      const int f = l - filled;
+      const bool mine = f >= 0 && f < tot;
+      const int o = owner_of(Pp, mine ? f : 0);
+      const int64_t start = gb - (int64_t)(Pp - len);
+      const int64_t st = __shfl(start, o, kWave);
+      const T so = __shfl(sv, o, kWave);
+      if (mine) {
+        const int64_t g = st + f;
+        key = d.g_idx[g];
+        if (SR::kVal) val = SR::mul(so, ((const T *)d.g_val)[g]);
+      }
+      filled += tot;
+    }
+  }
+  // bitonic sort of (key, val) across the 64 lanes, ascending key
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int pk = __shfl_xor(key, j, kWave);
+      const T pv = __shfl_xor(val, j, kWave);
+      const bool up = (l & k) == 0;
+      const bool low = (l & j) == 0;
+      const bool take = low ? (up ? pk < key : pk > key) : (up ? pk > key : pk < key);
+      if (take) {
+        key = pk;
+        val = pv;
+      }
+    }
+  }
+  // segmented (+) of equal ids: the head lane of each run ends with its total
+  if (SR::kVal) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int kd = __shfl_down(key, d, kWave);
+      const T vd = __shfl_down(val, d, kWave);
+      if (l + d < kWave && kd == key) val = SR::add(val, vd);
+    }
+  }
+  const int prev = __shfl_up(key, 1, kWave);
+  const bool head = key != INT32_MAX && (l == 0 || prev != key);
+  const uint64_t hm = __ballot(head);
+  if (COUNT) {
+    if (l == 0) P.ov_cnt[v] = __popcll(hm);
+    return;
+  }
+  if (head) {
+    const int r = __popcll(hm & ((1ull << l) - 1ull));
+    const OutDev &O = P.outs[P.ov_group[v]];
+    const int64_t pos = out_offset(P, v) + r;
+    O.idx[pos] = key;
+    if (SR::kVal) ((T *)O.val)[pos] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout helpers (offsets in 32-bit words).
+__device__ __forceinline__ int64_t align2(int64_t w) { return (w + 1) & ~(int64_t)1; }
+
+// Mid tier, bitmap-rank accumulator over the whole output id range.
+template <int K, bool COUNT>
+__device__ void mid_bitmap_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  typedef typename SR::Slot Slot;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wid = tid / kWave, nw = nt / kWave;
+  const int64_t minor = P.groups[P.ov_group[v]].minor;
+  const int nw32 = (int)((minor + 31) >> 5);
+  uint32_t *bits = lds;
+  uint16_t *pre = (uint16_t *)(lds + nw32);
+  Slot *vals = (Slot *)(lds + align2(nw32 + ((nw32 + 1) >> 1)));
+
+  auto mark = [&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); };
+  for_products<SR>(P, v, -1, wid, nw, mark);
+  __syncthreads();
+
+  // per-thread contiguous word range
+  const int per = (nw32 + nt - 1) / nt;
+  const int w0 = tid * per < nw32 ? tid * per : nw32;
+  const int w1 = w0 + per < nw32 ? w0 + per : nw32;
+  int local = 0;
+  for (int w = w0; w < w1; ++w) local += __popc(bits[w]);
+  int64_t total;
+  const int64_t excl = block_excl_scan(local, scratch, &total);
+  if (COUNT) {
+    for (int w = w0; w < w1; ++w) bits[w] = 0;
+    if (tid == 0) P.ov_cnt[v] = total;
+    __syncthreads();
+    return;
+  }
+  const OutDev &O = P.outs[P.ov_group[v]];
+  const int64_t base = out_offset(P, v);
+  if (!SR::kVal) {
+    int64_t r = base + excl;
+    for (int w = w0; w < w1; ++w) {
+      uint32_t b = bits[w];
+      while (b) {
+        const int bit = __ffs(b) - 1;
+        b &= b - 1;
+        O.idx[r++] = (w << 5) + bit;
+      }
+      bits[w] = 0;
+    }
+    __syncthreads();
+    return;
+  }
+  {
+    int run = (int)excl;
+    for (int w = w0; w < w1; ++w) {
+      pre[w] = (uint16_t)run;
+      run += __popc(bits[w]);
+    }
+  }
+  __syncthreads();
+  auto accum = [&](int id, T x) {
+    const int w = id >> 5;
+    const int r = pre[w] + __popc(bits[w] & ((1u << (id & 31)) - 1u));
+    SR::acc(&vals[r], x);
+  };
+  for_products<SR>(P, v, -1, wid, nw, accum);
+  __syncthreads();
+  // emit: lane-interleaved words, so a wavefront writes one contiguous run
+  for (int w = tid; w < nw32; w += nt) {
+    uint32_t b = bits[w];
+    if (b) {
+      int r = pre[w];
+      while (b) {
+        const int bit = __ffs(b) - 1;
+        b &= b - 1;
+        O.idx[base + r] = (w << 5) + bit;
+        ((T *)O.val)[base + r] = SR::dec(vals[r]);
+        vals[r] = Slot();
+        ++r;
+      }
+      bits[w] = 0;
+    }
+    pre[w] = 0;
+  }
+  __syncthreads();
+}
+
+// Mid tier, open-addressing hash in LDS (ids stored as id + 1, 0 = empty),
+// then a bitonic sort of the whole table by id.
+__device__ __forceinline__ uint32_t hash_id(uint32_t id, int logts) { return (id * 0x9E3779B1u) >> (32 - logts); }
+
+template <int K, bool COUNT>
+__device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  typedef typename SR::Slot Slot;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wid = tid / kWave, nw = nt / kWave;
+  const int64_t f = P.ov_flops[v];
+  const int64_t minor = P.groups[P.ov_group[v]].minor;
+  const int64_t ub = f < minor ? f : minor;
+  int logts = 6;
+  while ((1ll << logts) < 2 * ub) ++logts;
+  const int ts = 1 << logts;
+  const int mask = ts - 1;
+  uint32_t *keys = lds;
+  Slot *vals = (Slot *)(lds + ts);
+
+  auto ins = [&](int id, T x) {
+    const uint32_t kk = (uint32_t)id + 1u;
+    int h = (int)hash_id((uint32_t)id, logts);
+    while (true) {
+      uint32_t cur = keys[h];
+      if (cur == 0) cur = atomicCAS(&keys[h], 0u, kk);
+      if (cur == 0 || cur == kk) break;
+      h = (h + 1) & mask;
+    }
+    if (!COUNT) SR::acc(&vals[h], x);
+  };
+  for_products<SR>(P, v, -1, wid, nw, ins);
+  __syncthreads();
+  if (COUNT) {
+    int64_t local = 0;
+    for (int i = tid; i < ts; i += nt) {
+      local += keys[i] != 0;
+      keys[i] = 0;
+    }
+    const int64_t total = block_sum(local, scratch);
+    if (tid == 0) P.ov_cnt[v] = total;
+    __syncthreads();
+    return;
+  }
+  // empty slots sort last
+  for (int i = tid; i < ts; i += nt)
+    if (keys[i] == 0) keys[i] = 0xFFFFFFFFu;
+  __syncthreads();
+  for (int k = 2; k <= ts; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < (ts >> 1); i += nt) {
+        const int lo = ((i / j) * 2 * j) + (i % j);
+        const int hi = lo + j;
+        const bool up = (lo & k) == 0;
+        const uint32_t a = keys[lo], b = keys[hi];
+        if ((a > b) == up) {
+          keys[lo] = b;
+          keys[hi] = a;
+          if (SR::kVal) {
+            const Slot t = vals[lo];
+            vals[lo] = vals[hi];
+            vals[hi] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const OutDev &O = P.outs[P.ov_group[v]];
+  const int64_t base = out_offset(P, v);
+  const int64_t cnt = P.ov_cnt[v];
+  for (int i = tid; i < ts; i += nt) {
+    if (i < cnt) {
+      O.idx[base + i] = (int32_t)(keys[i] - 1u);
+      if (SR::kVal) ((T *)O.val)[base + i] = SR::dec(vals[i]);
+    }
+    keys[i] = 0;
+    vals[i] = Slot();
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Heavy tier: dense LDS accumulator over one window of `win` output ids.
+template <int K, bool COUNT>
+__device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  typedef typename SR::Slot Slot;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wid = tid / kWave, nw = nt / kWave;
+  const int32_t q = P.item_vec[it];
+  const int32_t c = P.item_win[it];
+  const int64_t v = P.heavy_list[q];
+  const int64_t minor = P.groups[P.ov_group[v]].minor;
+  const int64_t lo = (int64_t)c * P.win;
+  const int width = (int)((minor - lo) < P.win ? (minor - lo) : P.win);
+  const int nwf = (width + 31) >> 5;
+  const int wcap = (P.win + 31) >> 5;
+  uint32_t *flags = lds;
+  Slot *vals = (Slot *)(lds + align2(wcap));
+  const int lo32 = (int)lo;
+
+  auto acc = [&](int id, T x) {
+    const int r = id - lo32;
+    atomicOr(&flags[r >> 5], 1u << (r & 31));
+    if (!COUNT) SR::acc(&vals[r], x);
+  };
+  for_products<SR>(P, v, c, wid, nw, acc);
+  __syncthreads();
+
+  const int per = (nwf + nt - 1) / nt;
+  const int w0 = tid * per < nwf ? tid * per : nwf;
+  const int w1 = w0 + per < nwf ? w0 + per : nwf;
+  int local = 0;
+  for (int w = w0; w < w1; ++w) local += __popc(flags[w]);
+  int64_t total;
+  const int64_t excl = block_excl_scan(local, scratch, &total);
+  if (COUNT) {
+    for (int w = w0; w < w1; ++w) flags[w] = 0;
+    if (tid == 0) P.item_cnt[it] = (int32_t)total;
+    __syncthreads();
+    return;
+  }
+  const OutDev &O = P.outs[P.ov_group[v]];
+  int64_t r = out_offset(P, v) + P.item_off[it] + excl;
+  for (int w = w0; w < w1; ++w) {
+    uint32_t b = flags[w];
+    while (b) {
+      const int bit = __ffs(b) - 1;
+      b &= b - 1;
+      const int x = (w << 5) + bit;
+      O.idx[r] = lo32 + x;
+      if (SR::kVal) {
+        ((T *)O.val)[r] = SR::dec(vals[x]);
+        vals[x] = Slot();
+      }
+      ++r;
+    }
+    flags[w] = 0;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels. Mid and heavy kernels pull work from a device queue counter;
+// every workgroup exits once the counter passes the item count, which is
+// fixed before the launch, so every wave reaches the exit.
+__device__ __forceinline__ void zero_lds(uint32_t *lds, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0;
+  __syncthreads();
+}
+
+template <int K, bool COUNT>
+__global__ void __launch_bounds__(1024) k_tiny(Plan P) {
+  const int64_t n = P.counters[kCtTiny];
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t i = wave; i < n; i += nwaves) tiny_vector<K, COUNT>(P, P.tiny_list[i]);
+}
+
+template <int K, bool COUNT>
+__global__ void __launch_bounds__(1024) k_mid(Plan P, int64_t *queue) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  __shared__ int64_t s_item;
+  zero_lds(lds, P.lds_words);
+  const int64_t n = P.counters[kCtMid];
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
+    __syncthreads();
+    const int64_t i = s_item;
+    __syncthreads();
+    if (i >= n) break;
+    if (P.mid_kind == 0) mid_bitmap_vector<K, COUNT>(P, P.mid_list[i], lds, scratch);
+    else mid_hash_vector<K, COUNT>(P, P.mid_list[i], lds, scratch);
+  }
+}
+
+template <int K, bool COUNT>
+__global__ void __launch_bounds__(1024) k_heavy(Plan P, int64_t *queue) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  __shared__ int64_t s_item;
+  zero_lds(lds, P.lds_words);
+  const int64_t n = P.counters[kCtItems];
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
+    __syncthreads();
+    const int64_t i = s_item;
+    __syncthreads();
+    if (i >= n) break;
+    heavy_item<K, COUNT>(P, i, lds, scratch);
+  }
+}
+
+// One persistent launch for every tier: queue items are heavy windows
+// first, then mid vectors, then groups of tiny vectors (one per wavefront).
+template <int K>
+__global__ void __launch_bounds__(1024) k_batched(Plan P, int64_t *queue, int64_t n_items, int64_t n_mid,
+                                                  int64_t n_tiny) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  __shared__ int64_t s_item;
+  zero_lds(lds, P.lds_words);
+  const int nw = blockDim.x / kWave;
+  const int64_t n_tiny_groups = (n_tiny + nw - 1) / nw;
+  const int64_t total = n_items + n_mid + n_tiny_groups;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
+    __syncthreads();
+    const int64_t i = s_item;
+    __syncthreads();
+    if (i >= total) break;
+    if (i < n_items) {
+      heavy_item<K, false>(P, i, lds, scratch);
+    } else if (i < n_items + n_mid) {
+      const int64_t v = P.mid_list[i - n_items];
+      if (P.mid_kind == 0) mid_bitmap_vector<K, false>(P, v, lds, scratch);
+      else mid_hash_vector<K, false>(P, v, lds, scratch);
+    } else {
+      const int64_t t = (i - n_items - n_mid) * nw + threadIdx.x / kWave;
+      if (t < n_tiny) tiny_vector<K, false>(P, P.tiny_list[t]);
+    }
+  }
+}
+
+}  // namespace sg

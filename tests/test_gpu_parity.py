@@ -1,0 +1,265 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Integer and boolean results must match bit for bit, patterns always; FP64
+(+,*) values within 1e-12 relative per entry; FP32 (+,*) within
+2 * d * 2^-24 relative, d being the number of terms of the entry (each side
+sums the same positive terms in a different order, and the recursive-sum
+bound of one side is (d - 1) u).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.helpers import assert_canonical, assert_same, triples
+
+pytestmark = pytest.mark.gpu
+
+SEMIRINGS = ["plus_times_f64", "plus_times_f32", "min_plus_i32", "or_and_bool"]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1006_2183_amd as sg
+    sg.load_library()
+    return sg
+
+
+def term_counts(A, B):
+    """Number of products per output entry (oracle on all-ones operands)."""
+    def ones(M):
+        import types
+        return types.SimpleNamespace(fmt=M.fmt, nrows=M.nrows, ncols=M.ncols, ptr=M.ptr, idx=M.idx,
+                                     vid=M.vid, val=np.ones(M.nnz))
+    C, _ = oracle.spgemm("plus_times_f64", ones(A), ones(B))
+    return C
+
+
+def check(semiring, Cg, A, B, what=""):
+    R, flops = oracle.spgemm(semiring, A, B)
+    assert_canonical(Cg)
+    if semiring == "plus_times_f32":
+        assert_same(Cg, R, "or_and_bool", what=what)
+        _, _, vg = triples(Cg)
+        _, _, vr = triples(R)
+        _, _, d = triples(term_counts(A, B))
+        err = np.abs(vg.astype(np.float64) - vr.astype(np.float64))
+        tol = 2.0 * d * 2.0 ** -24 * np.abs(vr.astype(np.float64))
+        assert np.all(err <= tol), f"{what}: f32 values beyond 2 d u"
+    else:
+        assert_same(Cg, R, semiring, 1e-12, what)
+    return R, flops
+
+
+def gpu_product(sg, semiring, A, B, out_fmt=None, batched=False, **tune):
+    dA = sg.DevMat.from_host(A, "cuda", semiring)
+    dB = sg.DevMat.from_host(B, "cuda", semiring)
+    t = sg.make_tuning(semiring, **tune) if tune else None
+    plan = sg.spgemm_symbolic(semiring, [dA], [dB], out_fmt=out_fmt, tuning=t)
+    C = plan.alloc_outputs()
+    (sg.spgemm_batched if batched else sg.spgemm_numeric)(plan, C)
+    import torch
+    torch.cuda.synchronize()
+    info = plan.infos[0]
+    plan.destroy()
+    return C[0].to_host(), info
+
+
+@pytest.mark.parametrize("semiring", SEMIRINGS)
+@pytest.mark.parametrize("batched", [False, True])
+def test_rmat_s10_default_tiers(sg, semiring, batched):
+    _say(f"case rmat s10 ef8 {semiring} batched={batched}")
+    A = W.rmat_matrix(10, 8, semiring, "csr", seed=1)
+    C, info = gpu_product(sg, semiring, A, A, batched=batched)
+    R, flops = check(semiring, C, A, A, "rmat10")
+    assert info["flops"] == flops
+    assert info["nnz"] == R.nnz
+    assert info["nnz_ub"] >= R.nnz
+
+
+@pytest.mark.parametrize("semiring", SEMIRINGS)
+@pytest.mark.parametrize("force,mid_kind", [(0, 0), (1, 0), (1, 1), (2, 0)])
+def test_forced_tiers_several_windows(sg, semiring, force, mid_kind):
+    """Every tier on every vector it can take, with heavy windows that leave a ragged tail."""
+    _say(f"case forced tier {force} mid_kind {mid_kind} {semiring}")
+    A = W.rmat_matrix(13, 8, semiring, "csr", seed=4)
+    # 16 KB of LDS: windows of ~2K ids over 8192 columns (five windows, the last partial)
+    C, info = gpu_product(sg, semiring, A, A, force_tier=force, mid_kind=mid_kind, lds_bytes=16384,
+                          block_threads=256)
+    check(semiring, C, A, A, f"force{force}")
+    if force == 2:
+        assert info["n_mid"] == 0 and info["n_tiny"] == 0
+    if force == 1:
+        assert info["n_mid"] > 0
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32", "or_and_bool"])
+@pytest.mark.parametrize("fa,fb,fo", [("csc", "csc", "csc"), ("dcsc", "dcsc", "dcsc"), ("dcsr", "dcsr", "dcsr"),
+                                      ("csr", "dcsr", "csr"), ("dcsc", "csc", "dcsc"), ("csr", "csr", "dcsr"),
+                                      ("csc", "dcsc", "dcsc")])
+def test_formats(sg, semiring, fa, fb, fo):
+    _say(f"case formats {fa} {fb} -> {fo} {semiring}")
+    A = W.rmat_matrix(11, 8, semiring, "csr", seed=6)
+    Af = W.to_format(A, fa, semiring)
+    Bf = W.to_format(A, fb, semiring)
+    for force in (-1, 2):
+        C, _ = gpu_product(sg, semiring, Af, Bf, out_fmt=fo, force_tier=force, lds_bytes=8192, block_threads=128)
+        assert C.fmt == fo
+        check(semiring, C, Af, Bf, f"{fa}{fb}{fo}")
+
+
+@pytest.mark.parametrize("fmt", ["csc", "dcsc", "csr", "dcsr"])
+def test_paper_fig8_example_gpu(sg, fmt):
+    from tests.golden import fixtures
+    f = fixtures.read("fig8_example.txt")
+    a = np.array(f["A"], dtype=np.int64) - 1
+    b = np.array(f["B"], dtype=np.int64) - 1
+    A = W.from_triples(a[:, 0], a[:, 1], np.ones(len(a)), 6, 6, fmt)
+    B = W.from_triples(b[:, 0], b[:, 1], np.ones(len(b)), 6, 6, fmt)
+    for force in (-1, 1, 2):
+        C, info = gpu_product(sg, "plus_times_f64", A, B, force_tier=force)
+        assert info["flops"] == 19
+        exp = np.array(f["C"], dtype=np.int64)
+        R = W.from_triples(exp[:, 0] - 1, exp[:, 1] - 1, exp[:, 2].astype(np.float64), 6, 6, "csr")
+        assert_same(C, R, "plus_times_f64", 0.0)
+
+
+def test_aux_matches_paper_example(sg):
+    from tests.golden import fixtures
+    f = fixtures.read("dcsc_example.txt")
+    n = int(f["n"][0][0])
+    t = f["triples"]
+    r = np.array([int(x[0]) for x in t]) - 1
+    c = np.array([int(x[1]) for x in t]) - 1
+    d = W.from_triples(r, c, np.array([float(x[2]) for x in t]), n, n, "dcsc")
+    aux = sg.build_aux(sg.DevMat.from_host(d, "cuda")).cpu().numpy()
+    assert (aux + 1).tolist() == [int(x) for x in f["aux"][0]]
+
+
+@pytest.mark.parametrize("semiring", SEMIRINGS)
+def test_edge_cases(sg, semiring):
+    _say(f"case edge {semiring}")
+    rng = np.random.default_rng(0)
+    for fmt in ("csr", "dcsc"):
+        # 1 x 1
+        X = W.from_triples([0], [0], W.random_values(rng, 1, semiring), 1, 1, fmt, semiring)
+        C, _ = gpu_product(sg, semiring, X, X)
+        check(semiring, C, X, X, "1x1")
+        # an operand with no entries
+        E = W.random_sparse(40, 30, 0.0, semiring, fmt, 1)
+        B = W.random_sparse(30, 20, 0.3, semiring, fmt, 2)
+        C, info = gpu_product(sg, semiring, E, B)
+        assert info["nnz"] == 0 and info["flops"] == 0
+        check(semiring, C, E, B, "empty")
+        # one dense column of B against a hub: a single heavy output vector
+        n = 3000
+        col = np.arange(n)
+        Bd = W.from_triples(col, np.zeros(n, dtype=np.int64), W.random_values(rng, n, semiring), n, 1, fmt, semiring)
+        Ah = W.random_sparse(n, n, 0.004, semiring, fmt, 3)
+        C, info = gpu_product(sg, semiring, Ah, Bd, lds_bytes=4096, block_threads=64)
+        check(semiring, C, Ah, Bd, "dense column")
+        # rectangular, mostly empty vectors
+        A = W.random_sparse(500, 7, 0.05, semiring, fmt, 4)
+        B = W.random_sparse(7, 900, 0.01, semiring, fmt, 5)
+        C, _ = gpu_product(sg, semiring, A, B)
+        check(semiring, C, A, B, "rect")
+
+
+def test_identity_and_permutation_bit_exact(sg):
+    for semiring in ("plus_times_f64", "min_plus_i32"):
+        A = W.rmat_matrix(12, 8, semiring, "csr", seed=8)
+        n = A.nrows
+        Q = W.permutation_matrix(n, 5, "csr", semiring)
+        for L, R in ((A, Q), (Q, A), (A, W.identity_matrix(n, "csr", semiring))):
+            C, _ = gpu_product(sg, semiring, L, R)
+            Ro, _ = oracle.spgemm(semiring, L, R)
+            assert_same(C, Ro, semiring, 0.0)
+
+
+def test_errors(sg):
+    import torch
+    A = W.rmat_matrix(8, 8, "plus_times_f64", "csr", seed=2)
+    dA = sg.DevMat.from_host(A, "cuda")
+    plan = sg.spgemm_symbolic("plus_times_f64", [dA], [dA])
+    C = plan.alloc_outputs()[0]
+    C.idx = C.idx[: max(0, C.idx.numel() - 1)]
+    with pytest.raises(sg.SgError) as e:
+        sg.spgemm_numeric(plan, [C])
+    assert e.value.status == -6
+    plan.destroy()
+    # a non-canonical operand is reported by validation
+    bad = sg.DevMat.from_host(A, "cuda")
+    idx = bad.idx.clone()
+    a, b = int(A.ptr[3]), int(A.ptr[4])
+    if b - a >= 2:
+        idx[a], idx[a + 1] = bad.idx[a + 1], bad.idx[a]
+    else:
+        idx[0] = A.ncols + 5
+    bad.idx = idx
+    assert sg.validate(dA)
+    assert not sg.validate(bad)
+    t = sg.make_tuning("plus_times_f64", validate=1)
+    with pytest.raises(sg.SgError) as e:
+        sg.spgemm_symbolic("plus_times_f64", [bad], [dA], tuning=t)
+    assert e.value.status == -3
+    torch.cuda.synchronize()
+
+
+def _rows(A, rows):
+    """Host CSR of the selected rows of A (input preparation for the oracle)."""
+    import types
+    lens = np.diff(A.ptr)[rows]
+    ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(lens, out=ptr[1:])
+    sel = np.concatenate([np.arange(A.ptr[r], A.ptr[r + 1]) for r in rows]) if len(rows) else np.zeros(0, np.int64)
+    return types.SimpleNamespace(fmt="csr", nrows=len(rows), ncols=A.ncols, ptr=ptr, idx=A.idx[sel],
+                                 val=None if A.val is None else A.val[sel], vid=None)
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
+def test_rmat_s18_sampled_rows(sg, semiring):
+    """Full-size product (R-MAT scale 18, edge factor 16) in the benchmark's configuration,
+    checked on sampled rows (the heaviest ones and a seeded random sample)."""
+    import torch
+    _say(f"case rmat s18 ef16 {semiring}")
+    A = W.rmat_matrix(18, 16, semiring, "csr", seed=1)
+    dA = sg.DevMat.from_host(A, "cuda", semiring)
+    plan = sg.spgemm_symbolic(semiring, [dA], [dA])
+    info = plan.infos[0]
+    Cd = plan.alloc_outputs()[0]
+    sg.spgemm_numeric(plan, [Cd])
+    torch.cuda.synchronize()
+    plan.destroy()
+    # flops identity (Section 2.4): sum over k of nnz(A(:,k)) nnz(A(k,:))
+    colc = np.bincount(A.idx, minlength=A.ncols).astype(np.int64)
+    rowc = np.diff(A.ptr).astype(np.int64)
+    assert info["flops"] == int(np.dot(colc, rowc))
+    cptr = Cd.ptr.cpu().numpy()
+    assert cptr[0] == 0 and np.all(np.diff(cptr) >= 0)
+    assert info["nnz"] == cptr[-1] and info["nnz"] <= info["flops"]
+    rf = np.zeros(A.nrows, dtype=np.int64)
+    np.add.at(rf, np.repeat(np.arange(A.nrows), np.diff(A.ptr)), rowc[A.idx])
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([np.argsort(rf)[-24:], rng.choice(A.nrows, 1500, replace=False)]))
+    R, _ = oracle.spgemm(semiring, _rows(A, rows), A)
+    lens = np.diff(cptr)[rows]
+    assert np.array_equal(lens, np.diff(R.ptr)), "row sizes differ"
+    sel = np.concatenate([np.arange(cptr[r], cptr[r + 1]) for r in rows])
+    st = torch.as_tensor(sel, device="cuda")
+    cidx = Cd.idx[st].cpu().numpy()
+    assert np.array_equal(cidx, R.idx)
+    cval = Cd.val[st].cpu().numpy()
+    if semiring == "min_plus_i32":
+        assert np.array_equal(cval, R.val)
+    else:
+        err = np.abs(cval - R.val)
+        assert np.all(err <= 1e-12 * np.abs(R.val))
