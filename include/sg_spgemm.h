@@ -113,10 +113,12 @@ typedef struct {
  *   mid_kind         0 = bitmap-rank accumulator, 1 = LDS hash accumulator
  *   lds_bytes        LDS budget of one workgroup of the mid/heavy tiers
  *   block_threads    threads per workgroup of the mid/heavy tiers (64..1024)
- *   chunk_width      heavy tier: output-index window of one dense LDS
- *                    accumulator (0 = the largest that fits lds_bytes)
- *   heavy_kind       0 = windowed dense accumulator reading the operand in
- *                    place, 1 = expand-sort-compress through global memory
+ *   chunk_width      heavy tier: width in ids of one split bucket (rank
+ *                    windows) or of one dense window (0 = automatic)
+ *   heavy_kind       heavy tier: 0 = bitmap-rank windows planned from exact
+ *                    bucket counts wherever the id-range bitmap fits in LDS,
+ *                    dense windows elsewhere; 1 = dense windows only (each
+ *                    one a flag bit and a value slot per id)
  *   force_tier       -1 = bin by size; 0/1/2 = route every vector with
  *                    work to the tiny / mid / heavy tier where it is legal
  *                    (tiny needs flops <= 64, mid needs the bound to fit)
@@ -148,6 +150,10 @@ typedef struct {
     int64_t n_mid;
     int64_t n_heavy;
     int64_t n_heavy_items; /* (vector, window) work items of the heavy tier  */
+    /* totals per tier (index 0 tiny, 1 mid, 2 heavy) over the whole call:  */
+    int64_t tier_flops[3]; /* multiplications                               */
+    int64_t tier_sent[3];  /* stored entries of the streamed operand read   */
+    int64_t tier_nnz[3];   /* output entries written                        */
 } sg_sym_info;
 
 typedef struct sg_plan sg_plan;
@@ -218,6 +224,19 @@ sg_status sg_spgemm_numeric(sg_plan *plan, sg_mat_out *C, void *stream);
  * values. Errors: as sg_spgemm_numeric.
  */
 sg_status sg_spgemm_batched(sg_plan *plan, sg_mat_out *C, void *stream);
+
+/*
+ * Kernel timing for measurement. With enable = 1, the following
+ * sg_spgemm_numeric / sg_spgemm_batched calls on this plan record HIP events
+ * on their stream around every kernel launch (do not enable it for a call
+ * that is being captured into a graph). sg_plan_kernel_times waits for the
+ * events of the last such call and writes up to n durations in milliseconds:
+ * out_ms[0] heavy tier (or the whole persistent launch of a batched call),
+ * out_ms[1] mid tier, out_ms[2] tiny tier, out_ms[3] output pointers.
+ * A launch that did not run reports 0.
+ */
+sg_status sg_plan_profile(sg_plan *plan, int32_t enable);
+sg_status sg_plan_kernel_times(sg_plan *plan, double *out_ms, int32_t n);
 
 /* Release a plan (host memory only; the workspace stays the caller's). */
 sg_status sg_plan_destroy(sg_plan *plan);

@@ -23,7 +23,8 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID_ARG", -2: "SG_ERR_DIM_MISMATCH", -3: "
           -8: "SG_ERR_OOM"}
 
 EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
-           "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_destroy", "sg_validate", "sg_build_aux"]
+           "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
+           "sg_validate", "sg_build_aux"]
 
 
 class SgError(RuntimeError):
@@ -60,10 +61,15 @@ class sg_tuning(ctypes.Structure):
 
 class sg_sym_info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("flops", "nnz_ub", "nnz", "nvec", "max_vec_flops", "n_out_vec",
-                                              "n_tiny", "n_mid", "n_heavy", "n_heavy_items")]
+                                              "n_tiny", "n_mid", "n_heavy", "n_heavy_items")] + [
+        ("tier_flops", ctypes.c_int64 * 3), ("tier_sent", ctypes.c_int64 * 3), ("tier_nnz", ctypes.c_int64 * 3)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        d = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            d[f] = [int(x) for x in v] if f.startswith("tier_") else int(v)
+        return d
 
 
 _lib = None
@@ -93,6 +99,10 @@ def load_library(path: str = LIB_PATH):
     lib.sg_spgemm_numeric.argtypes = [ctypes.c_void_p, P(sg_mat_out), ctypes.c_void_p]
     lib.sg_spgemm_batched.restype = ctypes.c_int
     lib.sg_spgemm_batched.argtypes = [ctypes.c_void_p, P(sg_mat_out), ctypes.c_void_p]
+    lib.sg_plan_profile.restype = ctypes.c_int
+    lib.sg_plan_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.sg_plan_kernel_times.restype = ctypes.c_int
+    lib.sg_plan_kernel_times.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int32]
     lib.sg_plan_destroy.restype = ctypes.c_int
     lib.sg_plan_destroy.argtypes = [ctypes.c_void_p]
     lib.sg_validate.restype = ctypes.c_int
@@ -207,6 +217,16 @@ class Plan:
         self.handle = handle
         self.ws = ws
         self.infos = infos
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every kernel launch of later numeric/batched calls."""
+        _check(load_library().sg_plan_profile(self.handle, 1 if enable else 0), "sg_plan_profile")
+
+    def kernel_times(self):
+        """Milliseconds of the last profiled call: heavy (or persistent), mid, tiny, pointers."""
+        out = (ctypes.c_double * 4)()
+        _check(load_library().sg_plan_kernel_times(self.handle, out, 4), "sg_plan_kernel_times")
+        return {"heavy": out[0], "mid": out[1], "tiny": out[2], "ptr": out[3]}
 
     def destroy(self):
         if self.handle:

@@ -39,17 +39,21 @@ struct ProdDev {
   int64_t aux_chunk;     // columns per AUX chunk
   int64_t aux_n;         // number of AUX chunks
   int32_t *gres;         // per S entry: resolved G vector (doubly compressed G only)
-  int32_t *wsplit;       // per G vector: nwin + 1 offsets of the output windows, or null
+  int32_t *wsplit;       // per G vector: nsplit + 1 offsets of the split buckets, or null
   int32_t group;
-  int32_t nwin;          // output windows of this product's group
+  int32_t nsplit;        // split buckets of this product's group
 };
 
 // One output C_g.
 struct GroupDev {
   int64_t minor;         // minor dimension of C_g (its output id range)
   int64_t major;         // major dimension of C_g
-  int32_t nwin;          // heavy-tier windows covering [0, minor)
+  int32_t nsplit;        // split buckets of `sw` ids covering [0, minor)
+  int32_t sw;            // split bucket width (a multiple of 32)
+  int32_t mode;          // heavy tier: 0 dense windows of one bucket, 1 rank windows of several buckets
   int32_t mid_ok;        // largest mid-tier vector of this group (0: the mid tier does not fit)
+  int32_t rank_cap;      // mode 1: most entries one window may hold
+  int32_t rank_wb;       // mode 1: most buckets one window may span
   int64_t ov_begin;      // first output vector of this group (device-filled)
   int64_t ov_end;
   int64_t nnz_base;      // global exclusive offset of the group's first entry
@@ -91,7 +95,10 @@ enum Counter {
   kCtQueue,        // work queue head of the persistent launch
   kCtQueueCount,   // work queue head of the persistent count launch
   kCtBad,          // validation failures
-  kCtNum
+  kCtTierFlops,    // 3 entries: multiplications per tier
+  kCtTierSent = kCtTierFlops + 3,  // 3 entries: streamed entries per tier
+  kCtTierNnz = kCtTierSent + 3,    // 3 entries: output entries per tier
+  kCtNum = kCtTierNnz + 3
 };
 
 // Everything a numeric or count kernel reads, passed by value.
@@ -112,10 +119,11 @@ struct Plan {
   const int32_t *mid_list;
   const int32_t *heavy_list;
   const int32_t *item_vec;   // heavy item -> position in heavy_list
-  const int32_t *item_win;   // heavy item -> window
-  int32_t *item_cnt;
-  int64_t *item_off;         // exclusive, relative to the group's first entry
-  int32_t win;               // window width of the heavy tier
+  const int32_t *item_b0;    // heavy item -> first split bucket
+  const int32_t *item_b1;    // heavy item -> one past the last split bucket
+  const int64_t *item_off;   // heavy item -> offset of its entries inside its vector
+  int32_t *bcnt;             // heavy vector q: entries per split bucket, at q * nbmax
+  int32_t nbmax;             // largest nsplit of any group
   int32_t mid_cap;           // max entries of a mid-tier vector
   int32_t mid_kind;          // 0 bitmap-rank, 1 hash
   int32_t lds_words;         // dynamic LDS size in 32-bit words

@@ -68,12 +68,6 @@ struct Carve {
   }
 };
 
-// Derived sizes of the mid and heavy tiers for one output id range.
-struct TierGeom {
-  int win;      // heavy window width (ids)
-  int lds;      // LDS bytes per workgroup
-  int threads;  // threads per workgroup
-};
 
 int heavy_window(const sg_tuning &t, int32_t kind) {
   const int sb = slot_bytes(kind);
@@ -81,7 +75,7 @@ int heavy_window(const sg_tuning &t, int32_t kind) {
   // flags live at the front in whole 64-bit units; keep the value array aligned
   while (w > 32 && 4 * (((w + 31) / 32 + 1) & ~1ll) + (int64_t)w * sb > t.lds_bytes) w -= 32;
   w &= ~31ll;
-  if (t.chunk_width > 0 && t.chunk_width < w) w = t.chunk_width & ~31;
+  if (t.heavy_kind == 1 && t.chunk_width > 0 && t.chunk_width < w) w = t.chunk_width & ~31;
   if (w < 32) w = 32;
   return (int)w;
 }
@@ -105,6 +99,53 @@ int64_t mid_capacity(const sg_tuning &t, int32_t kind, int64_t minor) {
   }
   if (cap > t.mid_max_ub) cap = t.mid_max_ub;
   return cap < 0 ? 0 : cap;
+}
+
+// Heavy-tier geometry of one output id range (see GroupDev).
+struct Geom {
+  int32_t nsplit = 1, sw = 32, mode = 0, rank_cap = 0, rank_wb = 0;
+};
+
+Geom group_geom(const sg_tuning &t, int32_t kind, int64_t minor, int win_dense) {
+  const int64_t sb = slot_bytes(kind);
+  const int64_t L = t.lds_bytes;
+  Geom g;
+  if (minor <= win_dense) {  // one dense window covers every id
+    g.sw = win_dense;
+    return g;
+  }
+  if (sb > 0 && t.heavy_kind == 0) {
+    int64_t cap = (L / 2) / sb;
+    if (cap > 65504) cap = 65504;  // ranks are kept in 16 bits
+    cap &= ~31ll;
+    int64_t sw = t.chunk_width > 0 ? t.chunk_width : 4096;
+    if (sw > cap) sw = cap;
+    sw &= ~31ll;
+    if (sw >= 32) {
+      const int64_t nw32 = (minor + 31) / 32;
+      const int64_t nb = (minor + sw - 1) / sw;
+      const bool count_fits = 4 * (nw32 + nb) <= L;
+      int64_t wb = 0;
+      while (wb < nb) {
+        const int64_t nwds = (wb + 1) * sw / 32;
+        const int64_t words = (nwds + (nwds + 1) / 2 + 1) & ~1ll;
+        if (4 * words + cap * sb > L) break;
+        ++wb;
+      }
+      if (count_fits && wb >= 1 && nb < INT32_MAX) {
+        g.mode = 1;
+        g.sw = (int32_t)sw;
+        g.nsplit = (int32_t)nb;
+        g.rank_cap = (int32_t)cap;
+        g.rank_wb = (int32_t)wb;
+        return g;
+      }
+    }
+  }
+  g.mode = 0;
+  g.sw = win_dense;
+  g.nsplit = (int32_t)((minor + win_dense - 1) / win_dense);
+  return g;
 }
 
 }  // namespace
@@ -132,6 +173,12 @@ struct sg_plan {
   OutDev *outs_dev = nullptr;
   OutDev *outs_host = nullptr;  // pinned staging of the output table
   int64_t *host_stats = nullptr;  // pinned
+  // optional kernel timing: events around [heavy, mid, tiny, pointers]
+  bool profile = false;
+  bool events_made = false;
+  bool timed = false;
+  bool ran[4] = {false, false, false, false};
+  hipEvent_t ev[8];
 };
 
 namespace {
@@ -147,7 +194,7 @@ struct Layout {
   int64_t *ov_seg, *ov_flops, *ov_cnt, *ov_off, *nzflag, *nzpos;
   int32_t *tiny, *mid, *heavy;
   int64_t *heavy_nwin, *ibase;
-  int32_t *item_vec, *item_win, *item_cnt;
+  int32_t *item_vec, *item_b0, *item_b1, *bcnt;
   int64_t *item_off;
   std::vector<int32_t *> gres, aux, wsplit;
   std::vector<int64_t> aux_chunk, aux_n;
@@ -161,9 +208,9 @@ struct Shape {
   int64_t nov_max = 0;
   int64_t ndense = 0;        // sum of output major dims (multi-product groups)
   int64_t ndense_ptr = 0;    // sum of (major + 1) for dense output pointers
-  int32_t max_nwin = 1;
+  int32_t nbmax = 1;
   bool dense_path = false;
-  std::vector<int32_t> nwin;  // per group
+  std::vector<Geom> geom;  // per group
   std::vector<int64_t> minor, major;
   std::vector<int32_t> gres_src, wsplit_src, aux_src;  // dedupe: product sharing the table
 };
@@ -238,20 +285,18 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
                 int32_t ngroup, const sg_tuning &t, int win, Shape &sh) {
   sh.nov_max = 0;
   for (int32_t p = 0; p < nprod; ++p) sh.nov_max += view(A[p], B[p]).S->nvec;
-  sh.nwin.resize(ngroup);
-  sh.max_nwin = 1;
+  sh.geom.resize(ngroup);
+  sh.nbmax = 1;
   sh.ndense = 0;
   sh.ndense_ptr = 0;
   for (int32_t g = 0; g < ngroup; ++g) {
-    int64_t nw = (sh.minor[g] + win - 1) / win;
-    if (nw < 1) nw = 1;
-    sh.nwin[g] = (int32_t)nw;
-    sh.max_nwin = std::max<int32_t>(sh.max_nwin, (int32_t)nw);
+    sh.geom[g] = group_geom(t, kind, sh.minor[g], win);
+    sh.nbmax = std::max<int32_t>(sh.nbmax, sh.geom[g].nsplit);
     sh.ndense += sh.major[g];
     sh.ndense_ptr += sh.major[g] + 1;
   }
-  // products whose gathered operand is the same arrays (and window count)
-  // share the AUX, resolution-free split tables
+  // products whose gathered operand is the same arrays share the AUX index,
+  // and the split table too when their groups split ids the same way
   sh.wsplit_src.assign(nprod, -1);
   sh.aux_src.assign(nprod, -1);
   for (int32_t p = 0; p < nprod; ++p) {
@@ -260,12 +305,11 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
       const sg_mat *H = view(A[q], B[q]).G;
       if (H->ptr == G->ptr && H->idx == G->idx && H->vid == G->vid && H->nvec == G->nvec) {
         if (sh.aux_src[p] < 0) sh.aux_src[p] = q;
-        if (sh.wsplit_src[p] < 0 && sh.nwin[grp[q]] == sh.nwin[grp[p]]) sh.wsplit_src[p] = q;
+        const Geom &a = sh.geom[grp[q]], &b = sh.geom[grp[p]];
+        if (sh.wsplit_src[p] < 0 && a.nsplit == b.nsplit && a.sw == b.sw) sh.wsplit_src[p] = q;
       }
     }
   }
-  (void)kind;
-  (void)t;
 }
 
 Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t ngroup, const Shape &sh,
@@ -294,10 +338,11 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.heavy = c.take<int32_t>(nov);
   L.heavy_nwin = c.take<int64_t>(nov + 1);
   L.ibase = c.take<int64_t>(nov + 1);
-  const int64_t items = nov * (int64_t)sh.max_nwin;
+  const int64_t items = nov * (int64_t)sh.nbmax;
   L.item_vec = c.take<int32_t>(items);
-  L.item_win = c.take<int32_t>(items);
-  L.item_cnt = c.take<int32_t>(items);
+  L.item_b0 = c.take<int32_t>(items);
+  L.item_b1 = c.take<int32_t>(items);
+  L.bcnt = c.take<int32_t>(items);
   L.item_off = c.take<int64_t>(items);
   L.gres.assign(nprod, nullptr);
   L.aux.assign(nprod, nullptr);
@@ -318,10 +363,10 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
       if (sh.aux_src[p] >= 0) L.aux[p] = L.aux[sh.aux_src[p]];
       else L.aux[p] = c.take<int32_t>(nchunks + 1);
     }
-    const int32_t nw = sh.nwin[grp[p]];
-    if (nw > 1) {
+    const int32_t nb = sh.geom[grp[p]].nsplit;
+    if (nb > 1) {
       if (sh.wsplit_src[p] >= 0) L.wsplit[p] = L.wsplit[sh.wsplit_src[p]];
-      else L.wsplit[p] = c.take<int32_t>(G.nvec * (int64_t)(nw + 1));
+      else L.wsplit[p] = c.take<int32_t>(G.nvec * (int64_t)(nb + 1));
     }
   }
   int64_t scan_max = std::max<int64_t>(nov + 1, sh.ndense + 1);
@@ -376,7 +421,7 @@ void normalise(sg_tuning &t, int32_t kind) {
   t.lds_bytes &= ~7;
   if (t.block_threads < 64 || t.block_threads > 1024 || t.block_threads % 64) t.block_threads = d.block_threads;
   if (t.chunk_width < 0) t.chunk_width = 0;
-  if (t.heavy_kind != 0) t.heavy_kind = 0;
+  if (t.heavy_kind != 0 && t.heavy_kind != 1) t.heavy_kind = 0;
   if (t.force_tier < -1 || t.force_tier > 2) t.force_tier = -1;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) t.blocks_per_cu = d.blocks_per_cu;
 }
@@ -407,6 +452,13 @@ sg_status launch_counts(sg_plan *pl, hipStream_t st) {
   return SG_OK;
 }
 
+sg_status mark(sg_plan *pl, int which, bool end, hipStream_t st) {
+  if (!pl->profile) return SG_OK;
+  SG_HIP(hipEventRecord(pl->ev[2 * which + (end ? 1 : 0)], st));
+  if (end) pl->ran[which] = true;
+  return SG_OK;
+}
+
 template <int K>
 sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
   const Plan &P = pl->P;
@@ -416,19 +468,25 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
   const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
   SG_TRY(fill64(pl->counters + kCtNum + 2, 2, 0, st));
   if (I.n_heavy_items > 0) {
+    SG_TRY(mark(pl, 0, false, st));
     hipLaunchKernelGGL((k_heavy<K, false>), dim3((unsigned)std::min<int64_t>(persist, I.n_heavy_items)), dim3(nt), lds, st,
                        P, pl->counters + kCtNum + 2);
     SG_HIP(hipGetLastError());
+    SG_TRY(mark(pl, 0, true, st));
   }
   if (I.n_mid > 0) {
+    SG_TRY(mark(pl, 1, false, st));
     hipLaunchKernelGGL((k_mid<K, false>), dim3((unsigned)std::min<int64_t>(persist, I.n_mid)), dim3(nt), lds, st, P,
                        pl->counters + kCtNum + 3);
     SG_HIP(hipGetLastError());
+    SG_TRY(mark(pl, 1, true, st));
   }
   if (I.n_tiny > 0) {
+    SG_TRY(mark(pl, 2, false, st));
     hipLaunchKernelGGL((k_tiny<K, false>), dim3((unsigned)std::min<int64_t>((I.n_tiny + 3) / 4, persist * 8)), dim3(256), 0,
                        st, P);
     SG_HIP(hipGetLastError());
+    SG_TRY(mark(pl, 2, true, st));
   }
   return SG_OK;
 }
@@ -441,9 +499,11 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   const sg_sym_info &I = pl->info[0];
   const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
+  SG_TRY(mark(pl, 0, false, st));
   hipLaunchKernelGGL((k_batched<K>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
                      (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
   SG_HIP(hipGetLastError());
+  SG_TRY(mark(pl, 0, true, st));
   return SG_OK;
 }
 
@@ -500,6 +560,9 @@ sg_status emit_outputs(sg_plan *pl, sg_mat_out *C, hipStream_t st) {
     D.pad = 0;
   }
   SG_HIP(hipMemcpyAsync(pl->outs_dev, pl->outs_host, sizeof(OutDev) * pl->ngroup, hipMemcpyHostToDevice, st));
+  for (int i = 0; i < 4; ++i) pl->ran[i] = false;
+  pl->timed = pl->profile;
+  SG_TRY(mark(pl, 3, false, st));
   if (doubly(pl->out_fmt)) {
     hipLaunchKernelGGL(k_emit_ptr_doubly, dim3((unsigned)grid_for(pl->nov_max + 1, kFillThreads)), dim3(kFillThreads), 0,
                        st, pl->P, pl->nzpos, pl->ngroup);
@@ -508,6 +571,7 @@ sg_status emit_outputs(sg_plan *pl, sg_mat_out *C, hipStream_t st) {
                        st, pl->P, pl->pbase, pl->ngroup, pl->ndense_ptr);
   }
   SG_HIP(hipGetLastError());
+  SG_TRY(mark(pl, 3, true, st));
   return SG_OK;
 }
 
@@ -642,7 +706,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     d.gres = L.gres[p];
     d.wsplit = L.wsplit[p];
     d.group = grp[p];
-    d.nwin = sh.nwin[grp[p]];
+    d.nsplit = sh.geom[grp[p]].nsplit;
     vbase[q + 1] = vbase[q] + pv.S->nvec;
   }
   std::vector<GroupDev> groups(ngroup);
@@ -651,7 +715,12 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     GroupDev &G = groups[g];
     G.minor = sh.minor[g];
     G.major = sh.major[g];
-    G.nwin = sh.nwin[g];
+    const Geom &ge = sh.geom[g];
+    G.nsplit = ge.nsplit;
+    G.sw = ge.sw;
+    G.mode = ge.mode;
+    G.rank_cap = ge.rank_cap;
+    G.rank_wb = ge.rank_wb;
     const int64_t cap = mid_capacity(t, sr->kind, G.minor);
     G.mid_ok = cap > 0 ? (int32_t)std::min<int64_t>(cap, INT32_MAX) : 0;
     G.ov_begin = G.ov_end = G.nnz_base = G.nz_base = 0;
@@ -738,10 +807,11 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   P.mid_list = L.mid;
   P.heavy_list = L.heavy;
   P.item_vec = L.item_vec;
-  P.item_win = L.item_win;
-  P.item_cnt = L.item_cnt;
+  P.item_b0 = L.item_b0;
+  P.item_b1 = L.item_b1;
   P.item_off = L.item_off;
-  P.win = win;
+  P.bcnt = L.bcnt;
+  P.nbmax = sh.nbmax;
   P.mid_cap = t.mid_max_ub;
   P.mid_kind = t.mid_kind;
   P.lds_words = t.lds_bytes / 4;
@@ -764,25 +834,25 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   for (int32_t q = 0; q < nprod; ++q) {
     const int32_t p = order[q];
     const ProdDev &d = prods[q];
-    if (d.nwin > 1 && sh.wsplit_src[p] < 0 && d.g_nvec > 0) {
-      const int64_t n = d.g_nvec * (int64_t)(d.nwin + 1);
+    if (d.nsplit > 1 && sh.wsplit_src[p] < 0 && d.g_nvec > 0) {
+      const int64_t n = d.g_nvec * (int64_t)(d.nsplit + 1);
       hipLaunchKernelGGL(k_wsplit, dim3((unsigned)grid_for(n, kFillThreads)), dim3(kFillThreads), 0, st, d.g_ptr,
-                         d.g_idx, d.g_nvec, d.nwin, win, d.wsplit);
+                         d.g_idx, d.g_nvec, d.nsplit, sh.geom[grp[p]].sw, d.wsplit);
       SG_HIP(hipGetLastError());
     }
   }
-  hipLaunchKernelGGL(k_heavy_nwin, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+
+  // exact sizes, then the heavy windows planned from the bucket counts
+  SG_TRY(dispatch<RunCounts>(sr->kind, pl, st));
+  hipLaunchKernelGGL(k_plan_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
                      sh.nov_max, L.heavy_nwin);
   SG_HIP(hipGetLastError());
   SG_TRY(scan64(L.heavy_nwin, sh.nov_max, L.ibase, L.part, st));
-  hipLaunchKernelGGL(k_heavy_items, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
-                     L.ibase, sh.nov_max, L.item_vec, L.item_win, L.counters);
+  hipLaunchKernelGGL(k_plan_fill, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                     L.ibase, sh.nov_max, L.item_vec, L.item_b0, L.item_b1, L.item_off, L.counters);
   SG_HIP(hipGetLastError());
-
-  // exact sizes
-  SG_TRY(dispatch<RunCounts>(sr->kind, pl, st));
-  hipLaunchKernelGGL(k_heavy_totals, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
-                     L.ibase);
+  hipLaunchKernelGGL(k_tier_nnz, dim3((unsigned)std::min<int64_t>(grid_for(sh.nov_max, 256), 1024)), dim3(256), 0, st, P,
+                     L.counters);
   SG_HIP(hipGetLastError());
   SG_TRY(scan64(L.ov_cnt, sh.nov_max, L.ov_off, L.part, st));
   hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
@@ -813,6 +883,11 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     I.n_mid = cnt[kCtMid];
     I.n_heavy = cnt[kCtHeavy];
     I.n_heavy_items = cnt[kCtItems];
+    for (int x = 0; x < 3; ++x) {
+      I.tier_flops[x] = cnt[kCtTierFlops + x];
+      I.tier_sent[x] = cnt[kCtTierSent + x];
+      I.tier_nnz[x] = cnt[kCtTierNnz + x];
+    }
     info[g] = I;
   }
   guard.p = nullptr;
@@ -834,8 +909,34 @@ sg_status sg_spgemm_batched(sg_plan *pl, sg_mat_out *C, void *stream) {
   return dispatch<RunBatched>(pl->kind, pl, st);
 }
 
+sg_status sg_plan_profile(sg_plan *pl, int32_t enable) {
+  if (!pl) return SG_ERR_INVALID_ARG;
+  if (enable && !pl->events_made) {
+    for (int i = 0; i < 8; ++i) SG_HIP(hipEventCreate(&pl->ev[i]));
+    pl->events_made = true;
+  }
+  pl->profile = enable != 0;
+  return SG_OK;
+}
+
+sg_status sg_plan_kernel_times(sg_plan *pl, double *out_ms, int32_t n) {
+  if (!pl || !out_ms || n < 0) return SG_ERR_INVALID_ARG;
+  for (int32_t i = 0; i < n; ++i) out_ms[i] = 0.0;
+  if (!pl->events_made || !pl->timed) return SG_OK;
+  for (int32_t i = 0; i < n && i < 4; ++i) {
+    if (!pl->ran[i]) continue;
+    SG_HIP(hipEventSynchronize(pl->ev[2 * i + 1]));
+    float ms = 0.f;
+    SG_HIP(hipEventElapsedTime(&ms, pl->ev[2 * i], pl->ev[2 * i + 1]));
+    out_ms[i] = ms;
+  }
+  return SG_OK;
+}
+
 sg_status sg_plan_destroy(sg_plan *pl) {
   if (!pl) return SG_ERR_INVALID_ARG;
+  if (pl->events_made)
+    for (int i = 0; i < 8; ++i) (void)hipEventDestroy(pl->ev[i]);
   if (pl->outs_host) (void)hipHostFree(pl->outs_host);
   if (pl->host_stats) (void)hipHostFree(pl->host_stats);
   delete pl;

@@ -288,63 +288,77 @@ struct BinParams {
 __global__ void k_bin(Plan P, BinParams bp, int64_t *counters, int32_t *tiny, int32_t *mid, int32_t *heavy) {
   const int64_t nov = counters[kCtNov];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t tf[3] = {0, 0, 0}, ts[3] = {0, 0, 0};
   // loop bound is uniform per wave so the ballots see the whole wave
   for (int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & ~(int64_t)(kWave - 1); v0 < nov; v0 += stride) {
     int64_t v = v0 + lane();
     int tier = -1;
+    int64_t f = 0, sent = 0;
     if (v < nov) {
-      int64_t f = P.ov_flops[v];
+      f = P.ov_flops[v];
       const GroupDev &g = P.groups[P.ov_group[v]];
       int64_t ub = f < g.minor ? f : g.minor;
       bool tiny_ok = f <= bp.tiny_max;
       bool mid_fit = g.mid_ok > 0 && ub <= (int64_t)g.mid_ok && ub <= (int64_t)bp.mid_cap;
       // with a single window the heavy tier's dense accumulator covers the
       // whole id range, which beats the mid tier unless it is forced
-      bool mid_ok = mid_fit && g.nwin > 1;
+      bool mid_ok = mid_fit && g.nsplit > 1;
       if (f == 0) tier = -1;
       else if (bp.force == 2) tier = 2;
       else if (bp.force == 1) tier = mid_fit ? 1 : 2;
       else if (tiny_ok) tier = 0;
       else if (mid_ok) tier = 1;
       else tier = 2;
+      if (tier >= 0) {
+        for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
+          const ProdDev &d = P.prods[P.seg_prod[s]];
+          const int32_t t = P.seg_svec[s];
+          sent += d.s_ptr[t + 1] - d.s_ptr[t];
+        }
+      }
     }
     append(tier == 0, (int32_t)v, tiny, &counters[kCtTiny]);
     append(tier == 1, (int32_t)v, mid, &counters[kCtMid]);
     append(tier == 2, (int32_t)v, heavy, &counters[kCtHeavy]);
-  }
-}
-
-// Number of windows of each heavy vector (0 past the end), for the item scan.
-__global__ void k_heavy_nwin(Plan P, int64_t cap, int64_t *out) {
-  int64_t nh = P.counters[kCtHeavy];
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x)
-    out[q] = q < nh ? P.groups[P.ov_group[P.heavy_list[q]]].nwin : 0;
-}
-
-__global__ void k_heavy_items(Plan P, const int64_t *ibase, int64_t cap, int32_t *item_vec, int32_t *item_win,
-                              int64_t *counters) {
-  int64_t nh = counters[kCtHeavy];
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
-    int64_t b = ibase[q], e = ibase[q + 1];
-    for (int64_t i = b; i < e; ++i) {
-      item_vec[i] = (int32_t)q;
-      item_win[i] = (int32_t)(i - b);
+    if (tier >= 0) {
+      tf[tier] += f;
+      ts[tier] += sent;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCtItems] = ibase[cap];
+  for (int x = 0; x < 3; ++x) {
+    const int64_t a = wave_sum64(tf[x]);
+    const int64_t b = wave_sum64(ts[x]);
+    if (lane() == 0 && (a | b)) {
+      atomicAdd((unsigned long long *)&counters[kCtTierFlops + x], (unsigned long long)a);
+      atomicAdd((unsigned long long *)&counters[kCtTierSent + x], (unsigned long long)b);
+    }
+  }
 }
 
-// Window split points of every G vector: wsplit[t * (nwin + 1) + c] is the
-// offset inside G(:, t) of the first id >= c * win.
-__global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_nvec, int32_t nwin, int32_t win,
+// Output entries per tier.
+__global__ void k_tier_nnz(Plan P, int64_t *counters) {
+  const int64_t n[3] = {counters[kCtTiny], counters[kCtMid], counters[kCtHeavy]};
+  const int32_t *lists[3] = {P.tiny_list, P.mid_list, P.heavy_list};
+  for (int x = 0; x < 3; ++x) {
+    int64_t acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n[x]; i += (int64_t)gridDim.x * blockDim.x)
+      acc += P.ov_cnt[lists[x][i]];
+    acc = wave_sum64(acc);
+    if (lane() == 0 && acc) atomicAdd((unsigned long long *)&counters[kCtTierNnz + x], (unsigned long long)acc);
+  }
+}
+
+// Window split points of every G vector: wsplit[t * (nsplit + 1) + c] is
+// the offset inside G(:, t) of the first id >= c * sw.
+__global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_nvec, int32_t nsplit, int32_t sw,
                          int32_t *wsplit) {
-  int64_t n = g_nvec * (nwin + 1);
+  int64_t n = g_nvec * (nsplit + 1);
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    int64_t t = x / (nwin + 1);
-    int64_t c = x - t * (nwin + 1);
+    int64_t t = x / (nsplit + 1);
+    int64_t c = x - t * (nsplit + 1);
     int64_t a = g_ptr[t], b = g_ptr[t + 1];
     int64_t lo = a, hi = b;
-    int64_t key = c * (int64_t)win;
+    int64_t key = c * (int64_t)sw;
     while (lo < hi) {
       int64_t mid = lo + ((hi - lo) >> 1);
       if (g_idx[mid] < key) lo = mid + 1; else hi = mid;
@@ -353,18 +367,67 @@ __global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_n
   }
 }
 
-// Heavy vector totals from their window counts; item_off becomes the offset
-// of each window inside its vector's output.
-__global__ void k_heavy_totals(Plan P, const int64_t *ibase) {
-  int64_t nh = P.counters[kCtHeavy];
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
-    int64_t run = 0;
-    for (int64_t i = ibase[q]; i < ibase[q + 1]; ++i) {
-      P.item_off[i] = run;
-      run += P.item_cnt[i];
+// Heavy-tier windows of one vector from its bucket counts. Mode 0: one
+// window per non-empty bucket. Mode 1: consecutive buckets are merged while
+// the entries fit rank_cap and the span fits rank_wb buckets; empty buckets
+// between windows are skipped. Every bucket holds at most sw <= rank_cap
+// entries, so each window takes at least one bucket. `emit` receives
+// (b0, b1, entries before the window).
+template <class F>
+__device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t *bc, F emit) {
+  int64_t nwin = 0, before = 0;
+  int32_t b = 0;
+  const int32_t nb = G.nsplit;
+  while (b < nb) {
+    if (bc[b] == 0) {
+      ++b;
+      continue;
     }
-    P.ov_cnt[P.heavy_list[q]] = run;
+    const int32_t b0 = b;
+    int64_t sum = 0;
+    if (G.mode == 0) {
+      sum = bc[b];
+      ++b;
+    } else {
+      while (b < nb && (b - b0) < G.rank_wb && sum + bc[b] <= G.rank_cap) {
+        sum += bc[b];
+        ++b;
+      }
+    }
+    emit(b0, b, before);
+    before += sum;
+    ++nwin;
   }
+  return nwin;
+}
+
+__global__ void k_plan_count(Plan P, int64_t cap, int64_t *nwin_out) {
+  const int64_t nh = P.counters[kCtHeavy];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x) {
+    if (q >= nh) {
+      nwin_out[q] = 0;
+      continue;
+    }
+    const GroupDev &G = P.groups[P.ov_group[P.heavy_list[q]]];
+    nwin_out[q] = plan_windows(G, P.bcnt + q * (int64_t)P.nbmax, [](int32_t, int32_t, int64_t) {});
+  }
+}
+
+__global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, int32_t *item_vec, int32_t *item_b0,
+                            int32_t *item_b1, int64_t *item_off, int64_t *counters) {
+  const int64_t nh = counters[kCtHeavy];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
+    const GroupDev &G = P.groups[P.ov_group[P.heavy_list[q]]];
+    int64_t i = ibase[q];
+    plan_windows(G, P.bcnt + q * (int64_t)P.nbmax, [&](int32_t b0, int32_t b1, int64_t before) {
+      item_vec[i] = (int32_t)q;
+      item_b0[i] = b0;
+      item_b1[i] = b1;
+      item_off[i] = before;
+      ++i;
+    });
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCtItems] = ibase[cap];
 }
 
 // Per-group totals after the scans of counts (ov_off) and non-empty flags (nzpos).

@@ -12,11 +12,16 @@
 //          a prefix count per 32-bit word turns an id into its rank, so the
 //          values are accumulated densely and emitted already sorted), or
 //          an open-addressing LDS hash followed by an in-LDS bitonic sort;
-//   heavy  one workgroup per (vector, window): the output id range is cut
-//          into windows of `win` ids, and each window is accumulated in a
-//          dense LDS sparse accumulator (the SPA of Section 3.3, a flag bit
-//          and a value per id); the gathered operand is read in place
-//          through per-vector window split points.
+//   heavy  a count pass marks the vector's whole id range in an LDS bitmap
+//          and records the entries per split bucket (a fixed run of ids);
+//          windows of consecutive buckets are then planned so that each
+//          fits the LDS value capacity, and every window is one workgroup
+//          item of the bitmap-rank accumulator restricted to its ids. Where
+//          the id range is narrow enough for one dense window (or the
+//          bitmap would not fit), a window is instead a dense LDS sparse
+//          accumulator (the SPA of Section 3.3: a flag bit and a value per
+//          id). The gathered operand is read in place through per-vector
+//          split points at bucket boundaries.
 //
 // Every workgroup keeps its dynamic LDS at all-zero bits between items; the
 // semiring traits encode the additive identity as zero bits.
@@ -73,10 +78,10 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
 }
 
 // Load the lane's stored S entry e of product d and describe its products:
-// the whole G vector (win_c < 0) or only the part inside window win_c.
+// the whole G vector (b0 < 0) or only its ids in split buckets [b0, b1).
 template <class SR>
-__device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t e1, int win_c, int &len, int64_t &gb,
-                                           typename SR::T &sv) {
+__device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t e1, int b0, int b1, int &len,
+                                           int64_t &gb, typename SR::T &sv) {
   typedef typename SR::T T;
   len = 0;
   gb = 0;
@@ -86,10 +91,11 @@ __device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t 
   const int32_t gt = d.gres ? d.gres[e] : ((k >= 0 && k < d.g_nvec) ? k : -1);
   if (gt < 0) return;
   const int64_t p0 = d.g_ptr[gt];
-  if (win_c >= 0 && d.wsplit) {
-    const int32_t *ws = d.wsplit + (int64_t)gt * (d.nwin + 1) + win_c;
-    gb = p0 + ws[0];
-    len = ws[1] - ws[0];
+  if (b0 >= 0 && d.wsplit) {
+    const int32_t *ws = d.wsplit + (int64_t)gt * (d.nsplit + 1);
+    const int32_t w0 = ws[b0];
+    gb = p0 + w0;
+    len = ws[b1] - w0;
   } else {
     gb = p0;
     len = (int)(d.g_ptr[gt + 1] - p0);
@@ -97,11 +103,11 @@ __device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t 
   if (SR::kVal) sv = ((const T *)d.s_val)[e];
 }
 
-// All products of output vector v (restricted to window win_c if >= 0),
-// shared among the nw wavefronts of the caller (wave wid takes every nw-th
-// batch of 64 S entries, counted across the vector's segments).
+// All products of output vector v (restricted to split buckets [b0, b1) if
+// b0 >= 0), shared among the nw wavefronts of the caller (wave wid takes
+// every nw-th batch of 64 S entries, counted across the vector's segments).
 template <class SR, class Act>
-__device__ __forceinline__ void for_products(const Plan &P, int64_t v, int win_c, int wid, int nw, Act &act) {
+__device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, int b1, int wid, int nw, Act &act) {
   typedef typename SR::T T;
   const int64_t s0 = P.ov_seg[v], s1 = P.ov_seg[v + 1];
   int64_t gbatch = 0;
@@ -115,7 +121,7 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int win_c
       int len;
       int64_t gb;
       T sv;
-      load_entry<SR>(d, e0 + b * kWave + lane(), e1, win_c, len, gb, sv);
+      load_entry<SR>(d, e0 + b * kWave + lane(), e1, b0, b1, len, gb, sv);
       run_batch<SR>(len, gb, sv, d.g_idx, (const T *)d.g_val, act);
     }
     gbatch += nb;
@@ -145,7 +151,7 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
       int len;
       int64_t gb;
       T sv;
-      load_entry<SR>(d, eb + l, e1, -1, len, gb, sv);
+      load_entry<SR>(d, eb + l, e1, -1, -1, len, gb, sv);
       const int Pp = wave_incl_scan(len);
       const int tot = read_lane(Pp, kWave - 1);
       if (tot == 0) continue;
@@ -208,28 +214,38 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
 // LDS layout helpers (offsets in 32-bit words).
 __device__ __forceinline__ int64_t align2(int64_t w) { return (w + 1) & ~(int64_t)1; }
 
-// Mid tier, bitmap-rank accumulator over the whole output id range.
+// Bitmap-rank accumulator over output ids [lo, hi) of vector v: a bit per
+// id marks the pattern, a 16-bit prefix count per 32-bit word turns an id
+// into its rank, and the values are accumulated densely by rank, so the
+// entries come out sorted without a sort. b0 < 0 means the whole range
+// (mid tier); else only the products in split buckets [b0, b1) are taken.
+// COUNT writes the number of entries to ov_cnt[v]; the numeric variant
+// writes them at out_pos.
 template <int K, bool COUNT>
-__device__ void mid_bitmap_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+__device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
+                            uint32_t *lds, int64_t *scratch) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wid = tid / kWave, nw = nt / kWave;
-  const int64_t minor = P.groups[P.ov_group[v]].minor;
-  const int nw32 = (int)((minor + 31) >> 5);
+  const int nwds = (int)((hi - lo + 31) >> 5);
+  const int lo32 = (int)lo;
   uint32_t *bits = lds;
-  uint16_t *pre = (uint16_t *)(lds + nw32);
-  Slot *vals = (Slot *)(lds + align2(nw32 + ((nw32 + 1) >> 1)));
+  uint16_t *pre = (uint16_t *)(lds + nwds);
+  Slot *vals = (Slot *)(lds + align2(nwds + ((nwds + 1) >> 1)));
 
-  auto mark = [&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); };
-  for_products<SR>(P, v, -1, wid, nw, mark);
+  auto mark = [&](int id, T) {
+    const int r = id - lo32;
+    atomicOr(&bits[r >> 5], 1u << (r & 31));
+  };
+  for_products<SR>(P, v, b0, b1, wid, nw, mark);
   __syncthreads();
 
   // per-thread contiguous word range
-  const int per = (nw32 + nt - 1) / nt;
-  const int w0 = tid * per < nw32 ? tid * per : nw32;
-  const int w1 = w0 + per < nw32 ? w0 + per : nw32;
+  const int per = (nwds + nt - 1) / nt;
+  const int w0 = tid * per < nwds ? tid * per : nwds;
+  const int w1 = w0 + per < nwds ? w0 + per : nwds;
   int local = 0;
   for (int w = w0; w < w1; ++w) local += __popc(bits[w]);
   int64_t total;
@@ -241,15 +257,14 @@ __device__ void mid_bitmap_vector(const Plan &P, int64_t v, uint32_t *lds, int64
     return;
   }
   const OutDev &O = P.outs[P.ov_group[v]];
-  const int64_t base = out_offset(P, v);
   if (!SR::kVal) {
-    int64_t r = base + excl;
+    int64_t r = out_pos + excl;
     for (int w = w0; w < w1; ++w) {
       uint32_t b = bits[w];
       while (b) {
         const int bit = __ffs(b) - 1;
         b &= b - 1;
-        O.idx[r++] = (w << 5) + bit;
+        O.idx[r++] = lo32 + (w << 5) + bit;
       }
       bits[w] = 0;
     }
@@ -265,22 +280,23 @@ __device__ void mid_bitmap_vector(const Plan &P, int64_t v, uint32_t *lds, int64
   }
   __syncthreads();
   auto accum = [&](int id, T x) {
-    const int w = id >> 5;
-    const int r = pre[w] + __popc(bits[w] & ((1u << (id & 31)) - 1u));
-    SR::acc(&vals[r], x);
+    const int r = id - lo32;
+    const int w = r >> 5;
+    const int rk = pre[w] + __popc(bits[w] & ((1u << (r & 31)) - 1u));
+    SR::acc(&vals[rk], x);
   };
-  for_products<SR>(P, v, -1, wid, nw, accum);
+  for_products<SR>(P, v, b0, b1, wid, nw, accum);
   __syncthreads();
   // emit: lane-interleaved words, so a wavefront writes one contiguous run
-  for (int w = tid; w < nw32; w += nt) {
+  for (int w = tid; w < nwds; w += nt) {
     uint32_t b = bits[w];
     if (b) {
       int r = pre[w];
       while (b) {
         const int bit = __ffs(b) - 1;
         b &= b - 1;
-        O.idx[base + r] = (w << 5) + bit;
-        ((T *)O.val)[base + r] = SR::dec(vals[r]);
+        O.idx[out_pos + r] = lo32 + (w << 5) + bit;
+        ((T *)O.val)[out_pos + r] = SR::dec(vals[r]);
         vals[r] = Slot();
         ++r;
       }
@@ -323,7 +339,7 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
     }
     if (!COUNT) SR::acc(&vals[h], x);
   };
-  for_products<SR>(P, v, -1, wid, nw, ins);
+  for_products<SR>(P, v, -1, -1, wid, nw, ins);
   __syncthreads();
   if (COUNT) {
     int64_t local = 0;
@@ -375,22 +391,17 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Heavy tier: dense LDS accumulator over one window of `win` output ids.
+// Heavy tier, dense LDS accumulator (flag bit + value per id) over the ids
+// [lo, hi) of split bucket c. COUNT returns the number of entries.
 template <int K, bool COUNT>
-__device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
+__device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int64_t hi, int64_t out_pos,
+                                uint32_t *lds, int64_t *scratch, int wcap) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wid = tid / kWave, nw = nt / kWave;
-  const int32_t q = P.item_vec[it];
-  const int32_t c = P.item_win[it];
-  const int64_t v = P.heavy_list[q];
-  const int64_t minor = P.groups[P.ov_group[v]].minor;
-  const int64_t lo = (int64_t)c * P.win;
-  const int width = (int)((minor - lo) < P.win ? (minor - lo) : P.win);
-  const int nwf = (width + 31) >> 5;
-  const int wcap = (P.win + 31) >> 5;
+  const int nwf = (int)((hi - lo + 31) >> 5);
   uint32_t *flags = lds;
   Slot *vals = (Slot *)(lds + align2(wcap));
   const int lo32 = (int)lo;
@@ -400,7 +411,7 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
     atomicOr(&flags[r >> 5], 1u << (r & 31));
     if (!COUNT) SR::acc(&vals[r], x);
   };
-  for_products<SR>(P, v, c, wid, nw, acc);
+  for_products<SR>(P, v, c, c + 1, wid, nw, acc);
   __syncthreads();
 
   const int per = (nwf + nt - 1) / nt;
@@ -412,12 +423,11 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
   const int64_t excl = block_excl_scan(local, scratch, &total);
   if (COUNT) {
     for (int w = w0; w < w1; ++w) flags[w] = 0;
-    if (tid == 0) P.item_cnt[it] = (int32_t)total;
     __syncthreads();
-    return;
+    return total;
   }
   const OutDev &O = P.outs[P.ov_group[v]];
-  int64_t r = out_offset(P, v) + P.item_off[it] + excl;
+  int64_t r = out_pos + excl;
   for (int w = w0; w < w1; ++w) {
     uint32_t b = flags[w];
     while (b) {
@@ -434,6 +444,73 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
     flags[w] = 0;
   }
   __syncthreads();
+  return total;
+}
+
+// Count pass of one heavy vector: entries per split bucket (P.bcnt) and in
+// total (ov_cnt). Mode 1 marks the whole id range once in an LDS bitmap;
+// mode 0 counts bucket by bucket with the dense window.
+template <int K>
+__device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *scratch) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t v = P.heavy_list[q];
+  const GroupDev &G = P.groups[P.ov_group[v]];
+  int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
+  if (G.mode == 0) {
+    int64_t total = 0;
+    for (int c = 0; c < G.nsplit; ++c) {
+      const int64_t lo = (int64_t)c * G.sw;
+      const int64_t hi = lo + G.sw < G.minor ? lo + G.sw : G.minor;
+      const int64_t n = dense_window<K, true>(P, v, c, lo, hi, 0, lds, scratch, (G.sw + 31) >> 5);
+      if (tid == 0) bc[c] = (int32_t)n;
+      total += n;
+    }
+    if (tid == 0) P.ov_cnt[v] = total;
+    // every item ends on a barrier after its thread-0 stores: without it the
+    // compiler may let the other lanes re-enter the queue loop on their own
+    __syncthreads();
+    return;
+  }
+  const int wid = tid / kWave, nw = nt / kWave;
+  const int nwds = (int)((G.minor + 31) >> 5);
+  uint32_t *bits = lds;
+  int32_t *lbc = (int32_t *)(lds + nwds);
+  auto mark = [&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); };
+  for_products<SR>(P, v, -1, -1, wid, nw, mark);
+  __syncthreads();
+  const int wpb = G.sw >> 5;  // words per bucket
+  int64_t local = 0;
+  for (int w = tid; w < nwds; w += nt) {
+    const int c = __popc(bits[w]);
+    if (c) {
+      atomicAdd(&lbc[w / wpb], c);
+      local += c;
+      bits[w] = 0;
+    }
+  }
+  const int64_t total = block_sum(local, scratch);
+  for (int b = tid; b < G.nsplit; b += nt) {
+    bc[b] = lbc[b];
+    lbc[b] = 0;
+  }
+  if (tid == 0) P.ov_cnt[v] = total;
+  __syncthreads();
+}
+
+// Numeric pass of one planned heavy window.
+template <int K>
+__device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
+  const int32_t q = P.item_vec[it];
+  const int32_t b0 = P.item_b0[it], b1 = P.item_b1[it];
+  const int64_t v = P.heavy_list[q];
+  const GroupDev &G = P.groups[P.ov_group[v]];
+  const int64_t lo = (int64_t)b0 * G.sw;
+  const int64_t hi = (int64_t)b1 * G.sw < G.minor ? (int64_t)b1 * G.sw : G.minor;
+  const int64_t pos = out_offset(P, v) + P.item_off[it];
+  if (G.mode == 0) dense_window<K, false>(P, v, b0, lo, hi, pos, lds, scratch, (G.sw + 31) >> 5);
+  else rank_window<K, false>(P, v, lo, hi, b0, b1, pos, lds, scratch);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,8 +543,9 @@ __global__ void __launch_bounds__(1024) k_mid(Plan P, int64_t *queue) {
     const int64_t i = s_item;
     __syncthreads();
     if (i >= n) break;
-    if (P.mid_kind == 0) mid_bitmap_vector<K, COUNT>(P, P.mid_list[i], lds, scratch);
-    else mid_hash_vector<K, COUNT>(P, P.mid_list[i], lds, scratch);
+    const int64_t v = P.mid_list[i];
+    if (P.mid_kind == 0) rank_window<K, COUNT>(P, v, 0, P.groups[P.ov_group[v]].minor, -1, -1, COUNT ? 0 : out_offset(P, v), lds, scratch);
+    else mid_hash_vector<K, COUNT>(P, v, lds, scratch);
   }
 }
 
@@ -477,14 +555,15 @@ __global__ void __launch_bounds__(1024) k_heavy(Plan P, int64_t *queue) {
   __shared__ int64_t scratch[kMaxWaves + 1];
   __shared__ int64_t s_item;
   zero_lds(lds, P.lds_words);
-  const int64_t n = P.counters[kCtItems];
+  const int64_t n = COUNT ? P.counters[kCtHeavy] : P.counters[kCtItems];
   while (true) {
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
     __syncthreads();
     const int64_t i = s_item;
     __syncthreads();
     if (i >= n) break;
-    heavy_item<K, COUNT>(P, i, lds, scratch);
+    if (COUNT) heavy_count<K>(P, i, lds, scratch);
+    else heavy_item<K>(P, i, lds, scratch);
   }
 }
 
@@ -507,10 +586,10 @@ __global__ void __launch_bounds__(1024) k_batched(Plan P, int64_t *queue, int64_
     __syncthreads();
     if (i >= total) break;
     if (i < n_items) {
-      heavy_item<K, false>(P, i, lds, scratch);
+      heavy_item<K>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
       const int64_t v = P.mid_list[i - n_items];
-      if (P.mid_kind == 0) mid_bitmap_vector<K, false>(P, v, lds, scratch);
+      if (P.mid_kind == 0) rank_window<K, false>(P, v, 0, P.groups[P.ov_group[v]].minor, -1, -1, out_offset(P, v), lds, scratch);
       else mid_hash_vector<K, false>(P, v, lds, scratch);
     } else {
       const int64_t t = (i - n_items - n_mid) * nw + threadIdx.x / kWave;

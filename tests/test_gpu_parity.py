@@ -87,14 +87,16 @@ def test_rmat_s10_default_tiers(sg, semiring, batched):
 
 
 @pytest.mark.parametrize("semiring", SEMIRINGS)
-@pytest.mark.parametrize("force,mid_kind", [(0, 0), (1, 0), (1, 1), (2, 0)])
-def test_forced_tiers_several_windows(sg, semiring, force, mid_kind):
-    """Every tier on every vector it can take, with heavy windows that leave a ragged tail."""
-    _say(f"case forced tier {force} mid_kind {mid_kind} {semiring}")
+@pytest.mark.parametrize("force,mid_kind,heavy_kind", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (2, 0, 0), (2, 0, 1),
+                                                       (-1, 0, 0), (-1, 1, 1)])
+def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind):
+    """Every tier on every vector it can take. 16 KB of LDS: rank windows hold 1024 (f64)
+    or 2048 (4-byte values) entries over 1K/2K-id buckets, so heavy rows split into several
+    planned windows; dense windows are ~2K ids wide over 8192 columns (the last partial)."""
+    _say(f"case forced tier {force} mid_kind {mid_kind} heavy_kind {heavy_kind} {semiring}")
     A = W.rmat_matrix(13, 8, semiring, "csr", seed=4)
-    # 16 KB of LDS: windows of ~2K ids over 8192 columns (five windows, the last partial)
-    C, info = gpu_product(sg, semiring, A, A, force_tier=force, mid_kind=mid_kind, lds_bytes=16384,
-                          block_threads=256)
+    C, info = gpu_product(sg, semiring, A, A, force_tier=force, mid_kind=mid_kind, heavy_kind=heavy_kind,
+                          lds_bytes=16384, block_threads=256)
     check(semiring, C, A, A, f"force{force}")
     if force == 2:
         assert info["n_mid"] == 0 and info["n_tiny"] == 0

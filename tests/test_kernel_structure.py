@@ -1,0 +1,60 @@
+"""Structure of the compiled queue loops (CPU only: compiles the library to gfx950 assembly).
+
+Every mid/heavy/batched kernel pulls work items with one atomic on a device
+counter, done by thread 0, followed by two workgroup barriers that publish
+the item to all threads. The item's work must end convergent. If a lane-0-
+only store ends an item with no barrier after it, the compiler can turn the
+queue loop into a nested loop whose back edge skips the atomic for every
+lane but thread 0's. Those lanes then re-read the old item forever (a GPU
+hang). This test checks the assembly: the atomic sits in the kernel's
+outermost loop and no other loop header lies between it and its two
+barriers.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "paper_1006_2183_amd", "csrc", "sg_spgemm.hip")
+
+
+def _asm(tmp_path):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = os.path.join(tmp_path, "sg.s")
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                           "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics", "-I" + os.path.join(ROOT, "include"),
+                           "--cuda-device-only", "-S", "-o", out, SRC],
+                          stderr=subprocess.DEVNULL)
+    with open(out) as f:
+        return f.read()
+
+
+def queue_loop_report(asm: str):
+    rows = []
+    for m in re.finditer(r"^(_ZN2sg(?:5k_mid|7k_heavy|9k_batched)\S*):.*?s_endpgm", asm, re.S | re.M):
+        name, body = m.group(1), m.group(0)
+        lines = body.split("\n")
+        atom = [i for i, l in enumerate(lines) if "global_atomic_add_x2" in l]
+        if not atom:
+            rows.append((name, False, "no queue atomic"))
+            continue
+        a = atom[0]
+        headers = [l for l in lines[:a] if "Loop Header: Depth=" in l]
+        depth = re.search(r"Depth=(\d+)", headers[-1]).group(1) if headers else None
+        bars = [i for i in range(a, len(lines)) if "s_barrier" in lines[i]][:2]
+        between = [l for l in lines[a:bars[-1]] if "Loop Header" in l] if len(bars) == 2 else ["?"]
+        ok = depth == "1" and len(bars) == 2 and not between
+        rows.append((name, ok, f"atomic at loop depth {depth}, loop headers before its barriers: {len(between)}"))
+    return rows
+
+
+def test_queue_loops_stay_convergent(tmp_path):
+    rows = queue_loop_report(_asm(str(tmp_path)))
+    assert len(rows) == 20, f"expected 20 queue kernels, found {len(rows)}"
+    bad = [r for r in rows if not r[1]]
+    assert not bad, "queue loop restructured: " + "; ".join(f"{n}: {why}" for n, _, why in bad)
