@@ -124,6 +124,17 @@ typedef struct {
  *                    (tiny needs flops <= 64, mid needs the bound to fit)
  *   blocks_per_cu    workgroups per compute unit of the persistent launches
  *   validate         non-zero: run sg_validate on every operand first
+ *   xcd_ranges       heavy tier: the output id range is cut into 8 x this
+ *                    many consecutive ranges, no heavy window crosses a range,
+ *                    and the numeric launch keeps one work queue per XCD (the
+ *                    chip's 8 dies, each with its own L2) holding the windows
+ *                    of that XCD's ranges, so each L2 caches a slice of the
+ *                    gathered operand; workgroups drain their own XCD's queue
+ *                    first and then help the others (0 = one shared queue)
+ *   bitmap_mb        heavy tier: MiB of workspace in which the count pass
+ *                    keeps each heavy vector's id bitmap, so that numeric
+ *                    windows load their slice instead of re-marking it
+ *                    (vectors beyond the budget re-mark; 0 = never keep)
  */
 typedef struct {
     int32_t tiny_max_flops;
@@ -136,6 +147,8 @@ typedef struct {
     int32_t force_tier;
     int32_t blocks_per_cu;
     int32_t validate;
+    int32_t xcd_ranges;
+    int32_t bitmap_mb;
 } sg_tuning;
 
 /* Host-side sizes of one output, valid when sg_spgemm_symbolic returns. */
@@ -163,6 +176,13 @@ void sg_tuning_default(int32_t semiring_kind, sg_tuning *tuning);
 
 /* Static text for a status code. */
 const char *sg_status_string(int32_t status);
+
+/*
+ * Text describing the last HIP runtime failure seen by this host thread
+ * (the call, HIP's error string and the source line), or "" if none.
+ * The pointer stays valid until the thread's next failing call.
+ */
+const char *sg_last_error(void);
 
 /*
  * Device workspace needed by sg_spgemm_symbolic for the same arguments.

@@ -22,14 +22,17 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID_ARG", -2: "SG_ERR_DIM_MISMATCH", -3: "
           -4: "SG_ERR_UNSUPPORTED", -5: "SG_ERR_WORKSPACE", -6: "SG_ERR_CAPACITY", -7: "SG_ERR_HIP",
           -8: "SG_ERR_OOM"}
 
-EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
+EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
            "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
            "sg_validate", "sg_build_aux"]
 
 
 class SgError(RuntimeError):
-    def __init__(self, status: int, where: str):
-        super().__init__(f"{where}: {STATUS.get(status, status)}")
+    def __init__(self, status: int, where: str, detail: str = ""):
+        msg = f"{where}: {STATUS.get(status, status)}"
+        if detail:
+            msg += f" [{detail}]"
+        super().__init__(msg)
         self.status = status
 
 
@@ -53,7 +56,8 @@ class sg_tuning(ctypes.Structure):
     _fields_ = [("tiny_max_flops", ctypes.c_int32), ("mid_max_ub", ctypes.c_int32), ("mid_kind", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("chunk_width", ctypes.c_int32),
                 ("heavy_kind", ctypes.c_int32), ("force_tier", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("validate", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("xcd_ranges", ctypes.c_int32),
+                ("bitmap_mb", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -80,6 +84,9 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # whichever is loaded first serves the whole process, so load torch's first
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is missing; build it with `python -c 'import __graft_entry__ as g; g.build()'`")
     lib = ctypes.CDLL(path)
@@ -88,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.sg_tuning_default.argtypes = [ctypes.c_int32, P(sg_tuning)]
     lib.sg_status_string.restype = ctypes.c_char_p
     lib.sg_status_string.argtypes = [ctypes.c_int32]
+    lib.sg_last_error.restype = ctypes.c_char_p
+    lib.sg_last_error.argtypes = []
     lib.sg_spgemm_workspace_size.restype = ctypes.c_int
     lib.sg_spgemm_workspace_size.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), ctypes.c_void_p,
                                              ctypes.c_int32, ctypes.c_int32, P(sg_tuning), P(ctypes.c_size_t)]
@@ -115,7 +124,10 @@ def load_library(path: str = LIB_PATH):
 
 def _check(status: int, where: str):
     if status != 0:
-        raise SgError(status, where)
+        detail = ""
+        if status == -7 and _lib is not None:
+            detail = (_lib.sg_last_error() or b"").decode(errors="replace")
+        raise SgError(status, where, detail)
 
 
 def _torch():

@@ -20,7 +20,13 @@
 namespace sg {
 
 constexpr int kWave = 64;
+constexpr int kXcds = 8;           // dies of an MI355X, each with its own L2
 constexpr int kMaxWaves = 16;  // 1024 threads per workgroup at most
+constexpr int kBlockMax = 512;     // threads per workgroup of the mid/heavy/batched kernels
+#ifndef SG_WAVES_PER_SIMD
+#define SG_WAVES_PER_SIMD 4
+#endif
+constexpr int kWavesPerSimd = SG_WAVES_PER_SIMD;  // occupancy the register budget is sized for
 
 // One product A_p (x) B_p, in S/G terms, as the kernels see it.
 struct ProdDev {
@@ -54,6 +60,8 @@ struct GroupDev {
   int32_t mid_ok;        // largest mid-tier vector of this group (0: the mid tier does not fit)
   int32_t rank_cap;      // mode 1: most entries one window may hold
   int32_t rank_wb;       // mode 1: most buckets one window may span
+  int32_t bpr;           // split buckets per XCD range (windows never cross a range)
+  int32_t pad;
   int64_t ov_begin;      // first output vector of this group (device-filled)
   int64_t ov_end;
   int64_t nnz_base;      // global exclusive offset of the group's first entry
@@ -124,6 +132,12 @@ struct Plan {
   const int64_t *item_off;   // heavy item -> offset of its entries inside its vector
   int32_t *bcnt;             // heavy vector q: entries per split bucket, at q * nbmax
   int32_t nbmax;             // largest nsplit of any group
+  int32_t nrange;            // XCD ranges (8 per XCD share, or 1 when ranges are off)
+  const int64_t *ibase;      // exclusive offsets of the heavy items by (range, vector)
+  int64_t ibase_stride;      // entries per range in ibase
+  uint32_t *hbits;           // kept id bitmaps of the first nkeep heavy vectors
+  int64_t hstride;           // 32-bit words per kept bitmap
+  int64_t nkeep;
   int32_t mid_cap;           // max entries of a mid-tier vector
   int32_t mid_kind;          // 0 bitmap-rank, 1 hash
   int32_t lds_words;         // dynamic LDS size in 32-bit words
@@ -196,6 +210,20 @@ struct Sr<SG_OR_AND_BOOL> {
   __device__ static T dec(Slot v) { return v; }
   __device__ static void acc(Slot *, T) {}
 };
+
+// ---------------------------------------------------------------------------
+// Global-memory access through explicitly global pointers: pointers read out
+// of descriptor structs are otherwise generic, and generic (flat) accesses
+// share the LDS wait counter, so every LDS wait would also drain the loads.
+#define SG_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gload(const T *p) {
+  return *(const SG_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T *p, T v) {
+  *(SG_GLOBAL T *)p = v;
+}
 
 // ---------------------------------------------------------------------------
 // Wavefront helpers (wave64).
@@ -306,12 +334,13 @@ __device__ __forceinline__ int64_t block_sum(int64_t x, int64_t *scratch) {
 __device__ __forceinline__ int32_t aux_find(const ProdDev &d, int64_t k) {
   if (k < 0 || k >= d.g_major) return -1;
   int64_t c = k / d.aux_chunk;
-  int32_t lo = d.aux[c], hi = d.aux[c + 1];
+  int32_t lo = gload(d.aux + c), hi = gload(d.aux + c + 1);
+  const int32_t end = hi;
   while (lo < hi) {
     int32_t mid = lo + ((hi - lo) >> 1);
-    if (d.g_vid[mid] < k) lo = mid + 1; else hi = mid;
+    if (gload(d.g_vid + mid) < k) lo = mid + 1; else hi = mid;
   }
-  return (lo < d.aux[c + 1] && d.g_vid[lo] == k) ? lo : -1;
+  return (lo < end && gload(d.g_vid + lo) == k) ? lo : -1;
 }
 
 }  // namespace sg

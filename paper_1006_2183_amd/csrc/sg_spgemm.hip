@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -17,10 +18,19 @@ using namespace sg;
 
 namespace {
 
-#define SG_HIP(call)                          \
-  do {                                        \
-    hipError_t e_ = (call);                   \
-    if (e_ != hipSuccess) return SG_ERR_HIP;  \
+// Text of the last failing HIP call (per host thread), for sg_last_error.
+thread_local char g_last_error[256] = "";
+
+sg_status hip_fail(hipError_t e, const char *what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (HIP error %d: %s) at sg_spgemm.hip:%d", what, (int)e,
+           hipGetErrorString(e), line);
+  return SG_ERR_HIP;
+}
+
+#define SG_HIP(call)                                                 \
+  do {                                                               \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #call, __LINE__);      \
   } while (0)
 
 #define SG_TRY(call)                \
@@ -85,8 +95,9 @@ int64_t mid_capacity(const sg_tuning &t, int32_t kind, int64_t minor) {
   const int sb = slot_bytes(kind);
   int64_t cap;
   if (t.mid_kind == 0) {
+    // bitmap-rank: one {bits, prefix} pair of 32-bit words per 32 ids (bits only without values)
     int64_t nw32 = (minor + 31) / 32;
-    int64_t words = sb ? ((nw32 + (nw32 + 1) / 2 + 1) & ~1ll) : nw32;
+    int64_t words = sb ? 2 * nw32 : nw32;
     int64_t left = (int64_t)t.lds_bytes - 4 * words;
     if (left < 0) return 0;
     if (sb == 0) return minor;  // the bitmap alone is the accumulator
@@ -103,7 +114,7 @@ int64_t mid_capacity(const sg_tuning &t, int32_t kind, int64_t minor) {
 
 // Heavy-tier geometry of one output id range (see GroupDev).
 struct Geom {
-  int32_t nsplit = 1, sw = 32, mode = 0, rank_cap = 0, rank_wb = 0;
+  int32_t nsplit = 1, sw = 32, mode = 0, rank_cap = 0, rank_wb = 0, bpr = 1;
 };
 
 Geom group_geom(const sg_tuning &t, int32_t kind, int64_t minor, int win_dense) {
@@ -128,8 +139,7 @@ Geom group_geom(const sg_tuning &t, int32_t kind, int64_t minor, int win_dense) 
       int64_t wb = 0;
       while (wb < nb) {
         const int64_t nwds = (wb + 1) * sw / 32;
-        const int64_t words = (nwds + (nwds + 1) / 2 + 1) & ~1ll;
-        if (4 * words + cap * sb > L) break;
+        if (8 * nwds + cap * sb > L) break;  // {bits, prefix} per 32 ids, then the values
         ++wb;
       }
       if (count_fits && wb >= 1 && nb < INT32_MAX) {
@@ -159,6 +169,7 @@ struct sg_plan {
   int win = 0;
   int ncu = 0;
   bool dense_path = false;
+  bool has_mode[2] = {false, false};  // heavy window kinds used by the groups
   int64_t nov_max = 0;
   int64_t items_max = 0;
   int64_t ndense_ptr = 0;
@@ -201,6 +212,7 @@ struct Layout {
   int64_t *dbase, *dcnt, *dflag, *vpos, *spos, *dfill;
   int64_t *pbase;
   int64_t *part;
+  uint32_t *hbits;
   size_t bytes;
 };
 
@@ -209,6 +221,9 @@ struct Shape {
   int64_t ndense = 0;        // sum of output major dims (multi-product groups)
   int64_t ndense_ptr = 0;    // sum of (major + 1) for dense output pointers
   int32_t nbmax = 1;
+  int32_t nrange = 1;      // XCD ranges of the heavy windows
+  int64_t hstride = 0;     // words of a kept heavy bitmap (widest rank-mode group)
+  int64_t nkeep = 0;       // heavy vectors whose bitmaps the workspace can keep
   bool dense_path = false;
   std::vector<Geom> geom;  // per group
   std::vector<int64_t> minor, major;
@@ -289,11 +304,20 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
   sh.nbmax = 1;
   sh.ndense = 0;
   sh.ndense_ptr = 0;
+  sh.nrange = t.xcd_ranges > 0 ? kXcds * t.xcd_ranges : 1;
   for (int32_t g = 0; g < ngroup; ++g) {
     sh.geom[g] = group_geom(t, kind, sh.minor[g], win);
+    Geom &ge = sh.geom[g];
+    ge.bpr = (ge.nsplit + sh.nrange - 1) / sh.nrange;
     sh.nbmax = std::max<int32_t>(sh.nbmax, sh.geom[g].nsplit);
     sh.ndense += sh.major[g];
     sh.ndense_ptr += sh.major[g] + 1;
+  }
+  for (int32_t g = 0; g < ngroup; ++g)
+    if (sh.geom[g].mode == 1) sh.hstride = std::max<int64_t>(sh.hstride, (sh.minor[g] + 31) / 32);
+  if (sh.hstride > 0 && t.bitmap_mb > 0) {
+    const int64_t budget = (int64_t)t.bitmap_mb << 20;
+    sh.nkeep = std::min<int64_t>(sh.nov_max, budget / (4 * sh.hstride));
   }
   // products whose gathered operand is the same arrays share the AUX index,
   // and the split table too when their groups split ids the same way
@@ -321,7 +345,7 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.groups = c.take<GroupDev>(ngroup);
   L.outs = c.take<OutDev>(ngroup);
   L.vbase = c.take<int64_t>(nprod + 1);
-  L.counters = c.take<int64_t>(kCtNum + 8);
+  L.counters = c.take<int64_t>(kCtNum + 24);
   L.gstat = c.take<int64_t>((int64_t)ngroup * kStCount);
   L.ov_id = c.take<int32_t>(nov);
   L.ov_group = c.take<int32_t>(nov);
@@ -336,8 +360,8 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.tiny = c.take<int32_t>(nov);
   L.mid = c.take<int32_t>(nov);
   L.heavy = c.take<int32_t>(nov);
-  L.heavy_nwin = c.take<int64_t>(nov + 1);
-  L.ibase = c.take<int64_t>(nov + 1);
+  L.heavy_nwin = c.take<int64_t>(nov * sh.nrange + 1);
+  L.ibase = c.take<int64_t>(nov * sh.nrange + 1);
   const int64_t items = nov * (int64_t)sh.nbmax;
   L.item_vec = c.take<int32_t>(items);
   L.item_b0 = c.take<int32_t>(items);
@@ -369,7 +393,7 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
       else L.wsplit[p] = c.take<int32_t>(G.nvec * (int64_t)(nb + 1));
     }
   }
-  int64_t scan_max = std::max<int64_t>(nov + 1, sh.ndense + 1);
+  int64_t scan_max = std::max<int64_t>(nov * sh.nrange + 1, sh.ndense + 1);
   L.dbase = c.take<int64_t>(ngroup + 1);
   if (sh.dense_path) {
     L.dcnt = c.take<int64_t>(sh.ndense + 1);
@@ -382,6 +406,7 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   }
   L.pbase = c.take<int64_t>(ngroup + 1);
   L.part = c.take<int64_t>(scan_max / kScanTile + 4);
+  L.hbits = sh.nkeep > 0 ? c.take<uint32_t>(sh.nkeep * sh.hstride) : nullptr;
   L.bytes = c.off + 256;
   return L;
 }
@@ -417,22 +442,29 @@ void normalise(sg_tuning &t, int32_t kind) {
   if (t.tiny_max_flops < 0 || t.tiny_max_flops > 64) t.tiny_max_flops = d.tiny_max_flops;
   if (t.mid_max_ub < 0) t.mid_max_ub = d.mid_max_ub;
   if (t.mid_kind != 0 && t.mid_kind != 1) t.mid_kind = 0;
-  if (t.lds_bytes < 4096 || t.lds_bytes > 160 * 1024) t.lds_bytes = d.lds_bytes;
+  // the kernels' static LDS (scan scratch, per-wave owner maps) takes the rest of the 160 KB
+  if (t.lds_bytes < 4096 || t.lds_bytes > 160 * 1024 - 2048) t.lds_bytes = d.lds_bytes;
   t.lds_bytes &= ~7;
-  if (t.block_threads < 64 || t.block_threads > 1024 || t.block_threads % 64) t.block_threads = d.block_threads;
+  if (t.block_threads < 64 || t.block_threads > kBlockMax || t.block_threads % 64) t.block_threads = d.block_threads;
   if (t.chunk_width < 0) t.chunk_width = 0;
   if (t.heavy_kind != 0 && t.heavy_kind != 1) t.heavy_kind = 0;
   if (t.force_tier < -1 || t.force_tier > 2) t.force_tier = -1;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) t.blocks_per_cu = d.blocks_per_cu;
+  if (t.xcd_ranges < 0 || t.xcd_ranges > 16) t.xcd_ranges = d.xcd_ranges;
+  if (t.bitmap_mb < 0) t.bitmap_mb = d.bitmap_mb;
 }
 
 template <int K>
 sg_status set_lds_attr(int bytes) {
   SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, true, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   return SG_OK;
 }
 
@@ -447,8 +479,14 @@ sg_status launch_counts(sg_plan *pl, hipStream_t st) {
   SG_HIP(hipGetLastError());
   hipLaunchKernelGGL((k_mid<K, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 0);
   SG_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_heavy<K, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 1);
-  SG_HIP(hipGetLastError());
+  for (int m = 0; m < 2; ++m) {
+    if (!pl->has_mode[m]) continue;
+    if (m == 0)
+      hipLaunchKernelGGL((k_heavy<K, true, 0>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 1);
+    else
+      hipLaunchKernelGGL((k_heavy<K, true, 1>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 4);
+    SG_HIP(hipGetLastError());
+  }
   return SG_OK;
 }
 
@@ -466,11 +504,15 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
   const int lds = pl->tune.lds_bytes;
   const sg_sym_info &I = pl->info[0];
   const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
-  SG_TRY(fill64(pl->counters + kCtNum + 2, 2, 0, st));
+  SG_TRY(fill64(pl->counters + kCtNum + 2, 22, 0, st));
   if (I.n_heavy_items > 0) {
     SG_TRY(mark(pl, 0, false, st));
-    hipLaunchKernelGGL((k_heavy<K, false>), dim3((unsigned)std::min<int64_t>(persist, I.n_heavy_items)), dim3(nt), lds, st,
-                       P, pl->counters + kCtNum + 2);
+    // a multiple of the XCD count so every die gets the same number of workgroups
+    const unsigned hg = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(persist, I.n_heavy_items) / kXcds * kXcds);
+    if (pl->has_mode[0])
+      hipLaunchKernelGGL((k_heavy<K, false, 0>), dim3(hg), dim3(nt), lds, st, P, pl->counters + kCtNum + 8);
+    if (pl->has_mode[1])
+      hipLaunchKernelGGL((k_heavy<K, false, 1>), dim3(hg), dim3(nt), lds, st, P, pl->counters + kCtNum + 16);
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 0, true, st));
   }
@@ -500,8 +542,16 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
   SG_TRY(mark(pl, 0, false, st));
-  hipLaunchKernelGGL((k_batched<K>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
-                     (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+  const int mode = pl->has_mode[0] && pl->has_mode[1] ? 2 : (pl->has_mode[1] ? 1 : 0);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_batched<K, 0>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
+                       (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_batched<K, 1>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
+                       (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+  else
+    hipLaunchKernelGGL((k_batched<K, 2>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
+                       (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
   SG_HIP(hipGetLastError());
   SG_TRY(mark(pl, 0, true, st));
   return SG_OK;
@@ -585,14 +635,18 @@ void sg_tuning_default(int32_t kind, sg_tuning *t) {
   t->tiny_max_flops = 64;
   t->mid_max_ub = 65535;
   t->mid_kind = 0;
-  t->lds_bytes = (kind == SG_OR_AND_BOOL) ? 72 * 1024 : 64 * 1024;
+  t->lds_bytes = 77 * 1024;
   t->block_threads = 512;
   t->chunk_width = 0;
   t->heavy_kind = 0;
   t->force_tier = -1;
   t->blocks_per_cu = 2;
   t->validate = 0;
+  t->xcd_ranges = 0;
+  t->bitmap_mb = 4096;
 }
+
+const char *sg_last_error(void) { return g_last_error; }
 
 const char *sg_status_string(int32_t s) {
   switch (s) {
@@ -673,6 +727,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   pl->ndense_ptr = sh.ndense_ptr;
   pl->out_minor = sh.minor;
   pl->out_major = sh.major;
+  for (int32_t g = 0; g < ngroup; ++g) pl->has_mode[sh.geom[g].mode] = true;
   pl->info.assign(ngroup, sg_sym_info{});
   SG_HIP(hipHostMalloc((void **)&pl->outs_host, sizeof(OutDev) * ngroup, hipHostMallocDefault));
   SG_HIP(hipHostMalloc((void **)&pl->host_stats, sizeof(int64_t) * ((size_t)ngroup * kStCount + kCtNum),
@@ -721,6 +776,8 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     G.mode = ge.mode;
     G.rank_cap = ge.rank_cap;
     G.rank_wb = ge.rank_wb;
+    G.bpr = ge.bpr;
+    G.pad = 0;
     const int64_t cap = mid_capacity(t, sr->kind, G.minor);
     G.mid_ok = cap > 0 ? (int32_t)std::min<int64_t>(cap, INT32_MAX) : 0;
     G.ov_begin = G.ov_end = G.nnz_base = G.nz_base = 0;
@@ -732,7 +789,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   SG_HIP(hipMemcpyAsync(L.vbase, vbase.data(), sizeof(int64_t) * (nprod + 1), hipMemcpyHostToDevice, st));
   SG_HIP(hipMemcpyAsync(L.dbase, dbase.data(), sizeof(int64_t) * (ngroup + 1), hipMemcpyHostToDevice, st));
   SG_HIP(hipMemcpyAsync(L.pbase, pbase.data(), sizeof(int64_t) * (ngroup + 1), hipMemcpyHostToDevice, st));
-  SG_TRY(fill64(L.counters, kCtNum + 8, 0, st));
+  SG_TRY(fill64(L.counters, kCtNum + 24, 0, st));
   SG_TRY(fill64(L.gstat, (int64_t)ngroup * kStCount, 0, st));
   SG_TRY(fill64(L.ov_cnt, sh.nov_max + 1, 0, st));
   SG_TRY(fill64(L.ov_flops, sh.nov_max, 0, st));
@@ -812,6 +869,12 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   P.item_off = L.item_off;
   P.bcnt = L.bcnt;
   P.nbmax = sh.nbmax;
+  P.nrange = sh.nrange;
+  P.ibase = L.ibase;
+  P.ibase_stride = sh.nov_max;
+  P.hbits = L.hbits;
+  P.hstride = sh.hstride;
+  P.nkeep = sh.nkeep;
   P.mid_cap = t.mid_max_ub;
   P.mid_kind = t.mid_kind;
   P.lds_words = t.lds_bytes / 4;
@@ -847,7 +910,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   hipLaunchKernelGGL(k_plan_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
                      sh.nov_max, L.heavy_nwin);
   SG_HIP(hipGetLastError());
-  SG_TRY(scan64(L.heavy_nwin, sh.nov_max, L.ibase, L.part, st));
+  SG_TRY(scan64(L.heavy_nwin, sh.nov_max * sh.nrange, L.ibase, L.part, st));
   hipLaunchKernelGGL(k_plan_fill, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
                      L.ibase, sh.nov_max, L.item_vec, L.item_b0, L.item_b1, L.item_off, L.counters);
   SG_HIP(hipGetLastError());

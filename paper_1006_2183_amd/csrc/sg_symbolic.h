@@ -367,18 +367,18 @@ __global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_n
   }
 }
 
-// Heavy-tier windows of one vector from its bucket counts. Mode 0: one
-// window per non-empty bucket. Mode 1: consecutive buckets are merged while
-// the entries fit rank_cap and the span fits rank_wb buckets; empty buckets
-// between windows are skipped. Every bucket holds at most sw <= rank_cap
-// entries, so each window takes at least one bucket. `emit` receives
-// (b0, b1, entries before the window).
+// Heavy-tier windows of one vector inside buckets [bs, be) (one XCD range)
+// from its bucket counts. Mode 0: one window per non-empty bucket. Mode 1:
+// consecutive buckets are merged while the entries fit rank_cap and the span
+// fits rank_wb buckets; empty buckets between windows are skipped. Every
+// bucket holds at most sw <= rank_cap entries, so each window takes at least
+// one bucket. `emit` receives (b0, b1, entries of the vector before b0).
 template <class F>
-__device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t *bc, F emit) {
-  int64_t nwin = 0, before = 0;
-  int32_t b = 0;
-  const int32_t nb = G.nsplit;
-  while (b < nb) {
+__device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t *bc, int32_t bs, int32_t be,
+                                                int64_t before, F emit) {
+  int64_t nwin = 0;
+  int32_t b = bs;
+  while (b < be) {
     if (bc[b] == 0) {
       ++b;
       continue;
@@ -389,7 +389,7 @@ __device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t
       sum = bc[b];
       ++b;
     } else {
-      while (b < nb && (b - b0) < G.rank_wb && sum + bc[b] <= G.rank_cap) {
+      while (b < be && (b - b0) < G.rank_wb && sum + bc[b] <= G.rank_cap) {
         sum += bc[b];
         ++b;
       }
@@ -401,15 +401,28 @@ __device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t
   return nwin;
 }
 
+// Range r of a group covers buckets [r * bpr, min((r + 1) * bpr, nsplit)).
+__device__ __forceinline__ void range_buckets(const GroupDev &G, int r, int32_t &bs, int32_t &be) {
+  const int64_t s0 = (int64_t)r * G.bpr, e0 = s0 + G.bpr;
+  bs = (int32_t)(s0 < G.nsplit ? s0 : G.nsplit);
+  be = (int32_t)(e0 < G.nsplit ? e0 : G.nsplit);
+}
+
+// Windows per (range, heavy vector), laid out range-major: out[r * cap + q].
 __global__ void k_plan_count(Plan P, int64_t cap, int64_t *nwin_out) {
   const int64_t nh = P.counters[kCtHeavy];
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x) {
     if (q >= nh) {
-      nwin_out[q] = 0;
+      for (int r = 0; r < P.nrange; ++r) nwin_out[r * cap + q] = 0;
       continue;
     }
     const GroupDev &G = P.groups[P.ov_group[P.heavy_list[q]]];
-    nwin_out[q] = plan_windows(G, P.bcnt + q * (int64_t)P.nbmax, [](int32_t, int32_t, int64_t) {});
+    const int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
+    for (int r = 0; r < P.nrange; ++r) {
+      int32_t bs, be;
+      range_buckets(G, r, bs, be);
+      nwin_out[r * cap + q] = plan_windows(G, bc, bs, be, 0, [](int32_t, int32_t, int64_t) {});
+    }
   }
 }
 
@@ -418,16 +431,23 @@ __global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, int32_t *
   const int64_t nh = counters[kCtHeavy];
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
     const GroupDev &G = P.groups[P.ov_group[P.heavy_list[q]]];
-    int64_t i = ibase[q];
-    plan_windows(G, P.bcnt + q * (int64_t)P.nbmax, [&](int32_t b0, int32_t b1, int64_t before) {
-      item_vec[i] = (int32_t)q;
-      item_b0[i] = b0;
-      item_b1[i] = b1;
-      item_off[i] = before;
-      ++i;
-    });
+    const int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
+    int64_t before = 0;
+    for (int r = 0; r < P.nrange; ++r) {
+      int32_t bs, be;
+      range_buckets(G, r, bs, be);
+      int64_t i = ibase[r * cap + q];
+      plan_windows(G, bc, bs, be, before, [&](int32_t b0, int32_t b1, int64_t bef) {
+        item_vec[i] = (int32_t)q;
+        item_b0[i] = b0;
+        item_b1[i] = b1;
+        item_off[i] = bef;
+        ++i;
+      });
+      for (int32_t b = bs; b < be; ++b) before += bc[b];
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCtItems] = ibase[cap];
+  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCtItems] = ibase[(int64_t)P.nrange * cap];
 }
 
 // Per-group totals after the scans of counts (ov_off) and non-empty flags (nzpos).

@@ -32,49 +32,88 @@
 namespace sg {
 
 // ---------------------------------------------------------------------------
+// Accumulators take a product in two steps so that the LDS reads of several
+// products can be in flight together: prep(id) issues the reads one product
+// needs and returns them as a token, commit(id, token, value) applies it.
+// Step wraps a one-step lambda.
+template <class T, class F>
+struct Step {
+  F f;
+  __device__ __forceinline__ uint64_t prep(int) const { return 0; }
+  __device__ __forceinline__ void commit(int id, uint64_t, T v) { f(id, v); }
+};
+template <class T, class F>
+__device__ __forceinline__ Step<T, F> step(F f) {
+  return Step<T, F>{f};
+}
+
 // Products of one batch of (up to) 64 stored entries of S, one per lane: the
 // lane holds `len` products in G positions [gb, gb + len) with S value sv.
-// act(id, value) is called once per product. Long G vectors are walked one
-// owner at a time with all lanes striding the vector (coalesced, no lane
-// search); short ones are flattened so that every lane gets a product.
+// Every product is passed to the accumulator once.
+//
+// The wavefront splits into groups of gs lanes, gs the power of two nearest
+// above the batch's mean length (1..64); the 64 / gs groups each take a
+// different entry at a time and stride its G positions, so that short and
+// long G vectors both keep every lane busy and the groups' loads are in
+// flight together. Entries with products are compacted through a per-wave
+// LDS byte map so that empty ones cost nothing.
+__shared__ uint8_t s_own[kMaxWaves * kWave];
+
 template <class SR, class Act>
 __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
                                           const typename SR::T *__restrict__ gval, Act &act) {
   typedef typename SR::T T;
   const int l = lane();
-  const int P = wave_incl_scan(len);
-  const int tot = read_lane(P, kWave - 1);
-  if (tot == 0) return;
-  const int steps_owner = wave_sum((len + kWave - 1) / kWave);
-  const int steps_flat = (tot + kWave - 1) / kWave;
-  if (steps_owner <= 2 * steps_flat) {
-    uint64_t m = __ballot(len > 0);
-    while (m) {
-      const int o = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      const int L = read_lane(len, o);
-      const int64_t b = read_lane64(gb, o);
-      const T s = read_lane_val(sv, o);
-      for (int f = l; f < L; f += kWave) {
-        const int64_t g = b + f;
-        if (SR::kVal) act(gidx[g], SR::mul(s, gval[g]));
-        else act(gidx[g], T());
+  const uint64_t m = __ballot(len > 0);
+  if (m == 0) return;
+  const int nz = __popcll(m);
+  const int tot = wave_sum(len);
+  const int avg = (tot + nz - 1) / nz;
+  int lg = 0;
+  while (lg < 6 && (1 << lg) < avg) ++lg;
+  const int gs = 1 << lg;
+  const int ng = kWave >> lg;
+  const int gi = l >> lg;
+  const int li = l & (gs - 1);
+  uint8_t *own = s_own + (threadIdx.x / kWave) * kWave;
+  if (len > 0) own[__popcll(m & ((1ull << l) - 1ull))] = (uint8_t)l;
+  __builtin_amdgcn_wave_barrier();
+  const int rounds = (nz + ng - 1) / ng;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int r = rd * ng + gi;
+    const bool valid = r < nz;
+    const int o = valid ? own[r] : 0;
+    const int L = __shfl(len, o, kWave);
+    const int64_t b = __shfl(gb, o, kWave);
+    const T s = __shfl(sv, o, kWave);
+    if (valid) {
+      int f = li;
+      for (; f + 3 * gs < L; f += 4 * gs) {
+        const int64_t g0 = b + f;
+        const int32_t i0 = gload(gidx + g0), i1 = gload(gidx + g0 + gs);
+        const int32_t i2 = gload(gidx + g0 + 2 * gs), i3 = gload(gidx + g0 + 3 * gs);
+        T v0 = T(), v1 = T(), v2 = T(), v3 = T();
+        if (SR::kVal) {
+          v0 = gload(gval + g0);
+          v1 = gload(gval + g0 + gs);
+          v2 = gload(gval + g0 + 2 * gs);
+          v3 = gload(gval + g0 + 3 * gs);
+        }
+        const uint64_t t0 = act.prep(i0), t1 = act.prep(i1), t2 = act.prep(i2), t3 = act.prep(i3);
+        act.commit(i0, t0, SR::kVal ? SR::mul(s, v0) : T());
+        act.commit(i1, t1, SR::kVal ? SR::mul(s, v1) : T());
+        act.commit(i2, t2, SR::kVal ? SR::mul(s, v2) : T());
+        act.commit(i3, t3, SR::kVal ? SR::mul(s, v3) : T());
       }
-    }
-  } else {
-    const int64_t start = gb - (int64_t)(P - len);
-    for (int base = 0; base < tot; base += kWave) {
-      const int f = base + l;
-      const int o = owner_of(P, f < tot ? f : tot - 1);
-      const int64_t st = __shfl(start, o, kWave);
-      const T s = __shfl(sv, o, kWave);
-      if (f < tot) {
-        const int64_t g = st + f;
-        if (SR::kVal) act(gidx[g], SR::mul(s, gval[g]));
-        else act(gidx[g], T());
+      for (; f < L; f += gs) {
+        const int64_t g = b + f;
+        const int32_t i = gload(gidx + g);
+        const T v = SR::kVal ? gload(gval + g) : T();
+        act.commit(i, act.prep(i), SR::kVal ? SR::mul(s, v) : T());
       }
     }
   }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Load the lane's stored S entry e of product d and describe its products:
@@ -87,44 +126,52 @@ __device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t 
   gb = 0;
   sv = T();
   if (e >= e1) return;
-  const int32_t k = d.s_idx[e];
-  const int32_t gt = d.gres ? d.gres[e] : ((k >= 0 && k < d.g_nvec) ? k : -1);
+  const int32_t k = gload(d.s_idx + e);
+  const int32_t gt = d.gres ? gload(d.gres + e) : ((k >= 0 && k < d.g_nvec) ? k : -1);
   if (gt < 0) return;
-  const int64_t p0 = d.g_ptr[gt];
+  const int64_t p0 = gload(d.g_ptr + gt);
   if (b0 >= 0 && d.wsplit) {
     const int32_t *ws = d.wsplit + (int64_t)gt * (d.nsplit + 1);
-    const int32_t w0 = ws[b0];
+    const int32_t w0 = gload(ws + b0);
     gb = p0 + w0;
-    len = ws[b1] - w0;
+    len = gload(ws + b1) - w0;
   } else {
     gb = p0;
-    len = (int)(d.g_ptr[gt + 1] - p0);
+    len = (int)(gload(d.g_ptr + gt + 1) - p0);
   }
-  if (SR::kVal) sv = ((const T *)d.s_val)[e];
+  if (SR::kVal) sv = gload((const T *)d.s_val + e);
 }
 
 // All products of output vector v (restricted to split buckets [b0, b1) if
-// b0 >= 0), shared among the nw wavefronts of the caller (wave wid takes
-// every nw-th batch of 64 S entries, counted across the vector's segments).
+// b0 >= 0), shared by the nw wavefronts of the caller. Every wave walks the
+// same batches of 64 stored S entries; the products of a batch, in entry
+// order, are cut into nw equal slices and wave wid takes slice wid by
+// clipping each entry's G range to it. A vector with few entries but long G
+// vectors (the typical heavy vector) thus keeps every wave busy.
 template <class SR, class Act>
 __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, int b1, int wid, int nw, Act &act) {
   typedef typename SR::T T;
   const int64_t s0 = P.ov_seg[v], s1 = P.ov_seg[v + 1];
-  int64_t gbatch = 0;
   for (int64_t s = s0; s < s1; ++s) {
     const ProdDev &d = P.prods[P.seg_prod[s]];
     const int32_t t = P.seg_svec[s];
-    const int64_t e0 = d.s_ptr[t], e1 = d.s_ptr[t + 1];
-    const int64_t nb = (e1 - e0 + kWave - 1) / kWave;
-    int64_t b = (int64_t)(((wid - gbatch) % nw + nw) % nw);
-    for (; b < nb; b += nw) {
+    const int64_t e1 = d.s_ptr[t + 1];
+    for (int64_t eb = d.s_ptr[t]; eb < e1; eb += kWave) {
       int len;
       int64_t gb;
       T sv;
-      load_entry<SR>(d, e0 + b * kWave + lane(), e1, b0, b1, len, gb, sv);
-      run_batch<SR>(len, gb, sv, d.g_idx, (const T *)d.g_val, act);
+      load_entry<SR>(d, eb + lane(), e1, b0, b1, len, gb, sv);
+      const int incl = wave_incl_scan(len);
+      const int tot = read_lane(incl, kWave - 1);
+      if (tot == 0) continue;
+      const int f0 = (int)((int64_t)tot * wid / nw);
+      const int f1 = (int)((int64_t)tot * (wid + 1) / nw);
+      const int st = incl - len;
+      const int a = st > f0 ? st : f0;
+      const int e = incl < f1 ? incl : f1;
+      const int len2 = e > a ? e - a : 0;
+      run_batch<SR>(len2, gb + (a - st), sv, d.g_idx, (const T *)d.g_val, act);
     }
-    gbatch += nb;
   }
 }
 
@@ -163,8 +210,8 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
       const T so = __shfl(sv, o, kWave);
       if (mine) {
         const int64_t g = st + f;
-        key = d.g_idx[g];
-        if (SR::kVal) val = SR::mul(so, ((const T *)d.g_val)[g]);
+        key = gload(d.g_idx + g);
+        if (SR::kVal) val = SR::mul(so, gload((const T *)d.g_val + g));
       }
       filled += tot;
     }
@@ -205,8 +252,8 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
     const int r = __popcll(hm & ((1ull << l) - 1ull));
     const OutDev &O = P.outs[P.ov_group[v]];
     const int64_t pos = out_offset(P, v) + r;
-    O.idx[pos] = key;
-    if (SR::kVal) ((T *)O.val)[pos] = val;
+    gstore(O.idx + pos, key);
+    if (SR::kVal) gstore((T *)O.val + pos, val);
   }
 }
 
@@ -215,31 +262,56 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
 __device__ __forceinline__ int64_t align2(int64_t w) { return (w + 1) & ~(int64_t)1; }
 
 // Bitmap-rank accumulator over output ids [lo, hi) of vector v: a bit per
-// id marks the pattern, a 16-bit prefix count per 32-bit word turns an id
+// id marks the pattern, a prefix count per 32-bit word of bits turns an id
 // into its rank, and the values are accumulated densely by rank, so the
-// entries come out sorted without a sort. b0 < 0 means the whole range
-// (mid tier); else only the products in split buckets [b0, b1) are taken.
-// COUNT writes the number of entries to ov_cnt[v]; the numeric variant
-// writes them at out_pos.
+// entries come out sorted without a sort. With values, each 32 ids own one
+// 8-byte LDS word {bits, prefix}, so a rank costs one LDS read. b0 < 0 means
+// the whole range (mid tier); else only the products in split buckets
+// [b0, b1) are taken. COUNT writes the number of entries to ov_cnt[v]; the
+// numeric variant writes them at out_pos.
+template <class SR>
+struct RankAcc {
+  typedef typename SR::T T;
+  typedef typename SR::Slot Slot;
+  uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
+  Slot *vals;
+  int lo32;
+  __device__ __forceinline__ uint64_t prep(int id) const {
+    const int r = id - lo32;
+    return *(const uint64_t *)(words + 2 * (r >> 5));
+  }
+  __device__ __forceinline__ void commit(int id, uint64_t tok, T x) {
+    const int r = id - lo32;
+    const uint32_t bits = (uint32_t)tok;
+    const uint32_t pre = (uint32_t)(tok >> 32);
+    SR::acc(&vals[pre + __popc(bits & ((1u << (r & 31)) - 1u))], x);
+  }
+};
+
 template <int K, bool COUNT>
 __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
-                            uint32_t *lds, int64_t *scratch) {
+                            uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
+  constexpr int WS = SR::kVal ? 2 : 1;  // 32-bit LDS words per 32 ids
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wid = tid / kWave, nw = nt / kWave;
   const int nwds = (int)((hi - lo + 31) >> 5);
   const int lo32 = (int)lo;
-  uint32_t *bits = lds;
-  uint16_t *pre = (uint16_t *)(lds + nwds);
-  Slot *vals = (Slot *)(lds + align2(nwds + ((nwds + 1) >> 1)));
+  uint32_t *words = lds;
+  Slot *vals = (Slot *)(lds + WS * nwds);
 
-  auto mark = [&](int id, T) {
-    const int r = id - lo32;
-    atomicOr(&bits[r >> 5], 1u << (r & 31));
-  };
-  for_products<SR>(P, v, b0, b1, wid, nw, mark);
+  if (kept) {  // the count pass kept this vector's bitmap: copy the window's words
+    const uint32_t *src = kept + (lo >> 5);
+    for (int w = tid; w < nwds; w += nt) words[WS * w] = gload(src + w);
+  } else {
+    auto mark = step<T>([&](int id, T) {
+      const int r = id - lo32;
+      atomicOr(&words[WS * (r >> 5)], 1u << (r & 31));
+    });
+    for_products<SR>(P, v, b0, b1, wid, nw, mark);
+  }
   __syncthreads();
 
   // per-thread contiguous word range
@@ -247,12 +319,12 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   const int w0 = tid * per < nwds ? tid * per : nwds;
   const int w1 = w0 + per < nwds ? w0 + per : nwds;
   int local = 0;
-  for (int w = w0; w < w1; ++w) local += __popc(bits[w]);
+  for (int w = w0; w < w1; ++w) local += __popc(words[WS * w]);
   int64_t total;
   const int64_t excl = block_excl_scan(local, scratch, &total);
   if (COUNT) {
-    for (int w = w0; w < w1; ++w) bits[w] = 0;
-    if (tid == 0) P.ov_cnt[v] = total;
+    for (int w = w0; w < w1; ++w) words[WS * w] = 0;
+    if (tid == 0) gstore(P.ov_cnt + v, total);
     __syncthreads();
     return;
   }
@@ -260,13 +332,14 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   if (!SR::kVal) {
     int64_t r = out_pos + excl;
     for (int w = w0; w < w1; ++w) {
-      uint32_t b = bits[w];
+      uint32_t b = words[w];
       while (b) {
         const int bit = __ffs(b) - 1;
         b &= b - 1;
-        O.idx[r++] = lo32 + (w << 5) + bit;
+        gstore(O.idx + r, lo32 + (w << 5) + bit);
+        ++r;
       }
-      bits[w] = 0;
+      words[w] = 0;
     }
     __syncthreads();
     return;
@@ -274,35 +347,30 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   {
     int run = (int)excl;
     for (int w = w0; w < w1; ++w) {
-      pre[w] = (uint16_t)run;
-      run += __popc(bits[w]);
+      words[WS * w + 1] = (uint32_t)run;
+      run += __popc(words[WS * w]);
     }
   }
   __syncthreads();
-  auto accum = [&](int id, T x) {
-    const int r = id - lo32;
-    const int w = r >> 5;
-    const int rk = pre[w] + __popc(bits[w] & ((1u << (r & 31)) - 1u));
-    SR::acc(&vals[rk], x);
-  };
+  RankAcc<SR> accum{words, vals, lo32};
   for_products<SR>(P, v, b0, b1, wid, nw, accum);
   __syncthreads();
   // emit: lane-interleaved words, so a wavefront writes one contiguous run
   for (int w = tid; w < nwds; w += nt) {
-    uint32_t b = bits[w];
+    uint32_t b = words[WS * w];
     if (b) {
-      int r = pre[w];
+      int r = (int)words[WS * w + 1];
       while (b) {
         const int bit = __ffs(b) - 1;
         b &= b - 1;
-        O.idx[out_pos + r] = lo32 + (w << 5) + bit;
-        ((T *)O.val)[out_pos + r] = SR::dec(vals[r]);
+        gstore(O.idx + out_pos + r, lo32 + (w << 5) + bit);
+        gstore((T *)O.val + out_pos + r, SR::dec(vals[r]));
         vals[r] = Slot();
         ++r;
       }
-      bits[w] = 0;
     }
-    pre[w] = 0;
+    words[WS * w] = 0;
+    words[WS * w + 1] = 0;
   }
   __syncthreads();
 }
@@ -328,7 +396,7 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
   uint32_t *keys = lds;
   Slot *vals = (Slot *)(lds + ts);
 
-  auto ins = [&](int id, T x) {
+  auto ins = step<T>([&](int id, T x) {
     const uint32_t kk = (uint32_t)id + 1u;
     int h = (int)hash_id((uint32_t)id, logts);
     while (true) {
@@ -338,7 +406,7 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
       h = (h + 1) & mask;
     }
     if (!COUNT) SR::acc(&vals[h], x);
-  };
+  });
   for_products<SR>(P, v, -1, -1, wid, nw, ins);
   __syncthreads();
   if (COUNT) {
@@ -381,8 +449,8 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
   const int64_t cnt = P.ov_cnt[v];
   for (int i = tid; i < ts; i += nt) {
     if (i < cnt) {
-      O.idx[base + i] = (int32_t)(keys[i] - 1u);
-      if (SR::kVal) ((T *)O.val)[base + i] = SR::dec(vals[i]);
+      gstore(O.idx + base + i, (int32_t)(keys[i] - 1u));
+      if (SR::kVal) gstore((T *)O.val + base + i, SR::dec(vals[i]));
     }
     keys[i] = 0;
     vals[i] = Slot();
@@ -406,11 +474,11 @@ __device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int
   Slot *vals = (Slot *)(lds + align2(wcap));
   const int lo32 = (int)lo;
 
-  auto acc = [&](int id, T x) {
+  auto acc = step<T>([&](int id, T x) {
     const int r = id - lo32;
     atomicOr(&flags[r >> 5], 1u << (r & 31));
     if (!COUNT) SR::acc(&vals[r], x);
-  };
+  });
   for_products<SR>(P, v, c, c + 1, wid, nw, acc);
   __syncthreads();
 
@@ -434,9 +502,9 @@ __device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int
       const int bit = __ffs(b) - 1;
       b &= b - 1;
       const int x = (w << 5) + bit;
-      O.idx[r] = lo32 + x;
+      gstore(O.idx + r, lo32 + x);
       if (SR::kVal) {
-        ((T *)O.val)[r] = SR::dec(vals[x]);
+        gstore((T *)O.val + r, SR::dec(vals[x]));
         vals[x] = Slot();
       }
       ++r;
@@ -450,7 +518,7 @@ __device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int
 // Count pass of one heavy vector: entries per split bucket (P.bcnt) and in
 // total (ov_cnt). Mode 1 marks the whole id range once in an LDS bitmap;
 // mode 0 counts bucket by bucket with the dense window.
-template <int K>
+template <int K, int MODE>
 __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *scratch) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
@@ -458,7 +526,8 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   const int64_t v = P.heavy_list[q];
   const GroupDev &G = P.groups[P.ov_group[v]];
   int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
-  if (G.mode == 0) {
+  if (G.mode != MODE) return;
+  if (MODE == 0) {
     int64_t total = 0;
     for (int c = 0; c < G.nsplit; ++c) {
       const int64_t lo = (int64_t)c * G.sw;
@@ -477,13 +546,16 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   const int nwds = (int)((G.minor + 31) >> 5);
   uint32_t *bits = lds;
   int32_t *lbc = (int32_t *)(lds + nwds);
-  auto mark = [&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); };
+  auto mark = step<T>([&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); });
   for_products<SR>(P, v, -1, -1, wid, nw, mark);
   __syncthreads();
   const int wpb = G.sw >> 5;  // words per bucket
+  uint32_t *keep = q < P.nkeep ? P.hbits + q * P.hstride : nullptr;
   int64_t local = 0;
   for (int w = tid; w < nwds; w += nt) {
-    const int c = __popc(bits[w]);
+    const uint32_t word = bits[w];
+    if (keep) gstore(keep + w, word);
+    const int c = __popc(word);
     if (c) {
       atomicAdd(&lbc[w / wpb], c);
       local += c;
@@ -499,8 +571,8 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   __syncthreads();
 }
 
-// Numeric pass of one planned heavy window.
-template <int K>
+// Numeric pass of one planned heavy window (MODE 2: either window kind).
+template <int K, int MODE>
 __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
   const int32_t q = P.item_vec[it];
   const int32_t b0 = P.item_b0[it], b1 = P.item_b1[it];
@@ -509,8 +581,9 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
   const int64_t lo = (int64_t)b0 * G.sw;
   const int64_t hi = (int64_t)b1 * G.sw < G.minor ? (int64_t)b1 * G.sw : G.minor;
   const int64_t pos = out_offset(P, v) + P.item_off[it];
-  if (G.mode == 0) dense_window<K, false>(P, v, b0, lo, hi, pos, lds, scratch, (G.sw + 31) >> 5);
-  else rank_window<K, false>(P, v, lo, hi, b0, b1, pos, lds, scratch);
+  if (MODE != 2 && G.mode != MODE) return;
+  if (MODE == 0 || (MODE == 2 && G.mode == 0)) dense_window<K, false>(P, v, b0, lo, hi, pos, lds, scratch, (G.sw + 31) >> 5);
+  else rank_window<K, false>(P, v, lo, hi, b0, b1, pos, lds, scratch, q < P.nkeep ? P.hbits + q * P.hstride : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -531,7 +604,7 @@ __global__ void __launch_bounds__(1024) k_tiny(Plan P) {
 }
 
 template <int K, bool COUNT>
-__global__ void __launch_bounds__(1024) k_mid(Plan P, int64_t *queue) {
+__global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_t *queue) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
   __shared__ int64_t s_item;
@@ -549,28 +622,59 @@ __global__ void __launch_bounds__(1024) k_mid(Plan P, int64_t *queue) {
   }
 }
 
-template <int K, bool COUNT>
-__global__ void __launch_bounds__(1024) k_heavy(Plan P, int64_t *queue) {
+// MODE selects the heavy window kind this launch handles (items of groups
+// with the other kind are skipped); a plan launches one kernel per kind used.
+// The count variant pulls heavy vectors from one queue. The numeric variant
+// keeps one queue per XCD over the windows of that XCD's id ranges
+// (`queue` has kXcds counters); a workgroup starts with the queue of the XCD
+// it runs on, taken as blockIdx.x mod kXcds (workgroups are dispatched to
+// the dies round-robin), and then drains the others in turn.
+template <int K, bool COUNT, int MODE>
+__global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int64_t *queue) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
   __shared__ int64_t s_item;
   zero_lds(lds, P.lds_words);
-  const int64_t n = COUNT ? P.counters[kCtHeavy] : P.counters[kCtItems];
-  while (true) {
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
-    __syncthreads();
-    const int64_t i = s_item;
-    __syncthreads();
-    if (i >= n) break;
-    if (COUNT) heavy_count<K>(P, i, lds, scratch);
-    else heavy_item<K>(P, i, lds, scratch);
+  if (COUNT) {
+    const int64_t n = P.counters[kCtHeavy];
+    while (true) {
+      if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
+      __syncthreads();
+      const int64_t i = s_item;
+      __syncthreads();
+      if (i >= n) break;
+      heavy_count<K, MODE>(P, i, lds, scratch);
+    }
+    return;
+  }
+  const int per_xcd = P.nrange >= kXcds ? P.nrange / kXcds : 0;
+  const int home = blockIdx.x % kXcds;
+  for (int d = 0; d < kXcds; ++d) {
+    const int x = (home + d) % kXcds;
+    int64_t lo, hi;
+    if (per_xcd == 0) {  // ranges off: one queue, held by XCD 0's counter
+      lo = 0;
+      hi = x == 0 ? P.counters[kCtItems] : 0;
+    } else {
+      lo = P.ibase[(int64_t)x * per_xcd * P.ibase_stride];
+      hi = P.ibase[(int64_t)(x + 1) * per_xcd * P.ibase_stride];
+    }
+    if (lo >= hi) continue;
+    while (true) {
+      if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
+      __syncthreads();
+      const int64_t i = lo + s_item;
+      __syncthreads();
+      if (i >= hi) break;
+      heavy_item<K, MODE>(P, i, lds, scratch);
+    }
   }
 }
 
 // One persistent launch for every tier: queue items are heavy windows
 // first, then mid vectors, then groups of tiny vectors (one per wavefront).
-template <int K>
-__global__ void __launch_bounds__(1024) k_batched(Plan P, int64_t *queue, int64_t n_items, int64_t n_mid,
+template <int K, int MODE>
+__global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, int64_t *queue, int64_t n_items, int64_t n_mid,
                                                   int64_t n_tiny) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
@@ -586,7 +690,7 @@ __global__ void __launch_bounds__(1024) k_batched(Plan P, int64_t *queue, int64_
     __syncthreads();
     if (i >= total) break;
     if (i < n_items) {
-      heavy_item<K>(P, i, lds, scratch);
+      heavy_item<K, MODE>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
       const int64_t v = P.mid_list[i - n_items];
       if (P.mid_kind == 0) rank_window<K, false>(P, v, 0, P.groups[P.ov_group[v]].minor, -1, -1, out_offset(P, v), lds, scratch);

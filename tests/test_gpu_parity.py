@@ -87,16 +87,18 @@ def test_rmat_s10_default_tiers(sg, semiring, batched):
 
 
 @pytest.mark.parametrize("semiring", SEMIRINGS)
-@pytest.mark.parametrize("force,mid_kind,heavy_kind", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (2, 0, 0), (2, 0, 1),
-                                                       (-1, 0, 0), (-1, 1, 1)])
-def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind):
+@pytest.mark.parametrize("force,mid_kind,heavy_kind,bitmap_mb", [(0, 0, 0, 4096), (1, 0, 0, 4096), (1, 1, 0, 4096),
+                                                                 (2, 0, 0, 4096), (2, 0, 0, 0), (2, 0, 0, 1),
+                                                                 (2, 0, 1, 4096), (-1, 0, 0, 4096), (-1, 1, 1, 0)])
+def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind, bitmap_mb):
     """Every tier on every vector it can take. 16 KB of LDS: rank windows hold 1024 (f64)
     or 2048 (4-byte values) entries over 1K/2K-id buckets, so heavy rows split into several
-    planned windows; dense windows are ~2K ids wide over 8192 columns (the last partial)."""
-    _say(f"case forced tier {force} mid_kind {mid_kind} heavy_kind {heavy_kind} {semiring}")
+    planned windows; dense windows are ~2K ids wide over 8192 columns (the last partial).
+    bitmap_mb 0 re-marks every window; 1 MiB keeps the bitmaps of only part of the heavy vectors."""
+    _say(f"case forced tier {force} mid_kind {mid_kind} heavy_kind {heavy_kind} bitmap_mb {bitmap_mb} {semiring}")
     A = W.rmat_matrix(13, 8, semiring, "csr", seed=4)
     C, info = gpu_product(sg, semiring, A, A, force_tier=force, mid_kind=mid_kind, heavy_kind=heavy_kind,
-                          lds_bytes=16384, block_threads=256)
+                          lds_bytes=16384, block_threads=256, bitmap_mb=bitmap_mb)
     check(semiring, C, A, A, f"force{force}")
     if force == 2:
         assert info["n_mid"] == 0 and info["n_tiny"] == 0

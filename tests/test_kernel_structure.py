@@ -6,9 +6,10 @@ the item to all threads. The item's work must end convergent. If a lane-0-
 only store ends an item with no barrier after it, the compiler can turn the
 queue loop into a nested loop whose back edge skips the atomic for every
 lane but thread 0's. Those lanes then re-read the old item forever (a GPU
-hang). This test checks the assembly: the atomic sits in the kernel's
-outermost loop and no other loop header lies between it and its two
-barriers.
+hang). This test checks the assembly: no loop header lies between the
+atomic and its two barriers (the atomic sits in the queue loop, which is
+the outermost loop or, for the per-XCD queues, the loop inside the one over
+the XCDs' queues).
 """
 import os
 import re
@@ -48,13 +49,14 @@ def queue_loop_report(asm: str):
         depth = re.search(r"Depth=(\d+)", headers[-1]).group(1) if headers else None
         bars = [i for i in range(a, len(lines)) if "s_barrier" in lines[i]][:2]
         between = [l for l in lines[a:bars[-1]] if "Loop Header" in l] if len(bars) == 2 else ["?"]
-        ok = depth == "1" and len(bars) == 2 and not between
+        ok = depth in ("1", "2") and len(bars) == 2 and not between
         rows.append((name, ok, f"atomic at loop depth {depth}, loop headers before its barriers: {len(between)}"))
     return rows
 
 
 def test_queue_loops_stay_convergent(tmp_path):
     rows = queue_loop_report(_asm(str(tmp_path)))
-    assert len(rows) == 20, f"expected 20 queue kernels, found {len(rows)}"
+    # 4 semirings x (mid count/numeric + heavy count/numeric per window kind + batched per kind set)
+    assert len(rows) == 36, f"expected 36 queue kernels, found {len(rows)}"
     bad = [r for r in rows if not r[1]]
     assert not bad, "queue loop restructured: " + "; ".join(f"{n}: {why}" for n, _, why in bad)
