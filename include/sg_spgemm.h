@@ -239,9 +239,11 @@ sg_status sg_spgemm_numeric(sg_plan *plan, sg_mat_out *C, void *stream);
  * Batched numeric phase: the same result as sg_spgemm_numeric, computed by
  * ONE persistent launch whose workgroups pull (output vector, tier) work
  * items of every product and group from a device queue, heaviest first. It
- * records no memset and no host synchronisation, so it can be captured in a
- * hipGraph and replayed; a replay recomputes C from the current operand
- * values. Errors: as sg_spgemm_numeric.
+ * records no memset, no copy and no host synchronisation, so it can be
+ * captured in a hipGraph and replayed; a replay recomputes C (the output
+ * arrays given at capture) from the current operand values. Calls on one
+ * plan share its workspace and must be ordered on one stream. Errors: as
+ * sg_spgemm_numeric.
  */
 sg_status sg_spgemm_batched(sg_plan *plan, sg_mat_out *C, void *stream);
 

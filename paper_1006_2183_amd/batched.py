@@ -1,0 +1,108 @@
+"""Batched forms of the local product: one plan for many products.
+
+* ``summa_share``: the local work of one Sparse SUMMA process, C_IJ =
+  (+)_k A_Ik (x) A_kJ over all stages k (paper, Sections 3.2 and 3.5). All
+  stage products form one group, so the stage partials are accumulated in
+  the same output vectors instead of being materialised and merged.
+* ``merge_partials``: the materialise-then-merge alternative: the stage
+  partials C_k are summed by a grouped product with an identity operand
+  (C = (+)_k I C_k column-major), a k-way merge on the same accumulators.
+* ``galerkin_rap``: R (A P) for many uneven instances (graph contraction and
+  multigrid coarsening, Section 6.2.3), two grouped plans (A P, then R (AP)).
+* ``GraphedNumeric``: captures the persistent batched launch of a plan in a
+  HIP graph; each replay recomputes the outputs from the current operand
+  values (same structure), with no host work.
+
+All arithmetic runs in the HIP library; this module arranges plans and
+PyTorch-owned buffers.
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+from . import binding as B
+from .binding import DevMat
+
+
+def summa_share(semiring: str, A_blocks: Sequence[DevMat], B_blocks: Sequence[DevMat], out_fmt: str = "dcsc",
+                tuning=None, batched: bool = True, stream=None) -> DevMat:
+    """C_IJ = (+)_k A_blocks[k] (x) B_blocks[k], every stage product in one plan."""
+    n = len(A_blocks)
+    Cs = B.spgemm_grouped(semiring, list(A_blocks), list(B_blocks), [0] * n, 1, out_fmt=out_fmt, tuning=tuning,
+                          batched=batched, stream=stream)
+    return Cs[0]
+
+
+def summa_share_plan(semiring: str, A_blocks, B_blocks, out_fmt: str = "dcsc", tuning=None, stream=None):
+    """The plan of ``summa_share`` (symbolic phase only), for repeated numeric phases."""
+    n = len(A_blocks)
+    return B.spgemm_symbolic(semiring, list(A_blocks), list(B_blocks), [0] * n, 1, out_fmt=out_fmt,
+                             tuning=tuning, stream=stream)
+
+
+def identity(n: int, semiring: str, fmt: str, device) -> DevMat:
+    """n x n identity with the semiring's multiplicative unit (as a device matrix)."""
+    import torch
+    one = {"plus_times_f64": (torch.float64, 1.0), "plus_times_f32": (torch.float32, 1.0),
+           "min_plus_i32": (torch.int32, 0), "or_and_bool": (None, None)}[semiring]
+    ptr = torch.arange(n + 1, dtype=torch.int64, device=device)
+    idx = torch.arange(n, dtype=torch.int32, device=device)
+    val = None if one[0] is None else torch.full((n,), one[1], dtype=one[0], device=device)
+    vid = torch.arange(n, dtype=torch.int32, device=device) if fmt in ("dcsr", "dcsc") else None
+    return DevMat(fmt, n, n, ptr, idx, val, vid)
+
+
+def merge_partials(semiring: str, partials: Sequence[DevMat], out_fmt: Optional[str] = None, tuning=None,
+                   batched: bool = True, stream=None) -> DevMat:
+    """(+)_k partials[k] as one grouped product with identity operands (a k-way merge)."""
+    C0 = partials[0]
+    col = C0.fmt in ("csc", "dcsc")
+    dev = C0.ptr.device
+    fmt = C0.fmt
+    # the partials are the streamed operand, so the output vectors are only
+    # their stored vectors: I C_k column-major, C_k I row-major
+    if col:
+        I = identity(C0.nrows, semiring, "csc", dev)
+        As, Bs = [I] * len(partials), list(partials)
+    else:
+        I = identity(C0.ncols, semiring, "csr", dev)
+        As, Bs = list(partials), [I] * len(partials)
+    Cs = B.spgemm_grouped(semiring, As, Bs, [0] * len(partials), 1, out_fmt=out_fmt or fmt, tuning=tuning,
+                          batched=batched, stream=stream)
+    return Cs[0]
+
+
+def galerkin_rap(semiring: str, Rs: Sequence[DevMat], As: Sequence[DevMat], Ps: Sequence[DevMat], tuning=None,
+                 batched: bool = True, stream=None) -> List[DevMat]:
+    """R_i (A_i P_i) for every instance i: two grouped plans, one output per instance."""
+    n = len(As)
+    AP = B.spgemm_grouped(semiring, list(As), list(Ps), list(range(n)), n, tuning=tuning, batched=batched,
+                          stream=stream)
+    return B.spgemm_grouped(semiring, list(Rs), AP, list(range(n)), n, tuning=tuning, batched=batched,
+                            stream=stream)
+
+
+class GraphedNumeric:
+    """A plan's persistent batched launch captured in a HIP graph (torch.cuda.CUDAGraph).
+
+    The outputs are allocated once; ``replay()`` recomputes them from the
+    current values of the operands the plan was built on.
+    """
+
+    def __init__(self, plan: B.Plan, outputs: Optional[List[DevMat]] = None):
+        import torch
+        self.plan = plan
+        self.outputs = outputs if outputs is not None else plan.alloc_outputs(plan.As[0].ptr.device)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            B.spgemm_batched(plan, self.outputs, side)  # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            B.spgemm_batched(plan, self.outputs, torch.cuda.current_stream())
+
+    def replay(self) -> List[DevMat]:
+        self.graph.replay()
+        return self.outputs

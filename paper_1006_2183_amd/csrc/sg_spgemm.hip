@@ -217,7 +217,8 @@ struct Layout {
 };
 
 struct Shape {
-  int64_t nov_max = 0;
+  int64_t nov_max = 0;       // output vectors (at most one per output major id of a group)
+  int64_t nseg_max = 0;      // segments: stored streamed vectors of all products
   int64_t ndense = 0;        // sum of output major dims (multi-product groups)
   int64_t ndense_ptr = 0;    // sum of (major + 1) for dense output pointers
   int32_t nbmax = 1;
@@ -298,8 +299,9 @@ sg_status check_args(const sg_semiring *sr, int32_t nprod, const sg_mat *A, cons
 
 void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, const std::vector<int32_t> &grp,
                 int32_t ngroup, const sg_tuning &t, int win, Shape &sh) {
-  sh.nov_max = 0;
-  for (int32_t p = 0; p < nprod; ++p) sh.nov_max += view(A[p], B[p]).S->nvec;
+  sh.nseg_max = 0;
+  for (int32_t p = 0; p < nprod; ++p) sh.nseg_max += view(A[p], B[p]).S->nvec;
+  sh.nov_max = sh.nseg_max;
   sh.geom.resize(ngroup);
   sh.nbmax = 1;
   sh.ndense = 0;
@@ -313,6 +315,7 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
     sh.ndense += sh.major[g];
     sh.ndense_ptr += sh.major[g] + 1;
   }
+  if (sh.dense_path) sh.nov_max = std::min<int64_t>(sh.nseg_max, sh.ndense);
   for (int32_t g = 0; g < ngroup; ++g)
     if (sh.geom[g].mode == 1) sh.hstride = std::max<int64_t>(sh.hstride, (sh.minor[g] + 31) / 32);
   if (sh.hstride > 0 && t.bitmap_mb > 0) {
@@ -349,8 +352,8 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.gstat = c.take<int64_t>((int64_t)ngroup * kStCount);
   L.ov_id = c.take<int32_t>(nov);
   L.ov_group = c.take<int32_t>(nov);
-  L.seg_prod = c.take<int32_t>(nov);
-  L.seg_svec = c.take<int32_t>(nov);
+  L.seg_prod = c.take<int32_t>(sh.nseg_max);
+  L.seg_svec = c.take<int32_t>(sh.nseg_max);
   L.ov_seg = c.take<int64_t>(nov + 1);
   L.ov_flops = c.take<int64_t>(nov);
   L.ov_cnt = c.take<int64_t>(nov + 1);
@@ -609,7 +612,14 @@ sg_status emit_outputs(sg_plan *pl, sg_mat_out *C, hipStream_t st) {
     D.fmt = O.fmt;
     D.pad = 0;
   }
-  SG_HIP(hipMemcpyAsync(pl->outs_dev, pl->outs_host, sizeof(OutDev) * pl->ngroup, hipMemcpyHostToDevice, st));
+  for (int32_t g0 = 0; g0 < pl->ngroup; g0 += kOutChunk) {
+    OutChunk chunk;
+    std::memset(&chunk, 0, sizeof(chunk));
+    const int32_t n = std::min<int32_t>(kOutChunk, pl->ngroup - g0);
+    for (int32_t i = 0; i < n; ++i) chunk.o[i] = pl->outs_host[g0 + i];
+    hipLaunchKernelGGL(k_set_outs, dim3(1), dim3(kOutChunk), 0, st, pl->outs_dev, g0, n, chunk);
+    SG_HIP(hipGetLastError());
+  }
   for (int i = 0; i < 4; ++i) pl->ran[i] = false;
   pl->timed = pl->profile;
   SG_TRY(mark(pl, 3, false, st));
@@ -818,9 +828,9 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   } else {
     SG_TRY(fill64(L.dcnt, sh.ndense + 1, 0, st));
     SG_TRY(fill64(L.dfill, sh.ndense + 1, 0, st));
-    if (sh.nov_max > 0) {
-      hipLaunchKernelGGL(k_dense_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
-                         L.prods, L.vbase, nprod, sh.nov_max, L.dbase, L.dcnt);
+    if (sh.nseg_max > 0) {
+      hipLaunchKernelGGL(k_dense_count, dim3((unsigned)grid_for(sh.nseg_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.prods, L.vbase, nprod, sh.nseg_max, L.dbase, L.dcnt);
       SG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(sh.ndense, kFillThreads)), dim3(kFillThreads), 0, st,
@@ -835,9 +845,9 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     } else {
       SG_TRY(fill64(L.ov_seg, 1, 0, st));
     }
-    if (sh.nov_max > 0) {
-      hipLaunchKernelGGL(k_dense_segs, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
-                         L.prods, L.vbase, nprod, sh.nov_max, L.dbase, L.spos, L.dfill, L.seg_prod, L.seg_svec);
+    if (sh.nseg_max > 0) {
+      hipLaunchKernelGGL(k_dense_segs, dim3((unsigned)grid_for(sh.nseg_max, kFillThreads)), dim3(kFillThreads), 0, st,
+                         L.prods, L.vbase, nprod, sh.nseg_max, L.dbase, L.spos, L.dfill, L.seg_prod, L.seg_svec);
       hipLaunchKernelGGL(k_sort_segs, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
                          L.ov_seg, L.counters, L.seg_prod, L.seg_svec);
       SG_HIP(hipGetLastError());

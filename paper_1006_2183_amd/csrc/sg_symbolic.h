@@ -505,6 +505,20 @@ __global__ void k_emit_ptr_doubly(Plan P, const int64_t *nzpos, int32_t ngroup) 
   }
 }
 
+// ---- output table -----------------------------------------------------------
+// The output descriptors of up to kOutChunk groups travel in the kernel's
+// arguments, so a launch recorded in a HIP graph carries its own table and
+// later calls with other outputs cannot redirect its replays.
+constexpr int kOutChunk = 24;
+struct OutChunk {
+  OutDev o[kOutChunk];
+};
+
+__global__ void k_set_outs(OutDev *table, int32_t first, int32_t n, OutChunk chunk) {
+  const int i = threadIdx.x;
+  if (i < n) table[first + i] = chunk.o[i];
+}
+
 // ---- operand validation -----------------------------------------------------
 __global__ void k_validate(const int64_t *ptr, const int32_t *vid, const int32_t *idx, int64_t nvec, int64_t nnz,
                            int64_t major, int64_t minor, int32_t doubly, int64_t *bad) {

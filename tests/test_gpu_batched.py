@@ -1,0 +1,154 @@
+"""GPU parity of the batched forms: the Sparse SUMMA share (stage products
+accumulated into one output), materialise-then-merge of stage partials,
+uneven Galerkin R (A P) instances, and HIP-graph replays of the persistent
+launch. Each is checked against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.helpers import assert_canonical, assert_same, triples
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1006_2183_amd as sg
+    sg.load_library()
+    return sg
+
+
+def strips(a_blocks, b_blocks, b, grid, semiring):
+    """A(I, :) and A(:, J) as single doubly compressed operands (the oracle's reference)."""
+    ra, ca, va, rb, cb, vb = [], [], [], [], [], []
+    for k in range(grid):
+        r, c, v = triples(a_blocks[k])
+        ra.append(r); ca.append(c + k * b); va.append(v)
+        r, c, v = triples(b_blocks[k])
+        rb.append(r + k * b); cb.append(c); vb.append(v)
+    cat = lambda x: None if x[0] is None else np.concatenate(x)
+    SA = W.from_triples(np.concatenate(ra), np.concatenate(ca), cat(va), b, grid * b, "dcsc", semiring)
+    SB = W.from_triples(np.concatenate(rb), np.concatenate(cb), cat(vb), grid * b, b, "dcsc", semiring)
+    return SA, SB
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32", "or_and_bool"])
+@pytest.mark.parametrize("batched", [False, True])
+def test_summa_share_fused(sg, semiring, batched):
+    """C_00 = (+)_k A_0k A_k0 over 8 stages (R-MAT scale 14 relabelled, 8 x 8 grid)."""
+    from paper_1006_2183_amd import batched as BT
+    _say(f"case summa share {semiring} batched={batched}")
+    scale, grid = 14, 8
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=semiring, seed=5)
+    b = (1 << scale) // grid
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    C = BT.summa_share(semiring, dA, dB, batched=batched).to_host()
+    SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
+    R, flops = oracle.spgemm(semiring, SA, SB)
+    assert_canonical(C)
+    assert_same(C, R, semiring, 1e-12, "summa share")
+
+
+def test_summa_share_forced_tiers_and_order(sg):
+    """Every tier on the stage-merged output, and the stage order does not matter."""
+    from paper_1006_2183_amd import batched as BT
+    import torch
+    semiring = "min_plus_i32"
+    scale, grid = 13, 4
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (1, 2), semiring=semiring, seed=9)
+    b = (1 << scale) // grid
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
+    R, _ = oracle.spgemm(semiring, SA, SB)
+    for force in (-1, 1, 2):
+        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=16384, block_threads=256)
+        C = BT.summa_share(semiring, dA, dB, tuning=t).to_host()
+        assert_same(C, R, semiring, 0.0, f"force {force}")
+    perm = [3, 0, 2, 1]
+    C = BT.summa_share(semiring, [dA[i] for i in perm], [dB[i] for i in perm]).to_host()
+    assert_same(C, R, semiring, 0.0, "shuffled stages")
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
+def test_partials_then_merge(sg, semiring):
+    """Materialised stage partials merged by a grouped identity product equal the fused share."""
+    from paper_1006_2183_amd import batched as BT
+    scale, grid = 13, 8
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=semiring, seed=3)
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    partials = [sg.spgemm(semiring, a, bb, out_fmt="dcsc") for a, bb in zip(dA, dB)]
+    for k in range(grid):
+        Rk, _ = oracle.spgemm(semiring, a_blocks[k], b_blocks[k])
+        assert_same(partials[k].to_host(), Rk, semiring, 1e-12, f"partial {k}")
+    M = BT.merge_partials(semiring, partials).to_host()
+    F = BT.summa_share(semiring, dA, dB).to_host()
+    assert_canonical(M)
+    assert_same(M, F, semiring, 1e-12, "merge vs fused")
+
+
+def test_galerkin_uneven_instances(sg):
+    """R (A P) = 4 L_{n/2} exactly, for 16 uneven 7-point grids in two grouped launches."""
+    from paper_1006_2183_amd import batched as BT
+    rng = np.random.default_rng(2)
+    sizes = rng.choice([4, 6, 8, 10, 12], size=16)
+    Ls = [W.laplacian_7pt(int(n), "csr") for n in sizes]
+    Ps = [W.aggregation_p(int(n), "csr") for n in sizes]
+    Rs = [W.transpose(P, "csr") for P in Ps]
+    dev = lambda M: sg.DevMat.from_host(M, "cuda")
+    for batched in (False, True):
+        out = BT.galerkin_rap("plus_times_f64", [dev(R) for R in Rs], [dev(L) for L in Ls], [dev(P) for P in Ps],
+                              batched=batched)
+        for i, n in enumerate(sizes):
+            Lc = W.laplacian_7pt(int(n) // 2, "csr")
+            Lc.val = Lc.val * 4.0
+            assert_same(out[i].to_host(), Lc, "plus_times_f64", 0.0, f"instance {i} n={n}")
+
+
+def test_graph_replay_tracks_values(sg):
+    """The persistent launch captured in a HIP graph: every replay equals an eager run on
+    the current values, with eager work and synchronisations between replays."""
+    import torch
+    from paper_1006_2183_amd import batched as BT
+    semiring = "plus_times_f64"
+    scale, grid = 13, 4
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=semiring, seed=11)
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    plan = BT.summa_share_plan(semiring, dA, dB)
+    G = BT.GraphedNumeric(plan)
+    scales = [1.0, 2.0, 0.5]
+    for rep, f in enumerate(scales):
+        for m in dA + dB:
+            m.val.mul_(f)  # eager work between replays changes the operand values
+        torch.cuda.synchronize()
+        out = G.replay()[0]
+        torch.cuda.synchronize()
+        eager = plan.alloc_outputs()
+        sg.spgemm_numeric(plan, eager)
+        torch.cuda.synchronize()
+        got = out.to_host()
+        ref = eager[0].to_host()
+        assert np.array_equal(got.ptr, ref.ptr) and np.array_equal(got.idx, ref.idx), f"replay {rep} pattern"
+        assert np.allclose(got.val, ref.val, rtol=1e-12, atol=0), f"replay {rep} values"
+        # and against the oracle on the current host values
+        ha = [sg.DevMat.to_host(m) for m in dA]
+        hb = [sg.DevMat.to_host(m) for m in dB]
+        b = (1 << scale) // grid
+        SA, SB = strips(ha, hb, b, grid, semiring)
+        R, _ = oracle.spgemm(semiring, SA, SB)
+        assert_same(got, R, semiring, 1e-12, f"replay {rep} vs oracle")
+    plan.destroy()
