@@ -1,0 +1,215 @@
+"""Serving loop: continuous batching of sparse products against a resident operand.
+
+Requests are products Y_r = A (x) X_r with A resident on the device (the
+multi-source breadth-first expansion of Section 6.2.2: A is the adjacency
+matrix, X_r a tall-skinny frontier, (or, and) semiring). The loop
+
+* admits a waiting request when a batch slot is free and its output-size
+  bound (the symbolic bound: sum over the stored entries (k, s) of X_r of
+  nnz(A(:, k)), which is also its flops) fits in the free part of the output
+  memory pool; a request whose bound exceeds the whole pool is rejected, and
+  one that waited past its deadline is cancelled before launch;
+* plans every admitted batch as one grouped product (one output per request)
+  and runs it as one persistent launch on one of several streams, so the
+  next batch is planned and launched while earlier ones compute
+  (continuous batching);
+* completes requests when their batch's event has fired, frees their pool
+  bytes and records latency (completion - arrival).
+
+``FifoExecutor`` runs one request per launch in arrival order, the baseline.
+The scheduler is host-only logic; executors do the device work.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds since the start of the run
+    X: object                      # the right operand (executor-specific)
+    ub: int                        # output-size bound (entries)
+    deadline: Optional[float] = None
+    status: str = "queued"         # queued, running, done, rejected, cancelled
+    start: float = float("nan")
+    done: float = float("nan")
+    result: object = None
+
+
+class Scheduler:
+    """Admission and continuous batching, independent of the device.
+
+    executor.launch(batch) -> handle; executor.poll(handle) -> bool (done);
+    executor.finish(handle) -> list of results aligned with the batch.
+    pool_entries: output entries that may be in flight at once.
+    """
+
+    def __init__(self, executor, pool_entries: int, max_batch: int = 64, max_inflight: int = 2,
+                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = lambda: None):
+        self.ex = executor
+        self.pool = int(pool_entries)
+        self.free = int(pool_entries)
+        self.max_batch = max_batch
+        self.max_inflight = max_inflight
+        self.clock = clock
+        self.idle = idle
+        self.waiting: collections.deque = collections.deque()
+        self.inflight: List = []
+        self.finished: List[Request] = []
+        self.batches = 0
+
+    def _admit(self, now: float) -> List[Request]:
+        batch = []
+        while self.waiting and len(batch) < self.max_batch:
+            r = self.waiting[0]
+            if r.deadline is not None and now > r.deadline:
+                self.waiting.popleft()
+                r.status = "cancelled"
+                r.done = now
+                self.finished.append(r)
+                continue
+            if r.ub > self.pool:
+                self.waiting.popleft()
+                r.status = "rejected"
+                r.done = now
+                self.finished.append(r)
+                continue
+            if r.ub > self.free:
+                break  # keep arrival order: wait for memory to free up
+            self.waiting.popleft()
+            self.free -= r.ub
+            r.status = "running"
+            r.start = now
+            batch.append(r)
+        return batch
+
+    def _complete(self, now: float):
+        keep = []
+        for handle, batch in self.inflight:
+            if self.ex.poll(handle):
+                results = self.ex.finish(handle)
+                t = self.clock() - self._t0
+                for r, res in zip(batch, results):
+                    r.result = res
+                    r.status = "done"
+                    r.done = t
+                    self.free += r.ub
+                    self.finished.append(r)
+            else:
+                keep.append((handle, batch))
+        self.inflight = keep
+
+    def run(self, requests: Sequence[Request]) -> List[Request]:
+        """Serve requests whose `arrival` times follow the clock; returns them finished."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        self._t0 = self.clock()
+        while pending or self.waiting or self.inflight:
+            now = self.clock() - self._t0
+            while pending and pending[0].arrival <= now:
+                self.waiting.append(pending.popleft())
+            if self.inflight:
+                self._complete(now)
+            launched = False
+            if self.waiting and len(self.inflight) < self.max_inflight:
+                batch = self._admit(self.clock() - self._t0)
+                if batch:
+                    self.inflight.append((self.ex.launch(batch), batch))
+                    self.batches += 1
+                    launched = True
+            if not launched:
+                self.idle()
+        return self.finished
+
+
+def latency_stats(reqs: Sequence[Request]) -> Dict[str, float]:
+    done = [r for r in reqs if r.status == "done"]
+    lat = np.array([r.done - r.arrival for r in done]) if done else np.zeros(0)
+    span = (max(r.done for r in done) - min(r.arrival for r in done)) if done else 0.0
+    return {
+        "done": len(done),
+        "rejected": sum(r.status == "rejected" for r in reqs),
+        "cancelled": sum(r.status == "cancelled" for r in reqs),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else float("nan"),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else float("nan"),
+        "mean_ms": float(lat.mean() * 1e3) if lat.size else float("nan"),
+        "throughput_rps": len(done) / span if span > 0 else float("nan"),
+    }
+
+
+# ---------------------------------------------------------------------------
+class GpuBatchExecutor:
+    """Each batch is one grouped product: C_r = A (x) X_r for every request r of
+    the batch, planned together and run as one persistent launch on one of
+    `nstreams` streams (round robin)."""
+
+    def __init__(self, semiring: str, A, out_fmt: Optional[str] = None, tuning=None, nstreams: int = 2):
+        import torch
+        from . import binding as B
+        self.B = B
+        self.torch = torch
+        self.semiring = semiring
+        self.A = A
+        self.out_fmt = out_fmt or A.fmt
+        self.tuning = tuning
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.next = 0
+
+    def launch(self, batch: Sequence[Request]):
+        torch = self.torch
+        s = self.streams[self.next % len(self.streams)]
+        self.next += 1
+        n = len(batch)
+        s.wait_stream(torch.cuda.current_stream())  # operands written on the caller's stream
+        with torch.cuda.stream(s):
+            plan = self.B.spgemm_symbolic(self.semiring, [self.A] * n, [r.X for r in batch], list(range(n)), n,
+                                          out_fmt=self.out_fmt, tuning=self.tuning, stream=s)
+            outs = plan.alloc_outputs(self.A.ptr.device)
+            self.B.spgemm_batched(plan, outs, s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (ev, plan, outs)
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle):
+        ev, plan, outs = handle
+        plan.destroy()
+        return outs
+
+
+class FifoExecutor:
+    """Baseline: one request per plain product, completed before the next starts."""
+
+    def __init__(self, semiring: str, A, out_fmt: Optional[str] = None, tuning=None):
+        import torch
+        from . import binding as B
+        self.B = B
+        self.torch = torch
+        self.semiring = semiring
+        self.A = A
+        self.out_fmt = out_fmt or A.fmt
+        self.tuning = tuning
+
+    def launch(self, batch: Sequence[Request]):
+        outs = [self.B.spgemm(self.semiring, self.A, r.X, out_fmt=self.out_fmt, tuning=self.tuning) for r in batch]
+        self.torch.cuda.synchronize()
+        return outs
+
+    def poll(self, handle) -> bool:
+        return True
+
+    def finish(self, handle):
+        return handle
+
+
+def frontier_bound(colcount: np.ndarray, X) -> int:
+    """Symbolic output bound of A X from a host copy of A's column counts:
+    sum over the stored entries (k, s) of X of nnz(A(:, k))."""
+    return int(colcount[np.asarray(X.idx, dtype=np.int64)].sum())
