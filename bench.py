@@ -170,6 +170,308 @@ def cpu_baseline(semiring, A, total_flops, seconds):
     }
 
 
+# ---------------------------------------------------------------------------
+# Batched and served forms (reported beside the main line)
+
+def _median_ms(torch, fn, reps):
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def _tier_bytes(infos, s):
+    """Algorithmic numeric bytes summed over the tiers of every output of a plan."""
+    tot = 0
+    for t in TIER_NAMES:
+        # tier statistics are global to the plan; take them from the first output's record
+        tot += algorithmic_bytes(infos[0], t, s)
+    return tot
+
+
+def _same(C, D, rtol, what):
+    a, b = C.to_host(), D.to_host()
+    if not (np.array_equal(a.ptr, b.ptr) and np.array_equal(a.idx, b.idx)
+            and (a.vid is None or np.array_equal(a.vid, b.vid))):
+        raise AssertionError(f"{what}: patterns differ")
+    if a.val is not None:
+        if rtol == 0.0:
+            ok = np.array_equal(a.val, b.val)
+        else:
+            ok = bool(np.all(np.abs(a.val - b.val) <= rtol * np.abs(b.val)))
+        if not ok:
+            raise AssertionError(f"{what}: values differ beyond {rtol}")
+
+
+def _summa_diagnose(res, sg, dA, dB, sr):
+    """On a mismatch: the differing columns, and which of the two forms a third one
+    (the fused plan run as per-tier launches) agrees with on them."""
+    from paper_1006_2183_amd import batched as BT
+    third = BT.summa_share(sr, dA, dB, batched=False).to_host()
+    C = {k: v.to_host() for k, v in res.items()}
+    C["per_tier"] = third
+    cols = {k: {int(H.vid[t]): H.idx[H.ptr[t]:H.ptr[t + 1]] for t in range(len(H.vid))} for k, H in C.items()}
+    none = np.zeros(0, np.int32)
+    allj = set(cols["plain"]) | set(cols["batched"]) | set(cols["per_tier"])
+    bad = sorted(j for j in allj if not (np.array_equal(cols["plain"].get(j, none), cols["batched"].get(j, none))
+                                         and np.array_equal(cols["plain"].get(j, none), cols["per_tier"].get(j, none))))
+    odd = {k: sum(1 for j in bad if not np.array_equal(cols[k].get(j, none), cols["per_tier"].get(j, none)))
+           for k in ("plain", "batched")}
+    return f"{len(bad)} columns differ (first {bad[:5]}); columns where each form differs from the per-tier run: {odd}"
+
+
+def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
+    """One Sparse SUMMA process's share: 64 stage products of DCSC blocks, merged."""
+    from paper_1006_2183_amd import batched as BT
+    sr = "plus_times_f64"
+    log(f"[bench] SUMMA share: R-MAT scale {scale}, {grid}x{grid} grid, process (0,0)")
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=sr, seed=seed, device="cuda", fmt="dcsc")
+    dA = [sg.DevMat.from_host(x, "cuda", sr) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", sr) for x in b_blocks]
+    nnz_blocks = [x.nnz for x in a_blocks]
+    del a_blocks, b_blocks
+    torch.cuda.empty_cache()
+    res = {}
+
+    def plain():
+        parts = [sg.spgemm(sr, a, b, out_fmt="dcsc") for a, b in zip(dA, dB)]
+        res["plain"] = BT.merge_partials(sr, parts)
+
+    def batched():
+        res["batched"] = BT.summa_share(sr, dA, dB, batched=True)
+
+    plain()
+    batched()
+    try:
+        _same(res["batched"], res["plain"], 1e-12, "SUMMA batched vs plain")
+    except AssertionError as e:
+        raise AssertionError(f"{e}; {_summa_diagnose(res, sg, dA, dB, sr)}")
+    plan = BT.summa_share_plan(sr, dA, dB)
+    flops = sum(i["flops"] for i in plan.infos)
+    nnz_c = plan.infos[0]["nnz"]
+    G = BT.GraphedNumeric(plan)
+    G.replay()
+    torch.cuda.synchronize()
+    _same(G.outputs[0], res["batched"], 0.0, "SUMMA graph replay vs batched")
+    ms_plain = _median_ms(torch, plain, reps)
+    ms_batched = _median_ms(torch, batched, reps)
+    ms_graph = _median_ms(torch, G.replay, max(reps, 5))
+    plan.profile(True)
+    sg.spgemm_batched(plan, G.outputs)
+    kms = plan.kernel_times()["heavy"]
+    algo = _tier_bytes(plan.infos, 8)
+    out = {
+        "workload": f"rmat_s{scale}_ef16_summa{grid}x{grid}_share_p00_f64",
+        "stages": len(dA), "nnz_blocks_min": int(min(nnz_blocks)), "nnz_blocks_max": int(max(nnz_blocks)),
+        "flops": int(flops), "nnz_C": int(nnz_c),
+        "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batched, 3), "graph_replay_ms": round(ms_graph, 3),
+        "plain_GFLOPs": round(flops / ms_plain / 1e6, 2), "batched_GFLOPs": round(flops / ms_batched / 1e6, 2),
+        "graph_GFLOPs": round(flops / ms_graph / 1e6, 2),
+        "batched_vs_plain": round(ms_plain / ms_batched, 2), "graph_vs_plain": round(ms_plain / ms_graph, 2),
+        "persistent_kernel": {"launch_ms": round(kms, 4), "algorithmic_bytes": int(algo),
+                              "achieved_GBs": round(algo / kms / 1e6, 1) if kms > 0 else None},
+        "plain": "64 x (symbolic + sync + alloc + per-tier numeric) into DCSC partials, then a 64-way merge",
+        "exact": "batched == plain (pattern exact, values within 1e-12 relative); graph replay == batched bitwise",
+    }
+    plan.destroy()
+    del G, res, dA, dB
+    torch.cuda.empty_cache()
+    return out
+
+
+def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
+    """R (A P) for uneven 3D Poisson instances, plain vs grouped vs graph, autotuned."""
+    from paper_1006_2183_amd import batched as BT
+    from paper_1006_2183_amd import autotune as AT
+    sr = "plus_times_f64"
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.choice([32, 48, 64, 96, 128], size=count)]
+    log(f"[bench] Galerkin R A P: {count} instances, grid sizes {sizes}")
+    host = {}
+    for n in sorted(set(sizes)):
+        L = W.laplacian_7pt(n, "csr")
+        P = W.aggregation_p(n, "csr")
+        host[n] = (L, P, W.transpose(P, "csr"))
+    dev = lambda M: sg.DevMat.from_host(M, "cuda")
+    Ls = [dev(host[n][0]) for n in sizes]
+    Ps = [dev(host[n][1]) for n in sizes]
+    Rs = [dev(host[n][2]) for n in sizes]
+    res = {}
+
+    def plain():
+        res["plain"] = [sg.spgemm(sr, R, sg.spgemm(sr, L, P)) for R, L, P in zip(Rs, Ls, Ps)]
+
+    def batched(tuning=None):
+        res["batched"] = BT.galerkin_rap(sr, Rs, Ls, Ps, batched=True, tuning=tuning)
+
+    plain()
+    batched()
+    for i, n in enumerate(sizes):
+        _same(res["batched"][i], res["plain"][i], 0.0, f"Galerkin instance {i}")
+        if i < len(set(sizes)) or i == count - 1:
+            Lc = W.laplacian_7pt(n // 2, "csr")
+            got = res["batched"][i].to_host()
+            if not (np.array_equal(got.ptr, Lc.ptr) and np.array_equal(got.idx, Lc.idx)
+                    and np.array_equal(got.val, 4.0 * Lc.val)):
+                raise AssertionError(f"Galerkin instance {i}: R A P != 4 L_(n/2)")
+    plan_ap, AP, plan_rap = BT.galerkin_plans(sr, Rs, Ls, Ps)
+    flops = sum(i["flops"] for i in plan_ap.infos) + sum(i["flops"] for i in plan_rap.infos)
+    # tune the two grouped products (the persistent launch), then time with the tuned setting
+    t_ap = AT.autotune(sr, Ls, Ps, list(range(count)), count, form="batched", reps=2)
+    t_rap = AT.autotune(sr, Rs, AP, list(range(count)), count, form="batched", reps=2)
+    tun_ap = sg.make_tuning(sr, **t_ap["tuning"])
+    tun_rap = sg.make_tuning(sr, **t_rap["tuning"])
+
+    def tuned():
+        APt = sg.spgemm_grouped(sr, Ls, Ps, list(range(count)), count, tuning=tun_ap, batched=True)
+        res["tuned"] = sg.spgemm_grouped(sr, Rs, APt, list(range(count)), count, tuning=tun_rap, batched=True)
+
+    tuned()
+    for i in range(count):
+        _same(res["tuned"][i], res["plain"][i], 0.0, f"Galerkin tuned instance {i}")
+    G = BT.GraphedNumeric([plan_ap, plan_rap], [AP, None])
+    G.replay()
+    torch.cuda.synchronize()
+    for i in range(count):
+        _same(G.outputs[i], res["plain"][i], 0.0, f"Galerkin graph instance {i}")
+    ms_plain = _median_ms(torch, plain, reps)
+    ms_batched = _median_ms(torch, batched, reps)
+    ms_tuned = _median_ms(torch, tuned, reps)
+    ms_graph = _median_ms(torch, G.replay, max(reps, 5))
+    out = {
+        "workload": f"galerkin_rap_7pt_{count}_instances_n_in_32_48_64_96_128_f64",
+        "sizes": sizes, "flops": int(flops),
+        "nnz_RAP": int(sum(i["nnz"] for i in plan_rap.infos)),
+        "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batched, 3), "tuned_ms": round(ms_tuned, 3),
+        "graph_replay_ms": round(ms_graph, 3),
+        "plain_GFLOPs": round(flops / ms_plain / 1e6, 2), "batched_GFLOPs": round(flops / ms_batched / 1e6, 2),
+        "tuned_GFLOPs": round(flops / ms_tuned / 1e6, 2), "graph_GFLOPs": round(flops / ms_graph / 1e6, 2),
+        "batched_vs_plain": round(ms_plain / ms_batched, 2), "graph_vs_plain": round(ms_plain / ms_graph, 2),
+        "autotune": {"ap": {"tuning": t_ap["tuning"], "ms": round(t_ap["ms"], 3),
+                            "default_ms": round(t_ap["default_ms"], 3), "tried": t_ap["tried"]},
+                     "rap": {"tuning": t_rap["tuning"], "ms": round(t_rap["ms"], 3),
+                             "default_ms": round(t_rap["default_ms"], 3), "tried": t_rap["tried"]}},
+        "plain": "per instance: symbolic + sync + alloc + numeric for A P, then for R (A P)",
+        "exact": "plain == grouped == tuned == graph bitwise; R A P == 4 L_(n/2) checked on one instance per size",
+    }
+    plan_ap.destroy()
+    plan_rap.destroy()
+    del G, res, Ls, Ps, Rs, AP
+    torch.cuda.empty_cache()
+    return out
+
+
+def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
+    """Served multi-source expansions Y = A X ((or, and)), Poisson arrivals; batched server vs FIFO."""
+    from paper_1006_2183_amd import serve as SV
+    sr = "or_and_bool"
+    log(f"[bench] serving: R-MAT scale {scale} bool resident, {count} requests per QPS level {qps_list}")
+    A = W.rmat_matrix(scale, 16, sr, "csc", seed=seed, device="cuda")
+    dA = sg.DevMat.from_host(A, "cuda", sr)
+    colcount = np.diff(A.ptr)
+    rng = np.random.default_rng(seed + 100)
+    ks = rng.integers(1, 513, size=count)
+    Xs, srcs = [], []
+    for i, k in enumerate(ks):
+        X = W.bfs_frontier(A.nrows, int(k), seed=1000 + i)
+        Xs.append(X)
+        srcs.append(X.idx.astype(np.int64))  # depth 0: X(:, s) holds only source s
+    dX = [sg.DevMat.from_host(X, "cuda", sr) for X in Xs]
+    ubs = [SV.frontier_bound(colcount, X) for X in Xs]
+    out = {"workload": f"rmat_s{scale}_ef16_bool_csc_resident_bfs_depth0_k_U1_512", "requests": count,
+           "request_flops_p50": float(np.percentile(ubs, 50)), "request_flops_p99": float(np.percentile(ubs, 99)),
+           "levels": []}
+    # warm both paths
+    SV.Scheduler(SV.GpuBatchExecutor(sr, dA), 1 << 26).run([SV.Request(0, 0.0, dX[0], ubs[0])])
+    SV.Scheduler(SV.FifoExecutor(sr, dA), 1 << 26).run([SV.Request(0, 0.0, dX[0], ubs[0])])
+    torch.cuda.synchronize()
+
+    def check(done):
+        # depth-0 closed form: Y(:, s) is the pattern of A(:, src_s)
+        for r in done:
+            Y = r.result.to_host() if not isinstance(r.result, list) else r.result[0].to_host()
+            src = srcs[r.rid]
+            for s_ in range(len(src)):
+                ref = A.idx[A.ptr[src[s_]]:A.ptr[src[s_] + 1]]
+                if not np.array_equal(Y.idx[Y.ptr[s_]:Y.ptr[s_ + 1]], ref):
+                    raise AssertionError(f"request {r.rid} column {s_} differs from A(:, src)")
+
+    for qps in qps_list:
+        arr = W.poisson_arrivals(qps, count, seed=int(qps))
+        line = {"qps": qps}
+        for name, ex, mb in (("batched", SV.GpuBatchExecutor(sr, dA), 64), ("fifo", SV.FifoExecutor(sr, dA), 1)):
+            reqs = [SV.Request(i, float(arr[i]), dX[i], ubs[i]) for i in range(count)]
+            sched = SV.Scheduler(ex, pool_entries=1 << 26, max_batch=mb, max_inflight=2 if mb > 1 else 1)
+            done = sched.run(reqs)
+            torch.cuda.synchronize()
+            st = SV.latency_stats(done)
+            check([r for r in done if r.status == "done"])
+            line[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            line[name]["launches"] = sched.batches
+            log(f"[bench] serving qps {qps} {name}: {line[name]}")
+        out["levels"].append(line)
+    out["exact"] = "every served column equals the pattern of A(:, src) (depth-0 closed form), both servers"
+    del dA, dX
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Counter ingestion: HBM bytes per launch from rocprofv3 --pmc passes
+
+def _counter_rows(d):
+    """(kernel name, counter name, value) of every dispatch in a rocprofv3 --pmc CSV under d."""
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(d):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                with open(os.path.join(dirpath, f)) as fh:
+                    for r in csv.DictReader(fh):
+                        rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]),
+                                     r.get("Dispatch_Id", "")))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def ingest_counters(root, copy_mib, workload, semiring):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the numeric heavy kernel by the
+    ratio the same counters read for a device copy of known size; write profiles/hbm_traffic.json."""
+    import re
+    copy_bytes = copy_mib * (1 << 20)
+    factors = {}
+    for ctr, sub in (("FETCH_SIZE", "cal_fetch"), ("WRITE_SIZE", "cal_write")):
+        vals = [v for k, c, v, _ in _counter_rows(os.path.join(root, sub)) if c == ctr and "copy" in k.lower()]
+        if not vals:
+            raise SystemExit(f"no copy kernel dispatch in {sub}")
+        factors[ctr] = copy_bytes / (float(np.median(vals)) * 1024.0)
+    per = {}
+    pat = re.compile(r"k_heavy<\d+, false")
+    for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        vals = [v for k, c, v, _ in _counter_rows(os.path.join(root, sub)) if c == ctr and pat.search(k)]
+        if not vals:
+            raise SystemExit(f"no numeric k_heavy dispatch in {sub}")
+        per[ctr] = float(np.mean(vals)) * 1024.0 * factors[ctr]
+    entry = {"kernel_hash": kernel_source_hash(), "bytes_per_launch": int(per["FETCH_SIZE"] + per["WRITE_SIZE"]),
+             "fetch_bytes": int(per["FETCH_SIZE"]), "write_bytes": int(per["WRITE_SIZE"]),
+             "copy_scale": {k: round(v, 4) for k, v in factors.items()}, "copy_mib": copy_mib}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    d = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            d = json.load(f)
+    d[f"{workload}/{semiring}/k_heavy"] = entry
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(json.dumps(entry))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,9 +485,25 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tuning", default=None, help="JSON object of sg_tuning overrides")
+    ap.add_argument("--no-suite", action="store_true",
+                    help="skip the batched (SUMMA share, Galerkin) and served measurements")
+    ap.add_argument("--suite-reps", type=int, default=3)
+    ap.add_argument("--only", choices=["summa", "galerkin", "serving"], default=None,
+                    help="run one of the batched/served measurements alone and print its JSON object")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-qps", default="500,2000,8000")
+    ap.add_argument("--ingest-counters", default=None,
+                    help="directory holding fetch/, write/, cal_fetch/, cal_write/ rocprofv3 --pmc outputs: "
+                         "write the measured HBM bytes per heavy launch to profiles/hbm_traffic.json and exit")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="run only a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters, args.copy_mib, f"rmat_s{args.scale}_ef{args.edge_factor}_AxA_plain",
+                        args.semiring)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -211,6 +529,14 @@ def main():
     import paper_1006_2183_amd as sg
     import workloads as W
     sg.load_library()
+
+    suites = {"summa": ("batched_summa", lambda: suite_summa(sg, torch, W, args.suite_reps)),
+              "galerkin": ("batched_galerkin", lambda: suite_galerkin(sg, torch, W, args.suite_reps)),
+              "serving": ("serving", lambda: suite_serve(sg, torch, W, args.serve_requests,
+                                                         [float(q) for q in args.serve_qps.split(",")]))}
+    if args.only:
+        print(json.dumps({suites[args.only][0]: suites[args.only][1]()}), flush=True)
+        return
 
     tune_kw = json.loads(args.tuning) if args.tuning else {}
     workload = f"rmat_s{args.scale}_ef{args.edge_factor}_AxA_plain"
@@ -298,6 +624,14 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample")
         out["cpu_baseline"] = cpu_baseline(args.semiring, A_main, info["flops"], args.cpu_seconds)
+    if not args.no_suite:
+        for name, fn in suites.values():
+            t = time.perf_counter()
+            try:
+                out[name] = fn()
+            except (AssertionError, sg.SgError, RuntimeError) as e:
+                out[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] {name}: {time.perf_counter() - t:.1f} s")
     print(json.dumps(out), flush=True)
 
 

@@ -9,9 +9,9 @@
   (C = (+)_k I C_k column-major), a k-way merge on the same accumulators.
 * ``galerkin_rap``: R (A P) for many uneven instances (graph contraction and
   multigrid coarsening, Section 6.2.3), two grouped plans (A P, then R (AP)).
-* ``GraphedNumeric``: captures the persistent batched launch of a plan in a
-  HIP graph; each replay recomputes the outputs from the current operand
-  values (same structure), with no host work.
+* ``GraphedNumeric``: captures the persistent batched launches of one plan
+  or a chain of plans in a HIP graph; each replay recomputes the outputs
+  from the current operand values (same structure), with no host work.
 
 All arithmetic runs in the HIP library; this module arranges plans and
 PyTorch-owned buffers.
@@ -82,27 +82,56 @@ def galerkin_rap(semiring: str, Rs: Sequence[DevMat], As: Sequence[DevMat], Ps: 
                             stream=stream)
 
 
-class GraphedNumeric:
-    """A plan's persistent batched launch captured in a HIP graph (torch.cuda.CUDAGraph).
+def galerkin_plans(semiring: str, Rs: Sequence[DevMat], As: Sequence[DevMat], Ps: Sequence[DevMat], tuning=None,
+                   stream=None):
+    """Plans of the two grouped products of ``galerkin_rap`` for repeated numeric phases.
 
-    The outputs are allocated once; ``replay()`` recomputes them from the
-    current values of the operands the plan was built on.
+    Returns (plan_ap, ap_outputs, plan_rap): the second plan reads the first
+    plan's outputs, so running the two persistent launches in order (or
+    replaying them in one graph) recomputes R (A P) from the current values.
+    """
+    n = len(As)
+    plan_ap = B.spgemm_symbolic(semiring, list(As), list(Ps), list(range(n)), n, tuning=tuning, stream=stream)
+    AP = plan_ap.alloc_outputs(As[0].ptr.device)
+    B.spgemm_batched(plan_ap, AP, stream)
+    plan_rap = B.spgemm_symbolic(semiring, list(Rs), AP, list(range(n)), n, tuning=tuning, stream=stream)
+    return plan_ap, AP, plan_rap
+
+
+class GraphedNumeric:
+    """The persistent batched launches of one or more plans captured in one HIP graph
+    (torch.cuda.CUDAGraph), in order.
+
+    The outputs are allocated once (or passed in: a later plan may read an
+    earlier plan's outputs, as R (A P) reads A P); ``replay()`` recomputes
+    them from the current values of the operands the plans were built on.
     """
 
-    def __init__(self, plan: B.Plan, outputs: Optional[List[DevMat]] = None):
+    def __init__(self, plans, outputs: Optional[List[List[DevMat]]] = None):
         import torch
-        self.plan = plan
-        self.outputs = outputs if outputs is not None else plan.alloc_outputs(plan.As[0].ptr.device)
+        self.plans = list(plans) if isinstance(plans, (list, tuple)) else [plans]
+        if outputs is None:
+            outputs = [None] * len(self.plans)
+        elif isinstance(outputs[0], DevMat):
+            outputs = [outputs]
+        self.outs = [o if o is not None else p.alloc_outputs(p.As[0].ptr.device) for p, o in zip(self.plans, outputs)]
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            B.spgemm_batched(plan, self.outputs, side)  # warm-up outside the capture
+            for p, o in zip(self.plans, self.outs):
+                B.spgemm_batched(p, o, side)  # warm-up outside the capture
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            B.spgemm_batched(plan, self.outputs, torch.cuda.current_stream())
+            for p, o in zip(self.plans, self.outs):
+                B.spgemm_batched(p, o, torch.cuda.current_stream())
+
+    @property
+    def outputs(self) -> List[DevMat]:
+        return self.outs[-1]
 
     def replay(self) -> List[DevMat]:
+        """Replays the graph; returns the last plan's outputs."""
         self.graph.replay()
-        return self.outputs
+        return self.outs[-1]

@@ -152,3 +152,55 @@ def test_graph_replay_tracks_values(sg):
         R, _ = oracle.spgemm(semiring, SA, SB)
         assert_same(got, R, semiring, 1e-12, f"replay {rep} vs oracle")
     plan.destroy()
+
+
+def test_galerkin_graph_chain_replay(sg):
+    """A P then R (A P) captured in one graph: after scaling the operator by f,
+    every replay gives R (f L_n) P = 4 f L_{n/2} exactly."""
+    import torch
+    from paper_1006_2183_amd import batched as BT
+    sizes = [4, 8, 6, 12, 10, 8]
+    Ls = [W.laplacian_7pt(n, "csr") for n in sizes]
+    Ps = [W.aggregation_p(n, "csr") for n in sizes]
+    Rs = [W.transpose(P, "csr") for P in Ps]
+    dev = lambda M: sg.DevMat.from_host(M, "cuda")
+    dL = [dev(L) for L in Ls]
+    plan_ap, AP, plan_rap = BT.galerkin_plans("plus_times_f64", [dev(R) for R in Rs], dL, [dev(P) for P in Ps])
+    G = BT.GraphedNumeric([plan_ap, plan_rap], [AP, None])
+    total = 1.0
+    for rep, f in enumerate([2.0, 0.5, 4.0]):
+        for m in dL:
+            m.val.mul_(f)
+        total *= f
+        torch.cuda.synchronize()
+        out = G.replay()
+        torch.cuda.synchronize()
+        for i, n in enumerate(sizes):
+            Lc = W.laplacian_7pt(n // 2, "csr")
+            Lc.val = Lc.val * (4.0 * total)
+            assert_same(out[i].to_host(), Lc, "plus_times_f64", 0.0, f"replay {rep} instance {i}")
+    plan_ap.destroy()
+    plan_rap.destroy()
+
+
+def test_autotune_keeps_results(sg, tmp_path):
+    """Every setting the tuner tries computes the same product; the cache round-trips."""
+    import torch
+    from paper_1006_2183_amd import autotune as AT
+    semiring = "min_plus_i32"
+    A = W.rmat_matrix(11, 16, semiring, "csr", seed=3)
+    dA = sg.DevMat.from_host(A, "cuda", semiring)
+    R, _ = oracle.spgemm(semiring, A, A)
+    cache = AT.TuneCache(str(tmp_path / "tune.json"))
+    space = {"lds_bytes": [16384, 65536], "blocks_per_cu": [1, 3], "tiny_max_flops": [16]}
+    res = AT.autotune(semiring, [dA], [dA], space=space, reps=1, cache=cache)
+    assert not res["cached"] and res["tried"] >= 2
+    again = AT.autotune(semiring, [dA], [dA], space=space, reps=1, cache=AT.TuneCache(str(tmp_path / "tune.json")))
+    assert again["cached"] and again["tuning"] == res["tuning"]
+    t = AT.tuned(semiring, [dA], [dA], cache=cache)
+    C = sg.spgemm(semiring, dA, dA, tuning=t).to_host()
+    assert_same(C, R, semiring, 0.0, "tuned")
+    for cand in ({"lds_bytes": 16384}, {"blocks_per_cu": 3, "tiny_max_flops": 16}):
+        C = sg.spgemm(semiring, dA, dA, tuning=sg.make_tuning(semiring, **cand)).to_host()
+        assert_same(C, R, semiring, 0.0, str(cand))
+    torch.cuda.synchronize()

@@ -150,7 +150,7 @@ def test_gpu_alone_equals_mix():
         hostX.append(X)
         reqs.append(Request(i, float(arr[i]), sg.DevMat.from_host(X, "cuda", "or_and_bool"), frontier_bound(colcount, X)))
     ex = GpuBatchExecutor("or_and_bool", dA)
-    sched = Scheduler(ex, pool_entries=400000, max_batch=8, max_inflight=2)
+    sched = Scheduler(ex, pool_entries=1 << 24, max_batch=8, max_inflight=2)
     done = sched.run(reqs)
     torch.cuda.synchronize()
     assert all(r.status == "done" for r in done)
@@ -163,3 +163,4 @@ def test_gpu_alone_equals_mix():
             R, _ = oracle.spgemm("or_and_bool", A, hostX[r.rid])
             assert_same(mix, R, "or_and_bool")
     print(latency_stats(done), flush=True)
+
