@@ -68,6 +68,19 @@ struct GroupDev {
   int64_t nz_base;       // global count of non-empty vectors before the group
 };
 
+// One heavy-tier item: the window of split buckets [b0, b1) of output
+// vector v (position q in the heavy list) of group g, whose entries start at
+// `pos` inside the group's output arrays.
+struct ItemDev {
+  int32_t v;
+  int32_t g;
+  int32_t b0;
+  int32_t b1;
+  int64_t pos;
+  int32_t q;
+  int32_t pad;
+};
+
 struct OutDev {
   int64_t *ptr;
   int32_t *vid;
@@ -126,10 +139,7 @@ struct Plan {
   const int32_t *tiny_list;
   const int32_t *mid_list;
   const int32_t *heavy_list;
-  const int32_t *item_vec;   // heavy item -> position in heavy_list
-  const int32_t *item_b0;    // heavy item -> first split bucket
-  const int32_t *item_b1;    // heavy item -> one past the last split bucket
-  const int64_t *item_off;   // heavy item -> offset of its entries inside its vector
+  const struct ItemDev *items;  // heavy (vector, window) items
   int32_t *bcnt;             // heavy vector q: entries per split bucket, at q * nbmax
   int32_t nbmax;             // largest nsplit of any group
   int32_t nrange;            // XCD ranges (8 per XCD share, or 1 when ranges are off)
@@ -223,6 +233,35 @@ __device__ __forceinline__ T gload(const T *p) {
 template <class T>
 __device__ __forceinline__ void gstore(T *p, T v) {
   *(SG_GLOBAL T *)p = v;
+}
+
+// Wave-uniform reads of descriptors and index arrays that no running kernel
+// writes (they are filled by earlier launches): through the constant address
+// space a load with a wave-uniform address becomes a scalar load, issued once
+// per wavefront and served by the scalar cache, instead of a chain of vector
+// loads each followed by a wait. Read-only: nothing is ever stored this way.
+#define SG_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ T uload(const T *p) {
+  if constexpr (__is_scalar(T)) {
+    return *(const SG_CONST T *)p;
+  } else {  // descriptor structs: word by word (merged into wide scalar loads)
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    T out;
+    uint32_t *o = (uint32_t *)&out;
+    const SG_CONST uint32_t *q = (const SG_CONST uint32_t *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
+    return out;
+  }
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Marks a value the caller knows to be wave-uniform (lane 0's copy is taken).
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // ---------------------------------------------------------------------------

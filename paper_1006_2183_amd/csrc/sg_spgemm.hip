@@ -205,8 +205,8 @@ struct Layout {
   int64_t *ov_seg, *ov_flops, *ov_cnt, *ov_off, *nzflag, *nzpos;
   int32_t *tiny, *mid, *heavy;
   int64_t *heavy_nwin, *ibase;
-  int32_t *item_vec, *item_b0, *item_b1, *bcnt;
-  int64_t *item_off;
+  ItemDev *items;
+  int32_t *bcnt;
   std::vector<int32_t *> gres, aux, wsplit;
   std::vector<int64_t> aux_chunk, aux_n;
   int64_t *dbase, *dcnt, *dflag, *vpos, *spos, *dfill;
@@ -366,11 +366,8 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.heavy_nwin = c.take<int64_t>(nov * sh.nrange + 1);
   L.ibase = c.take<int64_t>(nov * sh.nrange + 1);
   const int64_t items = nov * (int64_t)sh.nbmax;
-  L.item_vec = c.take<int32_t>(items);
-  L.item_b0 = c.take<int32_t>(items);
-  L.item_b1 = c.take<int32_t>(items);
+  L.items = c.take<ItemDev>(items);
   L.bcnt = c.take<int32_t>(items);
-  L.item_off = c.take<int64_t>(items);
   L.gres.assign(nprod, nullptr);
   L.aux.assign(nprod, nullptr);
   L.wsplit.assign(nprod, nullptr);
@@ -873,10 +870,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   P.tiny_list = L.tiny;
   P.mid_list = L.mid;
   P.heavy_list = L.heavy;
-  P.item_vec = L.item_vec;
-  P.item_b0 = L.item_b0;
-  P.item_b1 = L.item_b1;
-  P.item_off = L.item_off;
+  P.items = L.items;
   P.bcnt = L.bcnt;
   P.nbmax = sh.nbmax;
   P.nrange = sh.nrange;
@@ -921,9 +915,6 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
                      sh.nov_max, L.heavy_nwin);
   SG_HIP(hipGetLastError());
   SG_TRY(scan64(L.heavy_nwin, sh.nov_max * sh.nrange, L.ibase, L.part, st));
-  hipLaunchKernelGGL(k_plan_fill, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
-                     L.ibase, sh.nov_max, L.item_vec, L.item_b0, L.item_b1, L.item_off, L.counters);
-  SG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tier_nnz, dim3((unsigned)std::min<int64_t>(grid_for(sh.nov_max, 256), 1024)), dim3(256), 0, st, P,
                      L.counters);
   SG_HIP(hipGetLastError());
@@ -934,6 +925,11 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   SG_TRY(scan64(L.nzflag, sh.nov_max, L.nzpos, L.part, st));
   hipLaunchKernelGGL(k_group_totals, dim3((unsigned)grid_for(ngroup, 64)), dim3(64), 0, st, L.groups, ngroup,
                      L.ov_off, L.nzpos, L.gstat);
+  SG_HIP(hipGetLastError());
+  // the window items carry their absolute output positions, so they are
+  // filled once the vector offsets and the group bases are known
+  hipLaunchKernelGGL(k_plan_fill, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                     L.ibase, sh.nov_max, L.items, L.counters);
   SG_HIP(hipGetLastError());
 
   SG_HIP(hipMemcpyAsync(pl->host_stats, L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount, hipMemcpyDeviceToHost,

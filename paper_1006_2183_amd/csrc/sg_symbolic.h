@@ -224,12 +224,13 @@ __global__ void k_flops(Plan P, int64_t *gstat) {
   const int64_t nov = P.counters[kCtNov];
   int32_t cur_g = -1;
   int64_t acc_f = 0, acc_ub = 0, acc_max = 0;
-  for (int64_t v = wave; v < nov; v += nwaves) {
+  for (int64_t v = uni(wave); v < nov; v += nwaves) {
     int64_t f = 0;
-    for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
-      const ProdDev &d = P.prods[P.seg_prod[s]];
-      int32_t t = P.seg_svec[s];
-      int64_t e0 = d.s_ptr[t], e1 = d.s_ptr[t + 1];
+    const int64_t s1 = uload(P.ov_seg + v + 1);
+    for (int64_t s = uload(P.ov_seg + v); s < s1; ++s) {
+      const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+      const int32_t t = uload(P.seg_svec + s);
+      const int64_t e0 = uload(d.s_ptr + t), e1 = uload(d.s_ptr + t + 1);
       for (int64_t e = e0 + l; e < e1; e += kWave) {
         int32_t k = d.s_idx[e];
         int32_t gt;
@@ -243,7 +244,7 @@ __global__ void k_flops(Plan P, int64_t *gstat) {
       }
     }
     f = wave_sum64(f);
-    int32_t g = P.ov_group[v];
+    const int32_t g = uload(P.ov_group + v);
     if (l == 0) P.ov_flops[v] = f;
     if (g != cur_g) {
       if (cur_g >= 0 && l == 0) {
@@ -254,7 +255,7 @@ __global__ void k_flops(Plan P, int64_t *gstat) {
       cur_g = g;
       acc_f = acc_ub = acc_max = 0;
     }
-    int64_t minor = P.groups[g].minor;
+    const int64_t minor = uload(&P.groups[g].minor);
     acc_f += f;
     acc_ub += f < minor ? f : minor;
     acc_max = f > acc_max ? f : acc_max;
@@ -426,11 +427,13 @@ __global__ void k_plan_count(Plan P, int64_t cap, int64_t *nwin_out) {
   }
 }
 
-__global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, int32_t *item_vec, int32_t *item_b0,
-                            int32_t *item_b1, int64_t *item_off, int64_t *counters) {
+__global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, ItemDev *items, int64_t *counters) {
   const int64_t nh = counters[kCtHeavy];
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
-    const GroupDev &G = P.groups[P.ov_group[P.heavy_list[q]]];
+    const int32_t v = P.heavy_list[q];
+    const int32_t g = P.ov_group[v];
+    const GroupDev &G = P.groups[g];
+    const int64_t base = P.ov_off[v] - G.nnz_base;
     const int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
     int64_t before = 0;
     for (int r = 0; r < P.nrange; ++r) {
@@ -438,10 +441,15 @@ __global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, int32_t *
       range_buckets(G, r, bs, be);
       int64_t i = ibase[r * cap + q];
       plan_windows(G, bc, bs, be, before, [&](int32_t b0, int32_t b1, int64_t bef) {
-        item_vec[i] = (int32_t)q;
-        item_b0[i] = b0;
-        item_b1[i] = b1;
-        item_off[i] = bef;
+        ItemDev it;
+        it.v = v;
+        it.g = g;
+        it.b0 = b0;
+        it.b1 = b1;
+        it.pos = base + bef;
+        it.q = (int32_t)q;
+        it.pad = 0;
+        items[i] = it;
         ++i;
       });
       for (int32_t b = bs; b < be; ++b) before += bc[b];
@@ -497,7 +505,7 @@ __global__ void k_emit_ptr_doubly(Plan P, const int64_t *nzpos, int32_t ngroup) 
       continue;
     }
     if (P.ov_cnt[v] == 0) continue;
-    int32_t g = P.ov_group[v];
+    const int32_t g = uload(P.ov_group + v);
     const GroupDev &G = P.groups[g];
     int64_t pos = nzpos[v] - G.nz_base;
     P.outs[g].vid[pos] = P.ov_id[v];

@@ -2,11 +2,12 @@
 // (exact size of an output vector or window) and a numeric variant (writes
 // the sorted ids and accumulated values):
 //
-//   tiny   one wavefront per output vector with at most 64 multiplications:
-//          the products are placed one per lane, sorted by id with a
-//          register bitonic network, and equal ids are merged by a
-//          segmented reduction (the multiway merge of Section 2.4, done on
-//          64 lanes instead of a heap);
+//   tiny   output vectors with at most 64 multiplications: the products
+//          are placed one per lane, sorted by id with a register bitonic
+//          network, and equal ids are merged by a segmented reduction (the
+//          multiway merge of Section 2.4, done on 64 lanes instead of a
+//          heap); several small vectors share one wavefront pass, sorted by
+//          (vector, id);
 //   mid    one workgroup per vector whose size bound fits in LDS:
 //          bitmap-rank accumulator (a bit per output id marks the pattern,
 //          a prefix count per 32-bit word turns an id into its rank, so the
@@ -151,12 +152,12 @@ __device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t 
 template <class SR, class Act>
 __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, int b1, int wid, int nw, Act &act) {
   typedef typename SR::T T;
-  const int64_t s0 = P.ov_seg[v], s1 = P.ov_seg[v + 1];
+  const int64_t s0 = uload(P.ov_seg + v), s1 = uload(P.ov_seg + v + 1);
   for (int64_t s = s0; s < s1; ++s) {
-    const ProdDev &d = P.prods[P.seg_prod[s]];
-    const int32_t t = P.seg_svec[s];
-    const int64_t e1 = d.s_ptr[t + 1];
-    for (int64_t eb = d.s_ptr[t]; eb < e1; eb += kWave) {
+    const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+    const int32_t t = uload(P.seg_svec + s);
+    const int64_t e1 = uload(d.s_ptr + t + 1);
+    for (int64_t eb = uload(d.s_ptr + t); eb < e1; eb += kWave) {
       int len;
       int64_t gb;
       T sv;
@@ -176,7 +177,7 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
 }
 
 __device__ __forceinline__ int64_t out_offset(const Plan &P, int64_t v) {
-  return P.ov_off[v] - P.groups[P.ov_group[v]].nnz_base;
+  return uload(P.ov_off + v) - uload(&P.groups[uload(P.ov_group + v)].nnz_base);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,12 +190,12 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
   int key = INT32_MAX;
   T val = T();
   int filled = 0;
-  const int64_t s0 = P.ov_seg[v], s1 = P.ov_seg[v + 1];
+  const int64_t s0 = uload(P.ov_seg + v), s1 = uload(P.ov_seg + v + 1);
   for (int64_t s = s0; s < s1; ++s) {
-    const ProdDev &d = P.prods[P.seg_prod[s]];
-    const int32_t t = P.seg_svec[s];
-    const int64_t e1 = d.s_ptr[t + 1];
-    for (int64_t eb = d.s_ptr[t]; eb < e1; eb += kWave) {
+    const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+    const int32_t t = uload(P.seg_svec + s);
+    const int64_t e1 = uload(d.s_ptr + t + 1);
+    for (int64_t eb = uload(d.s_ptr + t); eb < e1; eb += kWave) {
       int len;
       int64_t gb;
       T sv;
@@ -250,10 +251,147 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
   }
   if (head) {
     const int r = __popcll(hm & ((1ull << l) - 1ull));
-    const OutDev &O = P.outs[P.ov_group[v]];
+    const OutDev O = uload(P.outs + uload(P.ov_group + v));
     const int64_t pos = out_offset(P, v) + r;
     gstore(O.idx + pos, key);
     if (SR::kVal) gstore((T *)O.val + pos, val);
+  }
+}
+
+// Tiny tier, packed: one wavefront takes tiny-list positions [c0, c1) (at
+// most 64 vectors). Vectors with a single segment of the chunk's first
+// product whose streamed entries fit the wave are packed: each round takes
+// consecutive such vectors while their multiplications and their streamed
+// entries each fit 64 lanes, places one streamed entry per lane, then one
+// product per lane tagged with its vector's lane, sorts the 64 lanes by
+// (vector, id), merges equal keys and writes each vector's run at its own
+// offset. A vector with 7 multiplications thus costs a ninth of a
+// wavefront pass instead of a whole one. The remaining vectors (several
+// segments, another product, more than 64 streamed entries) take the
+// one-vector path above.
+__device__ __forceinline__ uint64_t lane_range(int a, int b) {
+  const uint64_t hi = b >= kWave ? ~0ull : ((1ull << b) - 1ull);
+  const uint64_t lo = a >= kWave ? ~0ull : ((1ull << a) - 1ull);
+  return hi & ~lo;
+}
+
+template <int K, bool COUNT>
+__device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  const int l = lane();
+  const bool has = c0 + l < c1;
+  int64_t v = -1;
+  int32_t p = -1, t = 0;
+  int f = 0;
+  if (has) {
+    v = gload(P.tiny_list + c0 + l);
+    const int64_t s0 = gload(P.ov_seg + v), s1 = gload(P.ov_seg + v + 1);
+    f = (int)gload(P.ov_flops + v);
+    if (s1 - s0 == 1) {
+      p = gload(P.seg_prod + s0);
+      t = gload(P.seg_svec + s0);
+    }
+  }
+  const uint64_t hasp = __ballot(p >= 0);
+  bool pack = false;
+  int64_t e0 = 0;
+  int ne = 0;
+  if (hasp) {
+    const int32_t p0 = __builtin_amdgcn_readlane(p, __ffsll((unsigned long long)hasp) - 1);
+    const ProdDev d = uload(P.prods + p0);
+    if (p == p0) {
+      e0 = gload(d.s_ptr + t);
+      ne = (int)(gload(d.s_ptr + t + 1) - e0);
+      pack = ne <= kWave && f <= kWave;
+    }
+    const int fp = pack ? f : 0, np = pack ? ne : 0;
+    const int Finc = wave_incl_scan(fp), Einc = wave_incl_scan(np);
+    const OutDev O = uload(P.outs + d.group);
+    int64_t opos = 0;
+    if (!COUNT && pack) opos = gload(P.ov_off + v) - uload(&P.groups[d.group].nnz_base);
+    uint64_t rem = __ballot(pack);
+    while (rem) {
+      const int first = __ffsll((unsigned long long)rem) - 1;
+      const int bf = __builtin_amdgcn_readlane(Finc - fp, first);
+      const int be = __builtin_amdgcn_readlane(Einc - np, first);
+      const uint64_t sel = __ballot(((rem >> l) & 1ull) && Finc - bf <= kWave && Einc - be <= kWave);
+      rem &= ~sel;
+      const int last = 63 - __clzll((long long)sel);
+      const int etot = __builtin_amdgcn_readlane(Einc, last) - be;
+      const int ftot = __builtin_amdgcn_readlane(Finc, last) - bf;
+      // one streamed entry per lane; j = the lane of its vector
+      const bool ent = l < etot;
+      const int j = owner_of(Einc - be, ent ? l : 0);
+      const int64_t ej = __shfl(e0, j, kWave) + (l - (__shfl(Einc - np, j, kWave) - be));
+      int len;
+      int64_t gb;
+      T sv;
+      load_entry<SR>(d, ej, ent ? ej + 1 : ej, -1, -1, len, gb, sv);
+      // one product per lane
+      const int Pinc = wave_incl_scan(len);
+      const int o = owner_of(Pinc, l < ftot ? l : 0);
+      const int64_t st = __shfl(gb - (int64_t)(Pinc - len), o, kWave);
+      const T so = __shfl(sv, o, kWave);
+      const int tag_o = __shfl(j, o, kWave);
+      uint64_t ck = ((uint64_t)kWave << 32) | 0x7fffffffull;
+      T val = T();
+      if (l < ftot) {
+        const int64_t g = st + l;
+        ck = ((uint64_t)tag_o << 32) | (uint32_t)gload(d.g_idx + g);
+        if (SR::kVal) val = SR::mul(so, gload((const T *)d.g_val + g));
+      }
+      // bitonic sort of (vector, id) across the 64 lanes
+#pragma unroll
+      for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+          const uint64_t pk = __shfl_xor(ck, jj, kWave);
+          const T pv = __shfl_xor(val, jj, kWave);
+          const bool up = (l & k) == 0;
+          const bool low = (l & jj) == 0;
+          const bool take = low ? (up ? pk < ck : pk > ck) : (up ? pk > ck : pk < ck);
+          if (take) {
+            ck = pk;
+            val = pv;
+          }
+        }
+      }
+      if (SR::kVal) {
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+          const uint64_t kd = __shfl_down(ck, dd, kWave);
+          const T vd = __shfl_down(val, dd, kWave);
+          if (l + dd < kWave && kd == ck) val = SR::add(val, vd);
+        }
+      }
+      const uint64_t prev = __shfl_up(ck, 1, kWave);
+      const int tag = (int)(ck >> 32);
+      const bool head = tag < kWave && (l == 0 || prev != ck);
+      const uint64_t hm = __ballot(head);
+      // vector lane x owns the sorted lanes [Finc_x - f_x - bf, Finc_x - bf)
+      const int seg_a = Finc - fp - bf;
+      if (COUNT) {
+        if ((sel >> l) & 1ull) gstore(P.ov_cnt + v, (int64_t)__popcll(hm & lane_range(seg_a, Finc - bf)));
+      } else {
+        const int src = tag < kWave ? tag : 0;
+        const int a = __shfl(seg_a, src, kWave);
+        const int64_t base = __shfl(opos, src, kWave);
+        if (head) {
+          const int64_t pos = base + __popcll(hm & lane_range(a, l));
+          gstore(O.idx + pos, (int32_t)(uint32_t)ck);
+          if (SR::kVal) gstore((T *)O.val + pos, val);
+        }
+      }
+    }
+  }
+  uint64_t fb = __ballot(has && !pack);
+  while (fb) {
+    const int x = __ffsll((unsigned long long)fb) - 1;
+    fb &= fb - 1ull;
+    const int64_t vx = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)((uint64_t)v >> 32), x) << 32) |
+                                 (uint32_t)__builtin_amdgcn_readlane((int32_t)v, x));
+    tiny_vector<K, COUNT>(P, vx);
   }
 }
 
@@ -288,6 +426,73 @@ struct RankAcc {
   }
 };
 
+// Kept bitmap words [0, nwds) of a window (src) into the rank accumulator.
+// The window is covered in passes of nt * kStage words; in a pass, thread t
+// owns `per` consecutive words (per a multiple of 4, at most kStage) and
+// stages them in registers, so all of its loads are in flight before the
+// first wait; popcounts, a block scan and the writes follow from registers.
+// With values (WS == 2) each word is written with its prefix (the count of
+// set bits before it in the window). Pattern only (out_idx set), the ids are
+// the result and are written straight to out_idx[rank]. Returns the count.
+template <int WS>
+__device__ __forceinline__ int64_t rank_load_kept(const uint32_t *src, int nwds, uint32_t *words, int64_t *scratch,
+                                                  int32_t *out_idx = nullptr, int lo32 = 0) {
+  constexpr int kStage = 16;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const bool vec = (((uintptr_t)src) & 15) == 0;
+  int64_t run_total = 0;
+  for (int base = 0; base < nwds; base += nt * kStage) {
+    const int rem = nwds - base;
+    int per = (rem + nt - 1) / nt;
+    per = (per + 3) & ~3;
+    if (per > kStage) per = kStage;
+    const int w0 = base + tid * per;
+    uint32_t r[kStage];
+#pragma unroll
+    for (int j = 0; j < kStage; j += 4) {
+      const int w = w0 + j;
+      if (j < per && w + 3 < nwds && vec) {
+        const u32x4 x = gload((const u32x4 *)(src + w));
+        r[j] = x.x;
+        r[j + 1] = x.y;
+        r[j + 2] = x.z;
+        r[j + 3] = x.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[j + k] = (j + k < per && w + k < nwds) ? gload(src + w + k) : 0u;
+      }
+    }
+    int local = 0;
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) local += __popc(r[j]);
+    int64_t total;
+    int64_t run = block_excl_scan(local, scratch, &total) + run_total;
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+      const int w = w0 + j;
+      if (j < per && w < nwds) {
+        if (out_idx) {
+          uint32_t b = r[j];
+          while (b) {
+            const int bit = __ffs(b) - 1;
+            b &= b - 1;
+            gstore(out_idx + run, lo32 + (w << 5) + bit);
+            ++run;
+          }
+        } else if (WS == 2) {
+          *(uint2 *)&words[2 * w] = make_uint2(r[j], (uint32_t)run);
+          run += __popc(r[j]);
+        } else {
+          words[w] = r[j];
+          run += __popc(r[j]);
+        }
+      }
+    }
+    run_total += total;
+  }
+  return run_total;
+}
+
 template <int K, bool COUNT>
 __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
                             uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr) {
@@ -301,57 +506,65 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   const int lo32 = (int)lo;
   uint32_t *words = lds;
   Slot *vals = (Slot *)(lds + WS * nwds);
+  const OutDev O = uload(P.outs + uload(P.ov_group + v));
 
-  if (kept) {  // the count pass kept this vector's bitmap: copy the window's words
-    const uint32_t *src = kept + (lo >> 5);
-    for (int w = tid; w < nwds; w += nt) words[WS * w] = gload(src + w);
+  if (!COUNT && kept) {
+    // the count pass kept this vector's bitmap: the window's words arrive
+    // with their prefixes, without a marking pass; pattern only, the kept
+    // bits are the result
+    if (!SR::kVal) {
+      rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch, O.idx + out_pos, lo32);
+      __syncthreads();
+      return;
+    }
+    rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
+    __syncthreads();
   } else {
     auto mark = step<T>([&](int id, T) {
       const int r = id - lo32;
       atomicOr(&words[WS * (r >> 5)], 1u << (r & 31));
     });
     for_products<SR>(P, v, b0, b1, wid, nw, mark);
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // per-thread contiguous word range
-  const int per = (nwds + nt - 1) / nt;
-  const int w0 = tid * per < nwds ? tid * per : nwds;
-  const int w1 = w0 + per < nwds ? w0 + per : nwds;
-  int local = 0;
-  for (int w = w0; w < w1; ++w) local += __popc(words[WS * w]);
-  int64_t total;
-  const int64_t excl = block_excl_scan(local, scratch, &total);
-  if (COUNT) {
-    for (int w = w0; w < w1; ++w) words[WS * w] = 0;
-    if (tid == 0) gstore(P.ov_cnt + v, total);
-    __syncthreads();
-    return;
-  }
-  const OutDev &O = P.outs[P.ov_group[v]];
-  if (!SR::kVal) {
-    int64_t r = out_pos + excl;
-    for (int w = w0; w < w1; ++w) {
-      uint32_t b = words[w];
-      while (b) {
-        const int bit = __ffs(b) - 1;
-        b &= b - 1;
-        gstore(O.idx + r, lo32 + (w << 5) + bit);
-        ++r;
+    // per-thread contiguous word range
+    const int per = (nwds + nt - 1) / nt;
+    const int w0 = tid * per < nwds ? tid * per : nwds;
+    const int w1 = w0 + per < nwds ? w0 + per : nwds;
+    int local = 0;
+    for (int w = w0; w < w1; ++w) local += __popc(words[WS * w]);
+    int64_t total;
+    const int64_t excl = block_excl_scan(local, scratch, &total);
+    if (COUNT) {
+      for (int w = w0; w < w1; ++w) words[WS * w] = 0;
+      if (tid == 0) gstore(P.ov_cnt + v, total);
+      __syncthreads();
+      return;
+    }
+    if (!SR::kVal) {
+      int64_t r = out_pos + excl;
+      for (int w = w0; w < w1; ++w) {
+        uint32_t b = words[w];
+        while (b) {
+          const int bit = __ffs(b) - 1;
+          b &= b - 1;
+          gstore(O.idx + r, lo32 + (w << 5) + bit);
+          ++r;
+        }
+        words[w] = 0;
       }
-      words[w] = 0;
+      __syncthreads();
+      return;
+    }
+    {
+      int run = (int)excl;
+      for (int w = w0; w < w1; ++w) {
+        words[WS * w + 1] = (uint32_t)run;
+        run += __popc(words[WS * w]);
+      }
     }
     __syncthreads();
-    return;
   }
-  {
-    int run = (int)excl;
-    for (int w = w0; w < w1; ++w) {
-      words[WS * w + 1] = (uint32_t)run;
-      run += __popc(words[WS * w]);
-    }
-  }
-  __syncthreads();
   RankAcc<SR> accum{words, vals, lo32};
   for_products<SR>(P, v, b0, b1, wid, nw, accum);
   __syncthreads();
@@ -387,7 +600,7 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wid = tid / kWave, nw = nt / kWave;
   const int64_t f = P.ov_flops[v];
-  const int64_t minor = P.groups[P.ov_group[v]].minor;
+  const int64_t minor = uload(&P.groups[uload(P.ov_group + v)].minor);
   const int64_t ub = f < minor ? f : minor;
   int logts = 6;
   while ((1ll << logts) < 2 * ub) ++logts;
@@ -444,7 +657,7 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
       __syncthreads();
     }
   }
-  const OutDev &O = P.outs[P.ov_group[v]];
+  const OutDev O = uload(P.outs + uload(P.ov_group + v));
   const int64_t base = out_offset(P, v);
   const int64_t cnt = P.ov_cnt[v];
   for (int i = tid; i < ts; i += nt) {
@@ -494,7 +707,7 @@ __device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int
     __syncthreads();
     return total;
   }
-  const OutDev &O = P.outs[P.ov_group[v]];
+  const OutDev O = uload(P.outs + uload(P.ov_group + v));
   int64_t r = out_pos + excl;
   for (int w = w0; w < w1; ++w) {
     uint32_t b = flags[w];
@@ -523,8 +736,8 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   typedef Sr<K> SR;
   typedef typename SR::T T;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t v = P.heavy_list[q];
-  const GroupDev &G = P.groups[P.ov_group[v]];
+  const int64_t v = uload(P.heavy_list + q);
+  const GroupDev G = uload(P.groups + uload(P.ov_group + v));
   int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
   if (G.mode != MODE) return;
   if (MODE == 0) {
@@ -572,18 +785,19 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
 }
 
 // Numeric pass of one planned heavy window (MODE 2: either window kind).
+// `it` is wave-uniform; the item's descriptor is one scalar load.
 template <int K, int MODE>
 __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
-  const int32_t q = P.item_vec[it];
-  const int32_t b0 = P.item_b0[it], b1 = P.item_b1[it];
-  const int64_t v = P.heavy_list[q];
-  const GroupDev &G = P.groups[P.ov_group[v]];
-  const int64_t lo = (int64_t)b0 * G.sw;
-  const int64_t hi = (int64_t)b1 * G.sw < G.minor ? (int64_t)b1 * G.sw : G.minor;
-  const int64_t pos = out_offset(P, v) + P.item_off[it];
+  const ItemDev I = uload(P.items + it);
+  const GroupDev G = uload(P.groups + I.g);
+  const int64_t lo = (int64_t)I.b0 * G.sw;
+  const int64_t hi = (int64_t)I.b1 * G.sw < G.minor ? (int64_t)I.b1 * G.sw : G.minor;
   if (MODE != 2 && G.mode != MODE) return;
-  if (MODE == 0 || (MODE == 2 && G.mode == 0)) dense_window<K, false>(P, v, b0, lo, hi, pos, lds, scratch, (G.sw + 31) >> 5);
-  else rank_window<K, false>(P, v, lo, hi, b0, b1, pos, lds, scratch, q < P.nkeep ? P.hbits + q * P.hstride : nullptr);
+  if (MODE == 0 || (MODE == 2 && G.mode == 0))
+    dense_window<K, false>(P, I.v, I.b0, lo, hi, I.pos, lds, scratch, (G.sw + 31) >> 5);
+  else
+    rank_window<K, false>(P, I.v, lo, hi, I.b0, I.b1, I.pos, lds, scratch,
+                          I.q < P.nkeep ? P.hbits + I.q * P.hstride : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,9 +812,10 @@ __device__ __forceinline__ void zero_lds(uint32_t *lds, int words) {
 template <int K, bool COUNT>
 __global__ void __launch_bounds__(1024) k_tiny(Plan P) {
   const int64_t n = P.counters[kCtTiny];
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t i = wave; i < n; i += nwaves) tiny_vector<K, COUNT>(P, P.tiny_list[i]);
+  for (int64_t c0 = wave * kWave; c0 < n; c0 += nwaves * kWave)
+    tiny_pack<K, COUNT>(P, c0, c0 + kWave < n ? c0 + kWave : n);
 }
 
 template <int K, bool COUNT>
@@ -613,11 +828,11 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_
   while (true) {
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
     __syncthreads();
-    const int64_t i = s_item;
+    const int64_t i = uni(s_item);
     __syncthreads();
     if (i >= n) break;
-    const int64_t v = P.mid_list[i];
-    if (P.mid_kind == 0) rank_window<K, COUNT>(P, v, 0, P.groups[P.ov_group[v]].minor, -1, -1, COUNT ? 0 : out_offset(P, v), lds, scratch);
+    const int64_t v = uload(P.mid_list + i);
+    if (P.mid_kind == 0) rank_window<K, COUNT>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, COUNT ? 0 : out_offset(P, v), lds, scratch);
     else mid_hash_vector<K, COUNT>(P, v, lds, scratch);
   }
 }
@@ -640,7 +855,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
     while (true) {
       if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
       __syncthreads();
-      const int64_t i = s_item;
+      const int64_t i = uni(s_item);
       __syncthreads();
       if (i >= n) break;
       heavy_count<K, MODE>(P, i, lds, scratch);
@@ -663,7 +878,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
     while (true) {
       if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
       __syncthreads();
-      const int64_t i = lo + s_item;
+      const int64_t i = lo + uni(s_item);
       __syncthreads();
       if (i >= hi) break;
       heavy_item<K, MODE>(P, i, lds, scratch);
@@ -672,7 +887,8 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
 }
 
 // One persistent launch for every tier: queue items are heavy windows
-// first, then mid vectors, then groups of tiny vectors (one per wavefront).
+// first, then mid vectors, then chunks of 64 tiny-list positions (one chunk
+// per wavefront, packed as in tiny_pack).
 template <int K, int MODE>
 __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, int64_t *queue, int64_t n_items, int64_t n_mid,
                                                   int64_t n_tiny) {
@@ -681,23 +897,23 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
   __shared__ int64_t s_item;
   zero_lds(lds, P.lds_words);
   const int nw = blockDim.x / kWave;
-  const int64_t n_tiny_groups = (n_tiny + nw - 1) / nw;
+  const int64_t n_tiny_groups = (n_tiny + (int64_t)kWave * nw - 1) / ((int64_t)kWave * nw);
   const int64_t total = n_items + n_mid + n_tiny_groups;
   while (true) {
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
     __syncthreads();
-    const int64_t i = s_item;
+    const int64_t i = uni(s_item);
     __syncthreads();
     if (i >= total) break;
     if (i < n_items) {
       heavy_item<K, MODE>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
-      const int64_t v = P.mid_list[i - n_items];
-      if (P.mid_kind == 0) rank_window<K, false>(P, v, 0, P.groups[P.ov_group[v]].minor, -1, -1, out_offset(P, v), lds, scratch);
+      const int64_t v = uload(P.mid_list + (i - n_items));
+      if (P.mid_kind == 0) rank_window<K, false>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds, scratch);
       else mid_hash_vector<K, false>(P, v, lds, scratch);
     } else {
-      const int64_t t = (i - n_items - n_mid) * nw + threadIdx.x / kWave;
-      if (t < n_tiny) tiny_vector<K, false>(P, P.tiny_list[t]);
+      const int64_t c0 = uni(((i - n_items - n_mid) * nw + threadIdx.x / kWave) * (int64_t)kWave);
+      if (c0 < n_tiny) tiny_pack<K, false>(P, c0, c0 + kWave < n_tiny ? c0 + kWave : n_tiny);
     }
   }
 }
