@@ -257,7 +257,8 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
     G = BT.GraphedNumeric(plan)
     G.replay()
     torch.cuda.synchronize()
-    _same(G.outputs[0], res["batched"], 0.0, "SUMMA graph replay vs batched")
+    # FP64 sums accumulate through LDS atomics, so two runs may round differently
+    _same(G.outputs[0], res["batched"], 1e-12, "SUMMA graph replay vs batched")
     ms_plain = _median_ms(torch, plain, reps)
     ms_batched = _median_ms(torch, batched, reps)
     ms_graph = _median_ms(torch, G.replay, max(reps, 5))
@@ -276,7 +277,7 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
         "persistent_kernel": {"launch_ms": round(kms, 4), "algorithmic_bytes": int(algo),
                               "achieved_GBs": round(algo / kms / 1e6, 1) if kms > 0 else None},
         "plain": "64 x (symbolic + sync + alloc + per-tier numeric) into DCSC partials, then a 64-way merge",
-        "exact": "batched == plain (pattern exact, values within 1e-12 relative); graph replay == batched bitwise",
+        "exact": "batched == plain == graph replay (patterns exact, values within 1e-12 relative)",
     }
     plan.destroy()
     del G, res, dA, dB

@@ -217,53 +217,96 @@ __global__ void k_group_ranges(const int32_t *ov_group, const int64_t *counters,
 // flops_j = sum over stored (k, s) of S(:, j) of nnz(G(:, k)); a k with an
 // empty G vector contributes nothing (the Isect observation, Section 2.4).
 // For a doubly compressed G the resolved vector is kept per S entry.
+// flops of G(:, k) summed over the stored entries e in [e0, e1) of S, one
+// entry per lane or one lane walking all of them (lane-serial); resolves
+// doubly compressed G vectors into d.gres on the way.
+__device__ __forceinline__ int64_t entry_flops(const ProdDev &d, int64_t e) {
+  const int32_t k = gload(d.s_idx + e);
+  int32_t gt;
+  if (d.g_vid) {
+    gt = aux_find(d, k);
+    gstore(d.gres + e, gt);
+  } else {
+    gt = (k >= 0 && k < d.g_nvec) ? k : -1;
+  }
+  return gt >= 0 ? gload(d.g_ptr + gt + 1) - gload(d.g_ptr + gt) : 0;
+}
+
+// Flops per output vector (and per-group totals, bound and maximum). A
+// wavefront takes 64 consecutive output vectors, one per lane: vectors with
+// one segment of the chunk's common product and at most kSerial streamed
+// entries are summed by their own lane; the others are summed by the whole
+// wavefront, one at a time.
 __global__ void k_flops(Plan P, int64_t *gstat) {
+  constexpr int kSerial = 32;
   const int l = lane();
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int64_t nov = P.counters[kCtNov];
-  int32_t cur_g = -1;
-  int64_t acc_f = 0, acc_ub = 0, acc_max = 0;
-  for (int64_t v = uni(wave); v < nov; v += nwaves) {
+  for (int64_t v0 = wave * kWave; v0 < nov; v0 += nwaves * kWave) {
+    const int64_t v = v0 + l;
+    const bool valid = v < nov;
+    int32_t p = -1, t = 0;
+    if (valid) {
+      const int64_t s0 = gload(P.ov_seg + v);
+      if (gload(P.ov_seg + v + 1) - s0 == 1) {
+        p = gload(P.seg_prod + s0);
+        t = gload(P.seg_svec + s0);
+      }
+    }
+    const uint64_t hasp = __ballot(p >= 0);
     int64_t f = 0;
-    const int64_t s1 = uload(P.ov_seg + v + 1);
-    for (int64_t s = uload(P.ov_seg + v); s < s1; ++s) {
-      const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
-      const int32_t t = uload(P.seg_svec + s);
-      const int64_t e0 = uload(d.s_ptr + t), e1 = uload(d.s_ptr + t + 1);
-      for (int64_t e = e0 + l; e < e1; e += kWave) {
-        int32_t k = d.s_idx[e];
-        int32_t gt;
-        if (d.g_vid) {
-          gt = aux_find(d, k);
-          d.gres[e] = gt;
-        } else {
-          gt = (k >= 0 && k < d.g_nvec) ? k : -1;
+    bool done = false;
+    if (hasp) {
+      const int32_t p0 = __builtin_amdgcn_readlane(p, __ffsll((unsigned long long)hasp) - 1);
+      const ProdDev d = uload(P.prods + p0);
+      if (p == p0) {
+        const int64_t e0 = gload(d.s_ptr + t), e1 = gload(d.s_ptr + t + 1);
+        if (e1 - e0 <= kSerial) {
+          for (int64_t e = e0; e < e1; ++e) f += entry_flops(d, e);
+          done = true;
         }
-        if (gt >= 0) f += d.g_ptr[gt + 1] - d.g_ptr[gt];
       }
     }
-    f = wave_sum64(f);
-    const int32_t g = uload(P.ov_group + v);
-    if (l == 0) P.ov_flops[v] = f;
-    if (g != cur_g) {
-      if (cur_g >= 0 && l == 0) {
-        atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)acc_f);
-        atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStUb], (unsigned long long)acc_ub);
-        atomicMax((unsigned long long *)&gstat[cur_g * kStCount + kStMaxFlops], (unsigned long long)acc_max);
+    uint64_t coop = __ballot(valid && !done);
+    while (coop) {
+      const int x = __ffsll((unsigned long long)coop) - 1;
+      coop &= coop - 1ull;
+      const int64_t vx = v0 + x;
+      int64_t fx = 0;
+      const int64_t s1 = uload(P.ov_seg + vx + 1);
+      for (int64_t s = uload(P.ov_seg + vx); s < s1; ++s) {
+        const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+        const int32_t tt = uload(P.seg_svec + s);
+        const int64_t e1 = uload(d.s_ptr + tt + 1);
+        for (int64_t e = uload(d.s_ptr + tt) + l; e < e1; e += kWave) fx += entry_flops(d, e);
       }
-      cur_g = g;
-      acc_f = acc_ub = acc_max = 0;
+      fx = wave_sum64(fx);
+      if (l == x) f = fx;
     }
-    const int64_t minor = uload(&P.groups[g].minor);
-    acc_f += f;
-    acc_ub += f < minor ? f : minor;
-    acc_max = f > acc_max ? f : acc_max;
-  }
-  if (cur_g >= 0 && l == 0) {
-    atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)acc_f);
-    atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStUb], (unsigned long long)acc_ub);
-    atomicMax((unsigned long long *)&gstat[cur_g * kStCount + kStMaxFlops], (unsigned long long)acc_max);
+    int32_t g = -1;
+    int64_t minor = 0;
+    if (valid) {
+      gstore(P.ov_flops + v, f);
+      g = gload(P.ov_group + v);
+      minor = gload(&P.groups[g].minor);
+    }
+    const int64_t ub = f < minor ? f : minor;
+    // per-group totals: one set of atomics per group present in the chunk
+    uint64_t pend = __ballot(valid);
+    while (pend) {
+      const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
+      const bool mine = valid && g == gx;
+      pend &= ~__ballot(mine);
+      const int64_t sf = wave_sum64(mine ? f : 0);
+      const int64_t su = wave_sum64(mine ? ub : 0);
+      const int64_t mx = wave_max64(mine ? f : 0);
+      if (l == 0) {
+        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStFlops], (unsigned long long)sf);
+        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStUb], (unsigned long long)su);
+        atomicMax((unsigned long long *)&gstat[gx * kStCount + kStMaxFlops], (unsigned long long)mx);
+      }
+    }
   }
 }
 

@@ -80,17 +80,50 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
   if (len > 0) own[__popcll(m & ((1ull << l) - 1ull))] = (uint8_t)l;
   __builtin_amdgcn_wave_barrier();
   const int rounds = (nz + ng - 1) / ng;
-  for (int rd = 0; rd < rounds; ++rd) {
-    const int r = rd * ng + gi;
-    const bool valid = r < nz;
-    const int o = valid ? own[r] : 0;
-    const int L = __shfl(len, o, kWave);
-    const int64_t b = __shfl(gb, o, kWave);
-    const T s = __shfl(sv, o, kWave);
-    if (valid) {
-      int f = li;
-      for (; f + 3 * gs < L; f += 4 * gs) {
-        const int64_t g0 = b + f;
+  // four rounds at a time: the first product of four entries per lane is
+  // gathered before any is committed, so four loads are in flight per lane
+  // even when every entry fits its lane group; longer entries finish in the
+  // unrolled tail loop below
+  for (int rd = 0; rd < rounds; rd += 4) {
+    int L[4];
+    int64_t b[4];
+    T sv4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = (rd + k) * ng + gi;
+      const bool valid = rd + k < rounds && r < nz;
+      const int o = valid ? own[r] : 0;
+      L[k] = __shfl(len, o, kWave);
+      b[k] = __shfl(gb, o, kWave);
+      sv4[k] = __shfl(sv, o, kWave);
+      if (!valid) L[k] = 0;
+    }
+    int32_t i4[4];
+    T v4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      i4[k] = 0;
+      v4[k] = T();
+      if (li < L[k]) {
+        i4[k] = gload(gidx + b[k] + li);
+        if (SR::kVal) v4[k] = gload(gval + b[k] + li);
+      }
+    }
+    uint64_t t4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t4[k] = li < L[k] ? act.prep(i4[k]) : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (li < L[k]) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(sv4[k], v4[k]) : T());
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int Lk = L[k];
+      if (Lk <= gs) continue;
+      const int64_t bk = b[k];
+      const T s = sv4[k];
+      int f = li + gs;
+      for (; f + 3 * gs < Lk; f += 4 * gs) {
+        const int64_t g0 = bk + f;
         const int32_t i0 = gload(gidx + g0), i1 = gload(gidx + g0 + gs);
         const int32_t i2 = gload(gidx + g0 + 2 * gs), i3 = gload(gidx + g0 + 3 * gs);
         T v0 = T(), v1 = T(), v2 = T(), v3 = T();
@@ -106,8 +139,8 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
         act.commit(i2, t2, SR::kVal ? SR::mul(s, v2) : T());
         act.commit(i3, t3, SR::kVal ? SR::mul(s, v3) : T());
       }
-      for (; f < L; f += gs) {
-        const int64_t g = b + f;
+      for (; f < Lk; f += gs) {
+        const int64_t g = bk + f;
         const int32_t i = gload(gidx + g);
         const T v = SR::kVal ? gload(gval + g) : T();
         act.commit(i, act.prep(i), SR::kVal ? SR::mul(s, v) : T());
@@ -273,6 +306,13 @@ __device__ __forceinline__ uint64_t lane_range(int a, int b) {
   const uint64_t hi = b >= kWave ? ~0ull : ((1ull << b) - 1ull);
   const uint64_t lo = a >= kWave ? ~0ull : ((1ull << a) - 1ull);
   return hi & ~lo;
+}
+
+// Tiny-list positions per wavefront chunk: enough chunks for every one of
+// `waves` wavefronts, each at most 64 positions.
+__device__ __forceinline__ int64_t tiny_chunk(int64_t n, int64_t waves) {
+  const int64_t c = (n + waves - 1) / waves;
+  return c < 1 ? 1 : (c > kWave ? kWave : c);
 }
 
 template <int K, bool COUNT>
@@ -507,6 +547,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   uint32_t *words = lds;
   Slot *vals = (Slot *)(lds + WS * nwds);
   const OutDev O = uload(P.outs + uload(P.ov_group + v));
+  int64_t cnt = 0;  // entries of the window
 
   if (!COUNT && kept) {
     // the count pass kept this vector's bitmap: the window's words arrive
@@ -517,7 +558,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
       __syncthreads();
       return;
     }
-    rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
+    cnt = rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
     __syncthreads();
   } else {
     auto mark = step<T>([&](int id, T) {
@@ -563,12 +604,22 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
         run += __popc(words[WS * w]);
       }
     }
+    cnt = total;
     __syncthreads();
   }
   RankAcc<SR> accum{words, vals, lo32};
   for_products<SR>(P, v, b0, b1, wid, nw, accum);
   __syncthreads();
-  // emit: lane-interleaved words, so a wavefront writes one contiguous run
+  // emit in three coalesced passes: the values are already dense by rank;
+  // the ids are scattered by rank into the (emptied) value slots, then
+  // written in rank order. Every slot is back to zero at the end.
+  const int n = (int)cnt;
+  for (int r = tid; r < n; r += nt) {
+    gstore((T *)O.val + out_pos + r, SR::dec(vals[r]));
+    vals[r] = Slot();
+  }
+  __syncthreads();
+  int32_t *ids = (int32_t *)vals;
   for (int w = tid; w < nwds; w += nt) {
     uint32_t b = words[WS * w];
     if (b) {
@@ -576,14 +627,16 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
       while (b) {
         const int bit = __ffs(b) - 1;
         b &= b - 1;
-        gstore(O.idx + out_pos + r, lo32 + (w << 5) + bit);
-        gstore((T *)O.val + out_pos + r, SR::dec(vals[r]));
-        vals[r] = Slot();
-        ++r;
+        ids[r++] = lo32 + (w << 5) + bit;
       }
     }
     words[WS * w] = 0;
     words[WS * w + 1] = 0;
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += nt) {
+    gstore(O.idx + out_pos + r, ids[r]);
+    ids[r] = 0;
   }
   __syncthreads();
 }
@@ -814,8 +867,9 @@ __global__ void __launch_bounds__(1024) k_tiny(Plan P) {
   const int64_t n = P.counters[kCtTiny];
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t c0 = wave * kWave; c0 < n; c0 += nwaves * kWave)
-    tiny_pack<K, COUNT>(P, c0, c0 + kWave < n ? c0 + kWave : n);
+  // chunks as large as needed to give every wavefront work, at most 64
+  const int64_t csz = tiny_chunk(n, nwaves);
+  for (int64_t c0 = wave * csz; c0 < n; c0 += nwaves * csz) tiny_pack<K, COUNT>(P, c0, c0 + csz < n ? c0 + csz : n);
 }
 
 template <int K, bool COUNT>
@@ -897,7 +951,8 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
   __shared__ int64_t s_item;
   zero_lds(lds, P.lds_words);
   const int nw = blockDim.x / kWave;
-  const int64_t n_tiny_groups = (n_tiny + (int64_t)kWave * nw - 1) / ((int64_t)kWave * nw);
+  const int64_t csz = tiny_chunk(n_tiny, (int64_t)gridDim.x * nw);
+  const int64_t n_tiny_groups = (n_tiny + csz * nw - 1) / (csz * nw);
   const int64_t total = n_items + n_mid + n_tiny_groups;
   while (true) {
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
@@ -912,8 +967,8 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
       if (P.mid_kind == 0) rank_window<K, false>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds, scratch);
       else mid_hash_vector<K, false>(P, v, lds, scratch);
     } else {
-      const int64_t c0 = uni(((i - n_items - n_mid) * nw + threadIdx.x / kWave) * (int64_t)kWave);
-      if (c0 < n_tiny) tiny_pack<K, false>(P, c0, c0 + kWave < n_tiny ? c0 + kWave : n_tiny);
+      const int64_t c0 = uni(((i - n_items - n_mid) * nw + threadIdx.x / kWave) * csz);
+      if (c0 < n_tiny) tiny_pack<K, false>(P, c0, c0 + csz < n_tiny ? c0 + csz : n_tiny);
     }
   }
 }
