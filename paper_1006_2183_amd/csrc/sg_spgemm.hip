@@ -95,9 +95,11 @@ int64_t mid_capacity(const sg_tuning &t, int32_t kind, int64_t minor) {
   const int sb = slot_bytes(kind);
   int64_t cap;
   if (t.mid_kind == 0) {
-    // bitmap-rank: one {bits, prefix} pair of 32-bit words per 32 ids (bits only without values)
+    // bitmap-rank: one {bits, prefix} pair of 32-bit words per 32 ids (bits
+    // only without values), plus one bit per such word marking it touched
     int64_t nw32 = (minor + 31) / 32;
-    int64_t words = sb ? 2 * nw32 : nw32;
+    int64_t ntop = (nw32 + 31) / 32;
+    int64_t words = ((sb ? 2 * nw32 : nw32) + ntop + 1) & ~1ll;
     int64_t left = (int64_t)t.lds_bytes - 4 * words;
     if (left < 0) return 0;
     if (sb == 0) return minor;  // the bitmap alone is the accumulator

@@ -545,7 +545,16 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   const int nwds = (int)((hi - lo + 31) >> 5);
   const int lo32 = (int)lo;
   uint32_t *words = lds;
-  Slot *vals = (Slot *)(lds + WS * nwds);
+  // a whole-range window (the mid tier) is mostly empty words: a second
+  // bitmap with one bit per word of ids (top) lets the scan, the prefix
+  // and the emit visit only the touched words
+  const bool two = b0 < 0 && !kept;
+  const int ntop = (nwds + 31) >> 5;
+  uint32_t *top = lds + WS * nwds;
+  Slot *vals = (Slot *)(lds + (two ? ((WS * nwds + ntop + 1) & ~1) : WS * nwds));
+  const int tper = (ntop + nt - 1) / nt;  // top words per thread (contiguous)
+  const int tw0 = tid * tper < ntop ? tid * tper : ntop;
+  const int tw1 = tw0 + tper < ntop ? tw0 + tper : ntop;
   const OutDev O = uload(P.outs + uload(P.ov_group + v));
   int64_t cnt = 0;  // entries of the window
 
@@ -559,6 +568,62 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
       return;
     }
     cnt = rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
+    __syncthreads();
+  } else if (two) {
+    auto mark = step<T>([&](int id, T) {
+      const int r = id - lo32;
+      const int w = r >> 5;
+      atomicOr(&words[WS * w], 1u << (r & 31));
+      atomicOr(&top[w >> 5], 1u << (w & 31));
+    });
+    for_products<SR>(P, v, b0, b1, wid, nw, mark);
+    __syncthreads();
+    int local = 0;
+    for (int tw = tw0; tw < tw1; ++tw) {
+      uint32_t tb = top[tw];
+      while (tb) {
+        const int w = (tw << 5) + __ffs(tb) - 1;
+        tb &= tb - 1;
+        local += __popc(words[WS * w]);
+      }
+    }
+    int64_t total;
+    const int64_t excl = block_excl_scan(local, scratch, &total);
+    int64_t run = excl;
+    for (int tw = tw0; tw < tw1; ++tw) {
+      uint32_t tb = top[tw];
+      while (tb) {
+        const int w = (tw << 5) + __ffs(tb) - 1;
+        tb &= tb - 1;
+        const uint32_t b = words[WS * w];
+        if (COUNT) {
+          words[WS * w] = 0;
+        } else if (!SR::kVal) {
+          uint32_t bb = b;
+          while (bb) {
+            const int bit = __ffs(bb) - 1;
+            bb &= bb - 1;
+            gstore(O.idx + out_pos + run, lo32 + (w << 5) + bit);
+            ++run;
+          }
+          words[w] = 0;
+        } else {
+          words[WS * w + 1] = (uint32_t)run;
+          run += __popc(b);
+        }
+      }
+      if (COUNT || !SR::kVal) top[tw] = 0;
+    }
+    if (COUNT) {
+      if (tid == 0) gstore(P.ov_cnt + v, total);
+      __syncthreads();
+      return;
+    }
+    if (!SR::kVal) {
+      __syncthreads();
+      return;
+    }
+    cnt = total;
     __syncthreads();
   } else {
     auto mark = step<T>([&](int id, T) {
@@ -620,18 +685,38 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   }
   __syncthreads();
   int32_t *ids = (int32_t *)vals;
-  for (int w = tid; w < nwds; w += nt) {
-    uint32_t b = words[WS * w];
-    if (b) {
-      int r = (int)words[WS * w + 1];
-      while (b) {
-        const int bit = __ffs(b) - 1;
-        b &= b - 1;
-        ids[r++] = lo32 + (w << 5) + bit;
+  if (two) {
+    for (int tw = tw0; tw < tw1; ++tw) {
+      uint32_t tb = top[tw];
+      while (tb) {
+        const int w = (tw << 5) + __ffs(tb) - 1;
+        tb &= tb - 1;
+        uint32_t b = words[WS * w];
+        int r = (int)words[WS * w + 1];
+        while (b) {
+          const int bit = __ffs(b) - 1;
+          b &= b - 1;
+          ids[r++] = lo32 + (w << 5) + bit;
+        }
+        words[WS * w] = 0;
+        words[WS * w + 1] = 0;
       }
+      top[tw] = 0;
     }
-    words[WS * w] = 0;
-    words[WS * w + 1] = 0;
+  } else {
+    for (int w = tid; w < nwds; w += nt) {
+      uint32_t b = words[WS * w];
+      if (b) {
+        int r = (int)words[WS * w + 1];
+        while (b) {
+          const int bit = __ffs(b) - 1;
+          b &= b - 1;
+          ids[r++] = lo32 + (w << 5) + bit;
+        }
+      }
+      words[WS * w] = 0;
+      words[WS * w + 1] = 0;
+    }
   }
   __syncthreads();
   for (int r = tid; r < n; r += nt) {
@@ -818,14 +903,22 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   const int wpb = G.sw >> 5;  // words per bucket
   uint32_t *keep = q < P.nkeep ? P.hbits + q * P.hstride : nullptr;
   int64_t local = 0;
-  for (int w = tid; w < nwds; w += nt) {
-    const uint32_t word = bits[w];
-    if (keep) gstore(keep + w, word);
+  // rounds of 64 consecutive words per wavefront; the words of one bucket
+  // are summed across the wavefront before the bucket counter is touched
+  for (int w0 = wid * kWave; w0 < nwds; w0 += nt) {
+    const int w = w0 + lane();
+    const uint32_t word = w < nwds ? bits[w] : 0u;
+    if (keep && w < nwds) gstore(keep + w, word);
     const int c = __popc(word);
-    if (c) {
-      atomicAdd(&lbc[w / wpb], c);
-      local += c;
-      bits[w] = 0;
+    local += c;
+    if (word) bits[w] = 0;
+    const int bk = (w < nwds ? w : nwds - 1) / wpb;
+    const int bfirst = __builtin_amdgcn_readfirstlane(bk);
+    if (__ballot(bk != bfirst) == 0) {
+      const int sum = wave_sum(c);
+      if (lane() == 0 && sum) atomicAdd(&lbc[bfirst], sum);
+    } else if (c) {
+      atomicAdd(&lbc[bk], c);
     }
   }
   const int64_t total = block_sum(local, scratch);
