@@ -177,16 +177,24 @@ __device__ __forceinline__ void load_entry(const ProdDev &d, int64_t e, int64_t 
 }
 
 // All products of output vector v (restricted to split buckets [b0, b1) if
-// b0 >= 0), shared by the nw wavefronts of the caller. Every wave walks the
-// same batches of 64 stored S entries; the products of a batch, in entry
-// order, are cut into nw equal slices and wave wid takes slice wid by
-// clipping each entry's G range to it. A vector with few entries but long G
-// vectors (the typical heavy vector) thus keeps every wave busy.
+// b0 >= 0), shared by the nw wavefronts of the caller. With fewer segments
+// than wavefronts, every wave walks the same batches of 64 stored S
+// entries; the products of a batch, in entry order, are cut into nw equal
+// slices and wave wid takes slice wid by clipping each entry's G range to
+// it. A vector with few entries but long G vectors (the typical heavy
+// vector) thus keeps every wave busy.
 template <class SR, class Act>
 __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, int b1, int wid, int nw, Act &act) {
   typedef typename SR::T T;
   const int64_t s0 = uload(P.ov_seg + v), s1 = uload(P.ov_seg + v + 1);
-  for (int64_t s = s0; s < s1; ++s) {
+  // many segments (stage products accumulated into one vector): the
+  // segments are dealt to the wavefronts round robin and each wavefront
+  // takes every product of its own segments (one slice), so no wavefront
+  // walks the descriptors of all of them
+  const bool many = s1 - s0 >= nw;
+  const int uw = uni(wid);  // the wavefront index is wave-uniform: keep the walk scalar
+  const int sid = many ? 0 : uw, sn = many ? 1 : nw;
+  for (int64_t s = s0 + (many ? uw : 0); s < s1; s += many ? nw : 1) {
     const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
     const int32_t t = uload(P.seg_svec + s);
     const int64_t e1 = uload(d.s_ptr + t + 1);
@@ -198,8 +206,8 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
       const int incl = wave_incl_scan(len);
       const int tot = read_lane(incl, kWave - 1);
       if (tot == 0) continue;
-      const int f0 = (int)((int64_t)tot * wid / nw);
-      const int f1 = (int)((int64_t)tot * (wid + 1) / nw);
+      const int f0 = (int)((int64_t)tot * sid / sn);
+      const int f1 = (int)((int64_t)tot * (sid + 1) / sn);
       const int st = incl - len;
       const int a = st > f0 ? st : f0;
       const int e = incl < f1 ? incl : f1;
@@ -533,7 +541,7 @@ __device__ __forceinline__ int64_t rank_load_kept(const uint32_t *src, int nwds,
   return run_total;
 }
 
-template <int K, bool COUNT>
+template <int K, bool COUNT, bool WHOLE = false>
 __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
                             uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr) {
   typedef Sr<K> SR;
@@ -548,7 +556,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   // a whole-range window (the mid tier) is mostly empty words: a second
   // bitmap with one bit per word of ids (top) lets the scan, the prefix
   // and the emit visit only the touched words
-  const bool two = b0 < 0 && !kept;
+  constexpr bool two = WHOLE;  // whole id range, marked here (the mid tier)
   const int ntop = (nwds + 31) >> 5;
   uint32_t *top = lds + WS * nwds;
   Slot *vals = (Slot *)(lds + (two ? ((WS * nwds + ntop + 1) & ~1) : WS * nwds));
@@ -569,7 +577,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     }
     cnt = rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
     __syncthreads();
-  } else if (two) {
+  } else if constexpr (two) {
     auto mark = step<T>([&](int id, T) {
       const int r = id - lo32;
       const int w = r >> 5;
@@ -685,7 +693,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   }
   __syncthreads();
   int32_t *ids = (int32_t *)vals;
-  if (two) {
+  if constexpr (two) {
     for (int tw = tw0; tw < tw1; ++tw) {
       uint32_t tb = top[tw];
       while (tb) {
@@ -979,7 +987,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_
     __syncthreads();
     if (i >= n) break;
     const int64_t v = uload(P.mid_list + i);
-    if (P.mid_kind == 0) rank_window<K, COUNT>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, COUNT ? 0 : out_offset(P, v), lds, scratch);
+    if (P.mid_kind == 0) rank_window<K, COUNT, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, COUNT ? 0 : out_offset(P, v), lds, scratch);
     else mid_hash_vector<K, COUNT>(P, v, lds, scratch);
   }
 }
@@ -1057,7 +1065,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
       heavy_item<K, MODE>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
       const int64_t v = uload(P.mid_list + (i - n_items));
-      if (P.mid_kind == 0) rank_window<K, false>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds, scratch);
+      if (P.mid_kind == 0) rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds, scratch);
       else mid_hash_vector<K, false>(P, v, lds, scratch);
     } else {
       const int64_t c0 = uni(((i - n_items - n_mid) * nw + threadIdx.x / kWave) * csz);

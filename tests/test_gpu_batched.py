@@ -204,3 +204,23 @@ def test_autotune_keeps_results(sg, tmp_path):
         C = sg.spgemm(semiring, dA, dA, tuning=sg.make_tuning(semiring, **cand)).to_host()
         assert_same(C, R, semiring, 0.0, str(cand))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("force", [-1, 1, 2])
+def test_summa_share_many_segments(sg, force):
+    """16 stage products per output vector (more segments than wavefronts per workgroup), every tier."""
+    from paper_1006_2183_amd import batched as BT
+    semiring = "plus_times_f64"
+    scale, grid = 12, 16
+    _say(f"case summa share 16 stages force {force}")
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (3, 5), semiring=semiring, seed=17)
+    b = (1 << scale) // grid
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
+    R, _ = oracle.spgemm(semiring, SA, SB)
+    for batched in (False, True):
+        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=24576, block_threads=512)
+        C = BT.summa_share(semiring, dA, dB, tuning=t, batched=batched).to_host()
+        assert_canonical(C)
+        assert_same(C, R, semiring, 1e-12, f"force {force} batched {batched}")
