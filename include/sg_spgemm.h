@@ -111,8 +111,10 @@ typedef struct {
  *                    most this use one workgroup with an LDS-resident
  *                    accumulator (bitmap-rank or open-addressing hash)
  *   mid_kind         0 = bitmap-rank accumulator, 1 = LDS hash accumulator
- *   lds_bytes        LDS budget of one workgroup of the mid/heavy tiers
- *   block_threads    threads per workgroup of the mid/heavy tiers (64..1024)
+ *   lds_bytes        LDS budget of one workgroup of the mid tier and of the
+ *                    count passes
+ *   block_threads    threads per workgroup of the mid tier and of the count
+ *                    passes (64..1024)
  *   chunk_width      heavy tier: width in ids of one split bucket (rank
  *                    windows) or of one dense window (0 = automatic)
  *   heavy_kind       heavy tier: 0 = bitmap-rank windows planned from exact
@@ -135,6 +137,12 @@ typedef struct {
  *                    keeps each heavy vector's id bitmap, so that numeric
  *                    windows load their slice instead of re-marking it
  *                    (vectors beyond the budget re-mark; 0 = never keep)
+ *   heavy_threads    threads per workgroup of the heavy-tier numeric launch
+ *                    and of the single persistent launch (0 = block_threads)
+ *   heavy_lds_bytes  LDS budget of those workgroups; heavy windows are
+ *                    planned to fit it, so a larger budget means fewer,
+ *                    wider windows (0 = lds_bytes). The persistent launch
+ *                    uses the larger of the two budgets.
  */
 typedef struct {
     int32_t tiny_max_flops;
@@ -149,6 +157,8 @@ typedef struct {
     int32_t validate;
     int32_t xcd_ranges;
     int32_t bitmap_mb;
+    int32_t heavy_threads;
+    int32_t heavy_lds_bytes;
 } sg_tuning;
 
 /* Host-side sizes of one output, valid when sg_spgemm_symbolic returns. */

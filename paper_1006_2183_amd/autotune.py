@@ -1,9 +1,9 @@
 """Autotuner for the tier thresholds and accumulator sizes of a product shape.
 
 The tunable knobs are the fields of ``sg_tuning``: the tiny/mid flops
-thresholds of the binning step, the LDS bytes given to the mid and heavy
-accumulators (hash/bitmap capacity and heavy window width follow from it),
-the workgroup size and the number of persistent workgroups per compute unit.
+thresholds of the binning step, the LDS bytes and workgroup size of the mid
+tier and of the heavy tier (mid capacity and heavy window width follow from
+them) and the number of persistent workgroups per compute unit.
 A search times whole steps (symbolic + numeric, or numeric only for a
 structure-reusing caller) of the actual operands and keeps the fastest
 setting; candidates the library rejects are skipped. Results are cached in a
@@ -26,6 +26,8 @@ from . import binding as B
 
 # Coordinate-descent search space, most influential knob first.
 SPACE: Dict[str, List[int]] = {
+    "heavy_lds_bytes": [78848, 131072, 159744],
+    "heavy_threads": [512, 1024],
     "lds_bytes": [32768, 49152, 65536, 78848, 98304, 131072, 161792],
     "blocks_per_cu": [1, 2, 3, 4],
     "block_threads": [256, 512],

@@ -57,7 +57,9 @@ class sg_tuning(ctypes.Structure):
                 ("lds_bytes", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("chunk_width", ctypes.c_int32),
                 ("heavy_kind", ctypes.c_int32), ("force_tier", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("xcd_ranges", ctypes.c_int32),
-                ("bitmap_mb", ctypes.c_int32)]
+                ("bitmap_mb", ctypes.c_int32),
+                ("heavy_threads", ctypes.c_int32),
+                ("heavy_lds_bytes", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

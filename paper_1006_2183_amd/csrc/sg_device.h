@@ -22,7 +22,7 @@ namespace sg {
 constexpr int kWave = 64;
 constexpr int kXcds = 8;           // dies of an MI355X, each with its own L2
 constexpr int kMaxWaves = 16;  // 1024 threads per workgroup at most
-constexpr int kBlockMax = 512;     // threads per workgroup of the mid/heavy/batched kernels
+constexpr int kBlockMax = 1024;    // threads per workgroup of the mid/heavy/batched kernels
 #ifndef SG_WAVES_PER_SIMD
 #define SG_WAVES_PER_SIMD 4
 #endif

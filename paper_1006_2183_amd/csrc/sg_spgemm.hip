@@ -79,6 +79,15 @@ struct Carve {
 };
 
 
+// The tuning as the heavy tier sees it: its windows are planned for the
+// heavy workgroups' LDS budget.
+sg_tuning heavy_view(const sg_tuning &t) {
+  sg_tuning h = t;
+  h.lds_bytes = t.heavy_lds_bytes;
+  h.block_threads = t.heavy_threads;
+  return h;
+}
+
 int heavy_window(const sg_tuning &t, int32_t kind) {
   const int sb = slot_bytes(kind);
   int64_t w = ((int64_t)t.lds_bytes * 8) / (8 * sb + 1);
@@ -172,6 +181,8 @@ struct sg_plan {
   int ncu = 0;
   bool dense_path = false;
   bool has_mode[2] = {false, false};  // heavy window kinds used by the groups
+  int lds_mid_count = 0;               // dynamic LDS of the count passes (bitmaps only)
+  int lds_heavy_count = 0;
   int64_t nov_max = 0;
   int64_t items_max = 0;
   int64_t ndense_ptr = 0;
@@ -310,7 +321,7 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
   sh.ndense_ptr = 0;
   sh.nrange = t.xcd_ranges > 0 ? kXcds * t.xcd_ranges : 1;
   for (int32_t g = 0; g < ngroup; ++g) {
-    sh.geom[g] = group_geom(t, kind, sh.minor[g], win);
+    sh.geom[g] = group_geom(heavy_view(t), kind, sh.minor[g], win);
     Geom &ge = sh.geom[g];
     ge.bpr = (ge.nsplit + sh.nrange - 1) / sh.nrange;
     sh.nbmax = std::max<int32_t>(sh.nbmax, sh.geom[g].nsplit);
@@ -454,14 +465,20 @@ void normalise(sg_tuning &t, int32_t kind) {
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) t.blocks_per_cu = d.blocks_per_cu;
   if (t.xcd_ranges < 0 || t.xcd_ranges > 16) t.xcd_ranges = d.xcd_ranges;
   if (t.bitmap_mb < 0) t.bitmap_mb = d.bitmap_mb;
+  if (t.heavy_threads == 0) t.heavy_threads = t.block_threads;
+  if (t.heavy_threads < 64 || t.heavy_threads > kBlockMax || t.heavy_threads % 64) t.heavy_threads = d.heavy_threads;
+  if (t.heavy_lds_bytes == 0) t.heavy_lds_bytes = t.lds_bytes;
+  if (t.heavy_lds_bytes < 4096 || t.heavy_lds_bytes > 160 * 1024 - 2048) t.heavy_lds_bytes = d.heavy_lds_bytes;
+  t.heavy_lds_bytes &= ~7;
 }
+
 
 template <int K>
 sg_status set_lds_attr(int bytes) {
-  SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_mid_count<K>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, true, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy_count<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy_count<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
@@ -470,23 +487,36 @@ sg_status set_lds_attr(int bytes) {
   return SG_OK;
 }
 
+// Persistent workgroups for a kernel of `nt` threads and `lds` dynamic LDS
+// bytes whose register budget allows `waves_per_simd` wavefronts per SIMD.
+int64_t resident_blocks(int ncu, int nt, int lds, int waves_per_simd) {
+  const int64_t by_waves = (int64_t)4 * waves_per_simd / (nt / kWave);
+  const int64_t by_lds = lds > 0 ? (int64_t)(160 * 1024 - 2048) / lds : by_waves;
+  return (int64_t)ncu * std::max<int64_t>(1, std::min(by_waves, by_lds));
+}
+
 template <int K>
 sg_status launch_counts(sg_plan *pl, hipStream_t st) {
-  const Plan &P = pl->P;
   const int nt = pl->tune.block_threads;
-  const int lds = pl->tune.lds_bytes;
   const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
   const int64_t tiny_blocks = std::min<int64_t>(std::max<int64_t>(1, (pl->nov_max + 3) / 4), persist * 8);
-  hipLaunchKernelGGL((k_tiny<K, true>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, P);
+  hipLaunchKernelGGL((k_tiny<K, true>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, pl->P);
   SG_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_mid<K, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 0);
+  // the count kernels zero exactly the LDS they are launched with
+  Plan Pm = pl->P;
+  Pm.lds_words = pl->lds_mid_count / 4;
+  hipLaunchKernelGGL((k_mid_count<K>), dim3((unsigned)resident_blocks(pl->ncu, nt, pl->lds_mid_count, kCountWavesPerSimd)),
+                     dim3(nt), pl->lds_mid_count, st, Pm, pl->counters + kCtNum + 0);
   SG_HIP(hipGetLastError());
+  Plan Ph = pl->P;
+  Ph.lds_words = pl->lds_heavy_count / 4;
+  const unsigned hb = (unsigned)resident_blocks(pl->ncu, nt, pl->lds_heavy_count, kWavesPerSimd);
   for (int m = 0; m < 2; ++m) {
     if (!pl->has_mode[m]) continue;
     if (m == 0)
-      hipLaunchKernelGGL((k_heavy<K, true, 0>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 1);
+      hipLaunchKernelGGL((k_heavy_count<K, 0>), dim3(hb), dim3(nt), pl->lds_heavy_count, st, Ph, pl->counters + kCtNum + 1);
     else
-      hipLaunchKernelGGL((k_heavy<K, true, 1>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtNum + 4);
+      hipLaunchKernelGGL((k_heavy_count<K, 1>), dim3(hb), dim3(nt), pl->lds_heavy_count, st, Ph, pl->counters + kCtNum + 4);
     SG_HIP(hipGetLastError());
   }
   return SG_OK;
@@ -509,12 +539,17 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
   SG_TRY(fill64(pl->counters + kCtNum + 2, 22, 0, st));
   if (I.n_heavy_items > 0) {
     SG_TRY(mark(pl, 0, false, st));
-    // a multiple of the XCD count so every die gets the same number of workgroups
-    const unsigned hg = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(persist, I.n_heavy_items) / kXcds * kXcds);
+    const int hnt = pl->tune.heavy_threads, hlds = pl->tune.heavy_lds_bytes;
+    Plan Ph = P;
+    Ph.lds_words = hlds / 4;
+    // as many workgroups as fit the chip, a multiple of the XCD count so
+    // every die gets the same number
+    const int64_t hres = resident_blocks(pl->ncu, hnt, hlds, kWavesPerSimd);
+    const unsigned hg = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(hres, I.n_heavy_items) / kXcds * kXcds);
     if (pl->has_mode[0])
-      hipLaunchKernelGGL((k_heavy<K, false, 0>), dim3(hg), dim3(nt), lds, st, P, pl->counters + kCtNum + 8);
+      hipLaunchKernelGGL((k_heavy<K, false, 0>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 8);
     if (pl->has_mode[1])
-      hipLaunchKernelGGL((k_heavy<K, false, 1>), dim3(hg), dim3(nt), lds, st, P, pl->counters + kCtNum + 16);
+      hipLaunchKernelGGL((k_heavy<K, false, 1>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 16);
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 0, true, st));
   }
@@ -537,11 +572,14 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
 
 template <int K>
 sg_status launch_batched(sg_plan *pl, hipStream_t st) {
-  const Plan &P = pl->P;
-  const int nt = pl->tune.block_threads;
-  const int lds = pl->tune.lds_bytes;
+  // heavy windows are planned for the heavy workgroups, which also fit
+  // every mid vector when given the larger of the two LDS budgets
+  const int nt = pl->tune.heavy_threads;
+  const int lds = std::max(pl->tune.lds_bytes, pl->tune.heavy_lds_bytes);
+  Plan P = pl->P;
+  P.lds_words = lds / 4;
   const sg_sym_info &I = pl->info[0];
-  const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
+  const int64_t persist = resident_blocks(pl->ncu, nt, lds, kWavesPerSimd);
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
   SG_TRY(mark(pl, 0, false, st));
   const int mode = pl->has_mode[0] && pl->has_mode[1] ? 2 : (pl->has_mode[1] ? 1 : 0);
@@ -653,6 +691,10 @@ void sg_tuning_default(int32_t kind, sg_tuning *t) {
   t->validate = 0;
   t->xcd_ranges = 0;
   t->bitmap_mb = 4096;
+  // the heavy windows run best with the same two workgroups per compute
+  // unit (wider single workgroups halve the window count but not the time)
+  t->heavy_threads = 512;
+  t->heavy_lds_bytes = 77 * 1024;
 }
 
 const char *sg_last_error(void) { return g_last_error; }
@@ -683,7 +725,7 @@ sg_status sg_spgemm_workspace_size(const sg_semiring *sr, int32_t nprod, const s
   sg_tuning t;
   if (tuning) t = *tuning; else sg_tuning_default(sr->kind, &t);
   normalise(t, sr->kind);
-  const int win = heavy_window(t, sr->kind);
+  const int win = heavy_window(heavy_view(t), sr->kind);
   make_shape(sr->kind, nprod, A, B, grp, ngroup, t, win, sh);
   Layout L = carve(nullptr, nprod, A, B, ngroup, sh, grp);
   *ws_bytes = L.bytes;
@@ -703,7 +745,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   sg_tuning t;
   if (tuning) t = *tuning; else sg_tuning_default(sr->kind, &t);
   normalise(t, sr->kind);
-  const int win = heavy_window(t, sr->kind);
+  const int win = heavy_window(heavy_view(t), sr->kind);
   make_shape(sr->kind, nprod, A, B, grp, ngroup, t, win, sh);
   Layout L = carve(ws, nprod, A, B, ngroup, sh, grp);
   if (ws_bytes < L.bytes) return SG_ERR_WORKSPACE;
@@ -736,12 +778,25 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   pl->ndense_ptr = sh.ndense_ptr;
   pl->out_minor = sh.minor;
   pl->out_major = sh.major;
-  for (int32_t g = 0; g < ngroup; ++g) pl->has_mode[sh.geom[g].mode] = true;
+  for (int32_t g = 0; g < ngroup; ++g) {
+    const Geom &ge = sh.geom[g];
+    pl->has_mode[ge.mode] = true;
+    // count passes: the mid tier marks a whole-range bitmap plus its
+    // touched-word bitmap; the heavy tier a whole-range bitmap plus bucket
+    // counters (rank windows) or one bucket's flags (dense windows)
+    const int64_t nw32 = (sh.minor[g] + 31) / 32;
+    const int64_t mid_b = t.mid_kind == 0 ? 4 * ((nw32 + (nw32 + 31) / 32 + 1) & ~1ll) : (int64_t)t.lds_bytes;
+    const int64_t heavy_b = ge.mode == 1 ? 4 * (nw32 + ge.nsplit) : 4 * ((((int64_t)ge.sw + 31) / 32 + 1) & ~1ll);
+    pl->lds_mid_count = (int)std::max<int64_t>(pl->lds_mid_count, std::min<int64_t>(mid_b, t.lds_bytes));
+    pl->lds_heavy_count = (int)std::max<int64_t>(pl->lds_heavy_count, std::min<int64_t>(heavy_b, t.heavy_lds_bytes));
+  }
+  pl->lds_mid_count = (pl->lds_mid_count + 15) & ~15;
+  pl->lds_heavy_count = (pl->lds_heavy_count + 15) & ~15;
   pl->info.assign(ngroup, sg_sym_info{});
   SG_HIP(hipHostMalloc((void **)&pl->outs_host, sizeof(OutDev) * ngroup, hipHostMallocDefault));
   SG_HIP(hipHostMalloc((void **)&pl->host_stats, sizeof(int64_t) * ((size_t)ngroup * kStCount + kCtNum),
                        hipHostMallocDefault));
-  SG_TRY(dispatch<RunAttr>(sr->kind, t.lds_bytes));
+  SG_TRY(dispatch<RunAttr>(sr->kind, std::max(t.lds_bytes, t.heavy_lds_bytes)));
 
   // host tables: products (ordered as given; output vectors follow group order)
   std::vector<int32_t> order(nprod);
@@ -893,11 +948,9 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   // flops per output vector, then the tiers
   if (sh.nov_max > 0) {
     const int64_t waves = std::min<int64_t>(sh.nov_max, (int64_t)pl->ncu * 64);
-    hipLaunchKernelGGL(k_flops, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, L.gstat);
-    SG_HIP(hipGetLastError());
     BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier};
-    hipLaunchKernelGGL(k_bin, dim3((unsigned)grid_for(sh.nov_max, 256)), dim3(256), 0, st, P, bp, L.counters, L.tiny,
-                       L.mid, L.heavy);
+    hipLaunchKernelGGL(k_flops_bin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, bp, L.gstat, L.counters,
+                       L.tiny, L.mid, L.heavy);
     SG_HIP(hipGetLastError());
   }
   for (int32_t q = 0; q < nprod; ++q) {

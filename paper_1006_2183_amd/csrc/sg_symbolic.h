@@ -217,99 +217,6 @@ __global__ void k_group_ranges(const int32_t *ov_group, const int64_t *counters,
 // flops_j = sum over stored (k, s) of S(:, j) of nnz(G(:, k)); a k with an
 // empty G vector contributes nothing (the Isect observation, Section 2.4).
 // For a doubly compressed G the resolved vector is kept per S entry.
-// flops of G(:, k) summed over the stored entries e in [e0, e1) of S, one
-// entry per lane or one lane walking all of them (lane-serial); resolves
-// doubly compressed G vectors into d.gres on the way.
-__device__ __forceinline__ int64_t entry_flops(const ProdDev &d, int64_t e) {
-  const int32_t k = gload(d.s_idx + e);
-  int32_t gt;
-  if (d.g_vid) {
-    gt = aux_find(d, k);
-    gstore(d.gres + e, gt);
-  } else {
-    gt = (k >= 0 && k < d.g_nvec) ? k : -1;
-  }
-  return gt >= 0 ? gload(d.g_ptr + gt + 1) - gload(d.g_ptr + gt) : 0;
-}
-
-// Flops per output vector (and per-group totals, bound and maximum). A
-// wavefront takes 64 consecutive output vectors, one per lane: vectors with
-// one segment of the chunk's common product and at most kSerial streamed
-// entries are summed by their own lane; the others are summed by the whole
-// wavefront, one at a time.
-__global__ void k_flops(Plan P, int64_t *gstat) {
-  constexpr int kSerial = 32;
-  const int l = lane();
-  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const int64_t nov = P.counters[kCtNov];
-  for (int64_t v0 = wave * kWave; v0 < nov; v0 += nwaves * kWave) {
-    const int64_t v = v0 + l;
-    const bool valid = v < nov;
-    int32_t p = -1, t = 0;
-    if (valid) {
-      const int64_t s0 = gload(P.ov_seg + v);
-      if (gload(P.ov_seg + v + 1) - s0 == 1) {
-        p = gload(P.seg_prod + s0);
-        t = gload(P.seg_svec + s0);
-      }
-    }
-    const uint64_t hasp = __ballot(p >= 0);
-    int64_t f = 0;
-    bool done = false;
-    if (hasp) {
-      const int32_t p0 = __builtin_amdgcn_readlane(p, __ffsll((unsigned long long)hasp) - 1);
-      const ProdDev d = uload(P.prods + p0);
-      if (p == p0) {
-        const int64_t e0 = gload(d.s_ptr + t), e1 = gload(d.s_ptr + t + 1);
-        if (e1 - e0 <= kSerial) {
-          for (int64_t e = e0; e < e1; ++e) f += entry_flops(d, e);
-          done = true;
-        }
-      }
-    }
-    uint64_t coop = __ballot(valid && !done);
-    while (coop) {
-      const int x = __ffsll((unsigned long long)coop) - 1;
-      coop &= coop - 1ull;
-      const int64_t vx = v0 + x;
-      int64_t fx = 0;
-      const int64_t s1 = uload(P.ov_seg + vx + 1);
-      for (int64_t s = uload(P.ov_seg + vx); s < s1; ++s) {
-        const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
-        const int32_t tt = uload(P.seg_svec + s);
-        const int64_t e1 = uload(d.s_ptr + tt + 1);
-        for (int64_t e = uload(d.s_ptr + tt) + l; e < e1; e += kWave) fx += entry_flops(d, e);
-      }
-      fx = wave_sum64(fx);
-      if (l == x) f = fx;
-    }
-    int32_t g = -1;
-    int64_t minor = 0;
-    if (valid) {
-      gstore(P.ov_flops + v, f);
-      g = gload(P.ov_group + v);
-      minor = gload(&P.groups[g].minor);
-    }
-    const int64_t ub = f < minor ? f : minor;
-    // per-group totals: one set of atomics per group present in the chunk
-    uint64_t pend = __ballot(valid);
-    while (pend) {
-      const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
-      const bool mine = valid && g == gx;
-      pend &= ~__ballot(mine);
-      const int64_t sf = wave_sum64(mine ? f : 0);
-      const int64_t su = wave_sum64(mine ? ub : 0);
-      const int64_t mx = wave_max64(mine ? f : 0);
-      if (l == 0) {
-        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStFlops], (unsigned long long)sf);
-        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStUb], (unsigned long long)su);
-        atomicMax((unsigned long long *)&gstat[gx * kStCount + kStMaxFlops], (unsigned long long)mx);
-      }
-    }
-  }
-}
-
 // ---- tier binning -----------------------------------------------------------
 // Wave-aggregated append of this lane's vector to list `which` if `take`.
 __device__ __forceinline__ void append(bool take, int32_t v, int32_t *list, int64_t *counter) {
@@ -329,37 +236,125 @@ struct BinParams {
   int32_t force;
 };
 
-__global__ void k_bin(Plan P, BinParams bp, int64_t *counters, int32_t *tiny, int32_t *mid, int32_t *heavy) {
+// G vector of stored S entry e (-1: absent); a doubly compressed G is
+// resolved through AUX and the result kept in d.gres for the numeric kernels.
+__device__ __forceinline__ int32_t resolve_entry(const ProdDev &d, int64_t e, int32_t k) {
+  if (d.g_vid) {
+    const int32_t gt = aux_find(d, k);
+    gstore(d.gres + e, gt);
+    return gt;
+  }
+  return (k >= 0 && k < d.g_nvec) ? k : -1;
+}
+
+// Multiplications of the stored S entries e0 + l, e0 + l + stride, ... < e1
+// (stride 1 for one lane walking a short vector, 64 for a wavefront), four
+// entries in flight at a time.
+__device__ __forceinline__ int64_t entries_flops(const ProdDev &d, int64_t e0, int64_t e1, int64_t stride) {
+  int64_t f = 0;
+  for (int64_t e = e0; e < e1; e += 4 * stride) {
+    int32_t k[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = e + j * stride < e1 ? gload(d.s_idx + e + j * stride) : -1;
+    int32_t gt[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gt[j] = e + j * stride < e1 ? resolve_entry(d, e + j * stride, k[j]) : -1;
+    int64_t a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = gt[j] >= 0 ? gload(d.g_ptr + gt[j]) : 0;
+      b[j] = gt[j] >= 0 ? gload(d.g_ptr + gt[j] + 1) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f += b[j] - a[j];
+  }
+  return f;
+}
+
+// Flops per output vector, the group totals (flops, bound, largest vector)
+// and the tier of every vector (appended to the tiny, mid and heavy lists,
+// with per-tier flops and streamed entries). A wavefront takes 64
+// consecutive output vectors, one per lane: vectors with one segment of the
+// chunk's common product and at most kSerial streamed entries are summed by
+// their own lane; the others by the whole wavefront, one at a time.
+//
+// Tiers: no multiplication, none; else forced tier if any (a forced mid
+// vector that does not fit goes heavy); else tiny up to tiny_max flops; mid
+// when the size bound (flops capped by the id range) fits the mid
+// accumulator and the id range spans several split buckets (with one bucket
+// the heavy tier's single dense window is the better accumulator); else heavy.
+__global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *counters, int32_t *tiny, int32_t *mid,
+                            int32_t *heavy) {
+  constexpr int kSerial = 32;
+  const int l = lane();
+  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int64_t nov = counters[kCtNov];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t tf[3] = {0, 0, 0}, ts[3] = {0, 0, 0};
-  // loop bound is uniform per wave so the ballots see the whole wave
-  for (int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & ~(int64_t)(kWave - 1); v0 < nov; v0 += stride) {
-    int64_t v = v0 + lane();
-    int tier = -1;
+  for (int64_t v0 = wave * kWave; v0 < nov; v0 += nwaves * kWave) {
+    const int64_t v = v0 + l;
+    const bool valid = v < nov;
+    int32_t p = -1, t = 0;
+    if (valid) {
+      const int64_t s0 = gload(P.ov_seg + v);
+      if (gload(P.ov_seg + v + 1) - s0 == 1) {
+        p = gload(P.seg_prod + s0);
+        t = gload(P.seg_svec + s0);
+      }
+    }
+    const uint64_t hasp = __ballot(p >= 0);
     int64_t f = 0, sent = 0;
-    if (v < nov) {
-      f = P.ov_flops[v];
-      const GroupDev &g = P.groups[P.ov_group[v]];
-      int64_t ub = f < g.minor ? f : g.minor;
-      bool tiny_ok = f <= bp.tiny_max;
-      bool mid_fit = g.mid_ok > 0 && ub <= (int64_t)g.mid_ok && ub <= (int64_t)bp.mid_cap;
-      // with a single window the heavy tier's dense accumulator covers the
-      // whole id range, which beats the mid tier unless it is forced
-      bool mid_ok = mid_fit && g.nsplit > 1;
+    bool done = false;
+    if (hasp) {
+      const int32_t p0 = __builtin_amdgcn_readlane(p, __ffsll((unsigned long long)hasp) - 1);
+      const ProdDev d = uload(P.prods + p0);
+      if (p == p0) {
+        const int64_t e0 = gload(d.s_ptr + t), e1 = gload(d.s_ptr + t + 1);
+        if (e1 - e0 <= kSerial) {
+          f = entries_flops(d, e0, e1, 1);
+          sent = e1 - e0;
+          done = true;
+        }
+      }
+    }
+    uint64_t coop = __ballot(valid && !done);
+    while (coop) {
+      const int x = __ffsll((unsigned long long)coop) - 1;
+      coop &= coop - 1ull;
+      const int64_t vx = v0 + x;
+      int64_t fx = 0, sx = 0;
+      const int64_t s1 = uload(P.ov_seg + vx + 1);
+      for (int64_t s = uload(P.ov_seg + vx); s < s1; ++s) {
+        const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+        const int32_t tt = uload(P.seg_svec + s);
+        const int64_t e0 = uload(d.s_ptr + tt), e1 = uload(d.s_ptr + tt + 1);
+        fx += entries_flops(d, e0 + l, e1, kWave);
+        sx += e1 - e0;
+      }
+      fx = wave_sum64(fx);
+      if (l == x) {
+        f = fx;
+        sent = sx;
+      }
+    }
+    int32_t g = -1;
+    int64_t minor = 0;
+    int tier = -1;
+    if (valid) {
+      gstore(P.ov_flops + v, f);
+      g = gload(P.ov_group + v);
+      const GroupDev &G = P.groups[g];
+      minor = gload(&G.minor);
+      const int32_t mid_ok_cap = gload(&G.mid_ok);
+      const int32_t nsplit = gload(&G.nsplit);
+      const int64_t ub = f < minor ? f : minor;
+      const bool mid_fit = mid_ok_cap > 0 && ub <= (int64_t)mid_ok_cap && ub <= (int64_t)bp.mid_cap;
       if (f == 0) tier = -1;
       else if (bp.force == 2) tier = 2;
       else if (bp.force == 1) tier = mid_fit ? 1 : 2;
-      else if (tiny_ok) tier = 0;
-      else if (mid_ok) tier = 1;
+      else if (f <= bp.tiny_max) tier = 0;
+      else if (mid_fit && nsplit > 1) tier = 1;
       else tier = 2;
-      if (tier >= 0) {
-        for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
-          const ProdDev &d = P.prods[P.seg_prod[s]];
-          const int32_t t = P.seg_svec[s];
-          sent += d.s_ptr[t + 1] - d.s_ptr[t];
-        }
-      }
     }
     append(tier == 0, (int32_t)v, tiny, &counters[kCtTiny]);
     append(tier == 1, (int32_t)v, mid, &counters[kCtMid]);
@@ -368,11 +363,27 @@ __global__ void k_bin(Plan P, BinParams bp, int64_t *counters, int32_t *tiny, in
       tf[tier] += f;
       ts[tier] += sent;
     }
+    const int64_t ub = f < minor ? f : minor;
+    // per-group totals: one set of atomics per group present in the chunk
+    uint64_t pend = __ballot(valid);
+    while (pend) {
+      const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
+      const bool mine = valid && g == gx;
+      pend &= ~__ballot(mine);
+      const int64_t sf = wave_sum64(mine ? f : 0);
+      const int64_t su = wave_sum64(mine ? ub : 0);
+      const int64_t mx = wave_max64(mine ? f : 0);
+      if (l == 0) {
+        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStFlops], (unsigned long long)sf);
+        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStUb], (unsigned long long)su);
+        atomicMax((unsigned long long *)&gstat[gx * kStCount + kStMaxFlops], (unsigned long long)mx);
+      }
+    }
   }
   for (int x = 0; x < 3; ++x) {
     const int64_t a = wave_sum64(tf[x]);
     const int64_t b = wave_sum64(ts[x]);
-    if (lane() == 0 && (a | b)) {
+    if (l == 0 && (a | b)) {
       atomicAdd((unsigned long long *)&counters[kCtTierFlops + x], (unsigned long long)a);
       atomicAdd((unsigned long long *)&counters[kCtTierSent + x], (unsigned long long)b);
     }

@@ -547,7 +547,9 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
   typedef Sr<K> SR;
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
-  constexpr int WS = SR::kVal ? 2 : 1;  // 32-bit LDS words per 32 ids
+  // 32-bit LDS words per 32 ids: {bits, prefix} with values, bits alone
+  // when counting or without values
+  constexpr int WS = (SR::kVal && !COUNT) ? 2 : 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wid = tid / kWave, nw = nt / kWave;
   const int nwds = (int)((hi - lo + 31) >> 5);
@@ -911,24 +913,50 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   const int wpb = G.sw >> 5;  // words per bucket
   uint32_t *keep = q < P.nkeep ? P.hbits + q * P.hstride : nullptr;
   int64_t local = 0;
-  // rounds of 64 consecutive words per wavefront; the words of one bucket
-  // are summed across the wavefront before the bucket counter is touched
-  for (int w0 = wid * kWave; w0 < nwds; w0 += nt) {
-    const int w = w0 + lane();
-    const uint32_t word = w < nwds ? bits[w] : 0u;
-    if (keep && w < nwds) gstore(keep + w, word);
-    const int c = __popc(word);
-    local += c;
-    if (word) bits[w] = 0;
-    const int bk = (w < nwds ? w : nwds - 1) / wpb;
-    const int bfirst = __builtin_amdgcn_readfirstlane(bk);
-    if (__ballot(bk != bfirst) == 0) {
-      const int sum = wave_sum(c);
-      if (lane() == 0 && sum) atomicAdd(&lbc[bfirst], sum);
-    } else if (c) {
-      atomicAdd(&lbc[bk], c);
+  // thread t owns the contiguous words [t * per, (t + 1) * per), per a
+  // multiple of 4: they are read and kept 16 bytes at a time, and their
+  // popcount goes to the bucket counter with one LDS atomic per bucket run
+  int per = (nwds + nt - 1) / nt;
+  per = (per + 3) & ~3;
+  const int w0 = tid * per < nwds ? tid * per : nwds;
+  const int w1 = w0 + per < nwds ? w0 + per : nwds;
+  const bool vec = ((((uintptr_t)bits) | (keep ? (uintptr_t)keep : 0)) & 15) == 0;
+  int bk_run = -1, acc = 0;
+  for (int w = w0; w < w1; w += 4) {
+    uint32_t x[4];
+    if (vec && w + 3 < w1) {
+      const u32x4 q = *(const u32x4 *)&bits[w];
+      x[0] = q.x;
+      x[1] = q.y;
+      x[2] = q.z;
+      x[3] = q.w;
+      if (keep) gstore((u32x4 *)(keep + w), q);
+      if (q.x | q.y | q.z | q.w) *(u32x4 *)&bits[w] = u32x4{0u, 0u, 0u, 0u};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        x[j] = w + j < w1 ? bits[w + j] : 0u;
+        if (w + j < w1) {
+          if (keep) gstore(keep + w + j, x[j]);
+          if (x[j]) bits[w + j] = 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (w + j >= w1) break;
+      const int c = __popc(x[j]);
+      const int bk = (w + j) / wpb;
+      if (bk != bk_run) {
+        if (acc) atomicAdd(&lbc[bk_run], acc);
+        bk_run = bk;
+        acc = 0;
+      }
+      acc += c;
+      local += c;
     }
   }
+  if (acc) atomicAdd(&lbc[bk_run], acc);
   const int64_t total = block_sum(local, scratch);
   for (int b = tid; b < G.nsplit; b += nt) {
     bc[b] = lbc[b];
@@ -1038,6 +1066,50 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
       if (i >= hi) break;
       heavy_item<K, MODE>(P, i, lds, scratch);
     }
+  }
+}
+
+// Count passes of the mid and heavy tiers. They need only the id bitmaps
+// (no values), so they run with a smaller LDS allocation; the mid count
+// pass also gets a register budget for twice the resident wavefronts of
+// the numeric kernels (it is bound by the latency of its gathers).
+constexpr int kCountWavesPerSimd = 8;
+
+template <int K>
+__global__ void __launch_bounds__(kBlockMax, kCountWavesPerSimd) k_mid_count(Plan P, int64_t *queue) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  __shared__ int64_t s_item;
+  zero_lds(lds, P.lds_words);
+  const int64_t n = P.counters[kCtMid];
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
+    __syncthreads();
+    const int64_t i = uni(s_item);
+    __syncthreads();
+    if (i >= n) break;
+    const int64_t v = uload(P.mid_list + i);
+    if (P.mid_kind == 0) rank_window<K, true, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, 0, lds, scratch);
+    else mid_hash_vector<K, true>(P, v, lds, scratch);
+  }
+}
+
+// (the heavy count pass keeps the numeric kernels' register budget: at the
+// higher occupancy its product walk spills and runs slower)
+template <int K, int MODE>
+__global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy_count(Plan P, int64_t *queue) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  __shared__ int64_t s_item;
+  zero_lds(lds, P.lds_words);
+  const int64_t n = P.counters[kCtHeavy];
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
+    __syncthreads();
+    const int64_t i = uni(s_item);
+    __syncthreads();
+    if (i >= n) break;
+    heavy_count<K, MODE>(P, i, lds, scratch);
   }
 }
 

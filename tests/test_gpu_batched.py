@@ -73,7 +73,8 @@ def test_summa_share_forced_tiers_and_order(sg):
     SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
     R, _ = oracle.spgemm(semiring, SA, SB)
     for force in (-1, 1, 2):
-        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=16384, block_threads=256)
+        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384,
+                           heavy_threads=256)
         C = BT.summa_share(semiring, dA, dB, tuning=t).to_host()
         assert_same(C, R, semiring, 0.0, f"force {force}")
     perm = [3, 0, 2, 1]
@@ -192,7 +193,7 @@ def test_autotune_keeps_results(sg, tmp_path):
     dA = sg.DevMat.from_host(A, "cuda", semiring)
     R, _ = oracle.spgemm(semiring, A, A)
     cache = AT.TuneCache(str(tmp_path / "tune.json"))
-    space = {"lds_bytes": [16384, 65536], "blocks_per_cu": [1, 3], "tiny_max_flops": [16]}
+    space = {"lds_bytes": [16384, 65536], "heavy_lds_bytes": [24576], "blocks_per_cu": [1, 3], "tiny_max_flops": [16]}
     res = AT.autotune(semiring, [dA], [dA], space=space, reps=1, cache=cache)
     assert not res["cached"] and res["tried"] >= 2
     again = AT.autotune(semiring, [dA], [dA], space=space, reps=1, cache=AT.TuneCache(str(tmp_path / "tune.json")))
@@ -200,7 +201,8 @@ def test_autotune_keeps_results(sg, tmp_path):
     t = AT.tuned(semiring, [dA], [dA], cache=cache)
     C = sg.spgemm(semiring, dA, dA, tuning=t).to_host()
     assert_same(C, R, semiring, 0.0, "tuned")
-    for cand in ({"lds_bytes": 16384}, {"blocks_per_cu": 3, "tiny_max_flops": 16}):
+    for cand in ({"lds_bytes": 16384}, {"heavy_lds_bytes": 24576, "heavy_threads": 256},
+                 {"blocks_per_cu": 3, "tiny_max_flops": 16}):
         C = sg.spgemm(semiring, dA, dA, tuning=sg.make_tuning(semiring, **cand)).to_host()
         assert_same(C, R, semiring, 0.0, str(cand))
     torch.cuda.synchronize()
@@ -220,7 +222,8 @@ def test_summa_share_many_segments(sg, force):
     SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
     R, _ = oracle.spgemm(semiring, SA, SB)
     for batched in (False, True):
-        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=24576, block_threads=512)
+        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=24576, block_threads=512, heavy_lds_bytes=24576,
+                           heavy_threads=512)
         C = BT.summa_share(semiring, dA, dB, tuning=t, batched=batched).to_host()
         assert_canonical(C)
         assert_same(C, R, semiring, 1e-12, f"force {force} batched {batched}")

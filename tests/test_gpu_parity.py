@@ -98,7 +98,8 @@ def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind,
     _say(f"case forced tier {force} mid_kind {mid_kind} heavy_kind {heavy_kind} bitmap_mb {bitmap_mb} {semiring}")
     A = W.rmat_matrix(13, 8, semiring, "csr", seed=4)
     C, info = gpu_product(sg, semiring, A, A, force_tier=force, mid_kind=mid_kind, heavy_kind=heavy_kind,
-                          lds_bytes=16384, block_threads=256, bitmap_mb=bitmap_mb)
+                          lds_bytes=16384, block_threads=256, bitmap_mb=bitmap_mb,
+                          heavy_lds_bytes=16384, heavy_threads=256)
     check(semiring, C, A, A, f"force{force}")
     if force == 2:
         assert info["n_mid"] == 0 and info["n_tiny"] == 0
@@ -116,7 +117,8 @@ def test_formats(sg, semiring, fa, fb, fo):
     Af = W.to_format(A, fa, semiring)
     Bf = W.to_format(A, fb, semiring)
     for force in (-1, 2):
-        C, _ = gpu_product(sg, semiring, Af, Bf, out_fmt=fo, force_tier=force, lds_bytes=8192, block_threads=128)
+        C, _ = gpu_product(sg, semiring, Af, Bf, out_fmt=fo, force_tier=force, lds_bytes=8192, block_threads=128,
+                                heavy_lds_bytes=8192, heavy_threads=128)
         assert C.fmt == fo
         check(semiring, C, Af, Bf, f"{fa}{fb}{fo}")
 
@@ -169,7 +171,8 @@ def test_edge_cases(sg, semiring):
         col = np.arange(n)
         Bd = W.from_triples(col, np.zeros(n, dtype=np.int64), W.random_values(rng, n, semiring), n, 1, fmt, semiring)
         Ah = W.random_sparse(n, n, 0.004, semiring, fmt, 3)
-        C, info = gpu_product(sg, semiring, Ah, Bd, lds_bytes=4096, block_threads=64)
+        C, info = gpu_product(sg, semiring, Ah, Bd, lds_bytes=4096, block_threads=64,
+                                  heavy_lds_bytes=4096, heavy_threads=64)
         check(semiring, C, Ah, Bd, "dense column")
         # rectangular, mostly empty vectors
         A = W.random_sparse(500, 7, 0.05, semiring, fmt, 4)

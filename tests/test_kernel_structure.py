@@ -37,7 +37,7 @@ def _asm(tmp_path):
 
 def queue_loop_report(asm: str):
     rows = []
-    for m in re.finditer(r"^(_ZN2sg(?:5k_mid|7k_heavy|9k_batched)\S*):.*?s_endpgm", asm, re.S | re.M):
+    for m in re.finditer(r"^(_ZN2sg(?:5k_mid|7k_heavy|9k_batched|11k_mid_count|13k_heavy_count)\S*):.*?s_endpgm", asm, re.S | re.M):
         name, body = m.group(1), m.group(0)
         lines = body.split("\n")
         atom = [i for i, l in enumerate(lines) if "global_atomic_add_x2" in l]
@@ -56,7 +56,7 @@ def queue_loop_report(asm: str):
 
 def test_queue_loops_stay_convergent(tmp_path):
     rows = queue_loop_report(_asm(str(tmp_path)))
-    # 4 semirings x (mid count/numeric + heavy count/numeric per window kind + batched per kind set)
+    # 4 semirings x (mid count and numeric, heavy count and numeric per window kind, batched per kind set)
     assert len(rows) == 36, f"expected 36 queue kernels, found {len(rows)}"
     bad = [r for r in rows if not r[1]]
     assert not bad, "queue loop restructured: " + "; ".join(f"{n}: {why}" for n, _, why in bad)
