@@ -39,6 +39,7 @@ namespace sg {
 // Step wraps a one-step lambda.
 template <class T, class F>
 struct Step {
+  static constexpr bool kFlat = false;
   F f;
   __device__ __forceinline__ uint64_t prep(int) const { return 0; }
   __device__ __forceinline__ void commit(int id, uint64_t, T v) { f(id, v); }
@@ -150,6 +151,55 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
   __builtin_amdgcn_wave_barrier();
 }
 
+// Products of one batch of (up to) 64 stored entries of S, one per lane
+// (lane e holds `len` products at G positions [gb, gb + len) with S value
+// sv), spread flat over the lanes: product f (in entry order) goes to lane
+// f mod 64 of round f / 64, so every round but the last keeps all 64 lanes
+// busy whatever the entry lengths. A lane finds the entry of its product by
+// a binary search of the lanes' inclusive product counts, four rounds at a
+// time with all their gathers in flight before the accumulator sees any.
+template <class SR, class Act>
+__device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
+                                         const typename SR::T *__restrict__ gval, Act &act) {
+  typedef typename SR::T T;
+  const int l = lane();
+  const int incl = wave_incl_scan(len);
+  const int tot = read_lane(incl, kWave - 1);
+  if (tot == 0) return;
+  const int st = incl - len;
+  const int64_t gbase = gb - st;  // G position of product f of this entry is gbase + f
+  for (int j0 = 0; j0 < tot; j0 += 4 * kWave) {
+    int e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int f = j0 + k * kWave + l;
+      e[k] = owner_of(incl, f < tot ? f : tot - 1);
+    }
+    int64_t g[4];
+    T s4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      g[k] = __shfl(gbase, e[k], kWave) + j0 + k * kWave + l;
+      s4[k] = __shfl(sv, e[k], kWave);
+    }
+    int32_t i4[4];
+    T v4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool ok = j0 + k * kWave + l < tot;
+      i4[k] = ok ? gload(gidx + g[k]) : 0;
+      v4[k] = (SR::kVal && ok) ? gload(gval + g[k]) : T();
+    }
+    uint64_t t4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t4[k] = j0 + k * kWave + l < tot ? act.prep(i4[k]) : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (j0 + k * kWave + l < tot) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Load the lane's stored S entry e of product d and describe its products:
 // the whole G vector (b0 < 0) or only its ids in split buckets [b0, b1).
 template <class SR>
@@ -212,7 +262,13 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
       const int a = st > f0 ? st : f0;
       const int e = incl < f1 ? incl : f1;
       const int len2 = e > a ? e - a : 0;
-      run_batch<SR>(len2, gb + (a - st), sv, d.g_idx, (const T *)d.g_val, act);
+      // the rank accumulator (numeric windows) takes the products flat over
+      // the lanes; bitmap marks and dense windows keep the entry groups,
+      // whose lane layout suits their LDS atomics better
+      if constexpr (Act::kFlat)
+        run_flat<SR>(len2, gb + (a - st), sv, d.g_idx, (const T *)d.g_val, act);
+      else
+        run_batch<SR>(len2, gb + (a - st), sv, d.g_idx, (const T *)d.g_val, act);
     }
   }
 }
@@ -459,6 +515,7 @@ template <class SR>
 struct RankAcc {
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
+  static constexpr bool kFlat = true;
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
