@@ -156,9 +156,9 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
 // sv), spread flat over the lanes: product f (in entry order) goes to lane
 // f mod 64 of round f / 64, so every round but the last keeps all 64 lanes
 // busy whatever the entry lengths. A lane finds the entry of its product by
-// a binary search of the lanes' inclusive product counts, four rounds at a
+// a binary search of the lanes' inclusive product counts, R rounds at a
 // time with all their gathers in flight before the accumulator sees any.
-template <class SR, class Act>
+template <class SR, class Act, int R = 4>
 __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
                                          const typename SR::T *__restrict__ gval, Act &act) {
   typedef typename SR::T T;
@@ -168,33 +168,33 @@ __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv,
   if (tot == 0) return;
   const int st = incl - len;
   const int64_t gbase = gb - st;  // G position of product f of this entry is gbase + f
-  for (int j0 = 0; j0 < tot; j0 += 4 * kWave) {
-    int e[4];
+  for (int j0 = 0; j0 < tot; j0 += R * kWave) {
+    int e[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < R; ++k) {
       const int f = j0 + k * kWave + l;
       e[k] = owner_of(incl, f < tot ? f : tot - 1);
     }
-    int64_t g[4];
-    T s4[4];
+    int64_t g[R];
+    T s4[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < R; ++k) {
       g[k] = __shfl(gbase, e[k], kWave) + j0 + k * kWave + l;
       s4[k] = __shfl(sv, e[k], kWave);
     }
-    int32_t i4[4];
-    T v4[4];
+    int32_t i4[R];
+    T v4[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < R; ++k) {
       const bool ok = j0 + k * kWave + l < tot;
       i4[k] = ok ? gload(gidx + g[k]) : 0;
       v4[k] = (SR::kVal && ok) ? gload(gval + g[k]) : T();
     }
-    uint64_t t4[4];
+    uint64_t t4[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) t4[k] = j0 + k * kWave + l < tot ? act.prep(i4[k]) : 0;
+    for (int k = 0; k < R; ++k) t4[k] = j0 + k * kWave + l < tot ? act.prep(i4[k]) : 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < R; ++k)
       if (j0 + k * kWave + l < tot) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
   }
   __builtin_amdgcn_wave_barrier();
