@@ -76,7 +76,11 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
   const int gs = 1 << lg;
   const int ng = kWave >> lg;
   const int gi = l >> lg;
-  const int li = l & (gs - 1);
+  // position of this lane inside its group's run of gs consecutive products:
+  // a bijection that puts neighbouring lanes 9 products apart, so that the
+  // sorted ids of neighbouring lanes seldom share a 32-id bitmap word (same
+  // word atomics serialise in LDS); the run's cache lines are unchanged
+  const int li = ((l & (gs - 1)) * 9) & (gs - 1);
   uint8_t *own = s_own + (threadIdx.x / kWave) * kWave;
   if (len > 0) own[__popcll(m & ((1ull << l) - 1ull))] = (uint8_t)l;
   __builtin_amdgcn_wave_barrier();
