@@ -959,7 +959,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     if (d.nsplit > 1 && sh.wsplit_src[p] < 0 && d.g_nvec > 0) {
       const int64_t n = d.g_nvec * (int64_t)(d.nsplit + 1);
       hipLaunchKernelGGL(k_wsplit, dim3((unsigned)grid_for(n, kFillThreads)), dim3(kFillThreads), 0, st, d.g_ptr,
-                         d.g_idx, d.g_nvec, d.nsplit, sh.geom[grp[p]].sw, d.wsplit);
+                         d.g_idx, d.g_nvec, d.nsplit, sh.geom[grp[p]].sw, d.wsplit, L.counters);
       SG_HIP(hipGetLastError());
     }
   }

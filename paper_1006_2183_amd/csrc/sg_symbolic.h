@@ -286,100 +286,146 @@ __device__ __forceinline__ int64_t entries_flops(const ProdDev &d, int64_t e0, i
 __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *counters, int32_t *tiny, int32_t *mid,
                             int32_t *heavy) {
   constexpr int kSerial = 32;
+  constexpr int kBatch = 8;  // chunks whose list appends share one atomic per tier
   const int l = lane();
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int64_t nov = counters[kCtNov];
   int64_t tf[3] = {0, 0, 0}, ts[3] = {0, 0, 0};
-  for (int64_t v0 = wave * kWave; v0 < nov; v0 += nwaves * kWave) {
-    const int64_t v = v0 + l;
-    const bool valid = v < nov;
-    int32_t p = -1, t = 0;
-    if (valid) {
-      const int64_t s0 = gload(P.ov_seg + v);
-      if (gload(P.ov_seg + v + 1) - s0 == 1) {
-        p = gload(P.seg_prod + s0);
-        t = gload(P.seg_svec + s0);
-      }
+  // group totals of the current group, flushed when the group changes
+  int32_t cur_g = -1;
+  int64_t acc_f = 0, acc_ub = 0, acc_max = 0;
+  auto flush_group = [&]() {
+    if (cur_g < 0) return;
+    const int64_t sf = wave_sum64(acc_f), su = wave_sum64(acc_ub), mx = wave_max64(acc_max);
+    if (l == 0) {
+      atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)sf);
+      atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStUb], (unsigned long long)su);
+      atomicMax((unsigned long long *)&gstat[cur_g * kStCount + kStMaxFlops], (unsigned long long)mx);
     }
-    const uint64_t hasp = __ballot(p >= 0);
-    int64_t f = 0, sent = 0;
-    bool done = false;
-    if (hasp) {
-      const int32_t p0 = __builtin_amdgcn_readlane(p, __ffsll((unsigned long long)hasp) - 1);
-      const ProdDev d = uload(P.prods + p0);
-      if (p == p0) {
-        const int64_t e0 = gload(d.s_ptr + t), e1 = gload(d.s_ptr + t + 1);
-        if (e1 - e0 <= kSerial) {
-          f = entries_flops(d, e0, e1, 1);
-          sent = e1 - e0;
-          done = true;
+    acc_f = acc_ub = acc_max = 0;
+  };
+  // chunks per batch: one while the chunks do not outnumber the wavefronts
+  const int64_t nchunks = (nov + kWave - 1) / kWave;
+  const int64_t nbq = nchunks / nwaves;
+  const int nb = nbq < 1 ? 1 : (nbq > kBatch ? kBatch : (int)nbq);
+  for (int64_t c0 = wave * nb; c0 < nchunks; c0 += nwaves * nb) {
+    int8_t tier_of[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int64_t v0 = (c0 + i) * kWave;
+      tier_of[i] = -1;
+      if (i >= nb || v0 >= nov) continue;  // uniform
+      const int64_t v = v0 + l;
+      const bool valid = v < nov;
+      int32_t p = -1, t = 0;
+      if (valid) {
+        const int64_t s0 = gload(P.ov_seg + v);
+        if (gload(P.ov_seg + v + 1) - s0 == 1) {
+          p = gload(P.seg_prod + s0);
+          t = gload(P.seg_svec + s0);
+        }
+      }
+      const uint64_t hasp = __ballot(p >= 0);
+      int64_t f = 0, sent = 0;
+      bool done = false;
+      if (hasp) {
+        const int32_t p0 = __builtin_amdgcn_readlane(p, __ffsll((unsigned long long)hasp) - 1);
+        const ProdDev d = uload(P.prods + p0);
+        if (p == p0) {
+          const int64_t e0 = gload(d.s_ptr + t), e1 = gload(d.s_ptr + t + 1);
+          if (e1 - e0 <= kSerial) {
+            f = entries_flops(d, e0, e1, 1);
+            sent = e1 - e0;
+            done = true;
+          }
+        }
+      }
+      uint64_t coop = __ballot(valid && !done);
+      while (coop) {
+        const int x = __ffsll((unsigned long long)coop) - 1;
+        coop &= coop - 1ull;
+        const int64_t vx = v0 + x;
+        int64_t fx = 0, sx = 0;
+        const int64_t s1 = uload(P.ov_seg + vx + 1);
+        for (int64_t s = uload(P.ov_seg + vx); s < s1; ++s) {
+          const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+          const int32_t tt = uload(P.seg_svec + s);
+          const int64_t e0 = uload(d.s_ptr + tt), e1 = uload(d.s_ptr + tt + 1);
+          fx += entries_flops(d, e0 + l, e1, kWave);
+          sx += e1 - e0;
+        }
+        fx = wave_sum64(fx);
+        if (l == x) {
+          f = fx;
+          sent = sx;
+        }
+      }
+      int32_t g = -1;
+      int64_t minor = 0;
+      int tier = -1;
+      if (valid) {
+        gstore(P.ov_flops + v, f);
+        g = gload(P.ov_group + v);
+        const GroupDev &G = P.groups[g];
+        minor = gload(&G.minor);
+        const int32_t mid_ok_cap = gload(&G.mid_ok);
+        const int32_t nsplit = gload(&G.nsplit);
+        const int64_t ub = f < minor ? f : minor;
+        const bool mid_fit = mid_ok_cap > 0 && ub <= (int64_t)mid_ok_cap && ub <= (int64_t)bp.mid_cap;
+        if (f == 0) tier = -1;
+        else if (bp.force == 2) tier = 2;
+        else if (bp.force == 1) tier = mid_fit ? 1 : 2;
+        else if (f <= bp.tiny_max) tier = 0;
+        else if (mid_fit && nsplit > 1) tier = 1;
+        else tier = 2;
+      }
+      tier_of[i] = (int8_t)tier;
+      if (tier >= 0) {
+        tf[tier] += f;
+        ts[tier] += sent;
+      }
+      // group totals: registers while the chunk stays in the current group
+      const int64_t ub = f < minor ? f : minor;
+      uint64_t pend = __ballot(valid);
+      while (pend) {
+        const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
+        const bool mine = valid && g == gx;
+        pend &= ~__ballot(mine);
+        if (gx != cur_g) {
+          flush_group();
+          cur_g = gx;
+        }
+        if (mine) {
+          acc_f += f;
+          acc_ub += ub;
+          acc_max = f > acc_max ? f : acc_max;
         }
       }
     }
-    uint64_t coop = __ballot(valid && !done);
-    while (coop) {
-      const int x = __ffsll((unsigned long long)coop) - 1;
-      coop &= coop - 1ull;
-      const int64_t vx = v0 + x;
-      int64_t fx = 0, sx = 0;
-      const int64_t s1 = uload(P.ov_seg + vx + 1);
-      for (int64_t s = uload(P.ov_seg + vx); s < s1; ++s) {
-        const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
-        const int32_t tt = uload(P.seg_svec + s);
-        const int64_t e0 = uload(d.s_ptr + tt), e1 = uload(d.s_ptr + tt + 1);
-        fx += entries_flops(d, e0 + l, e1, kWave);
-        sx += e1 - e0;
+    // list appends of the kBatch chunks: one atomic per tier
+    for (int x = 0; x < 3; ++x) {
+      int32_t *list = x == 0 ? tiny : (x == 1 ? mid : heavy);
+      uint64_t m[kBatch];
+      int total = 0;
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        m[i] = __ballot(tier_of[i] == x);
+        total += __popcll(m[i]);
       }
-      fx = wave_sum64(fx);
-      if (l == x) {
-        f = fx;
-        sent = sx;
-      }
-    }
-    int32_t g = -1;
-    int64_t minor = 0;
-    int tier = -1;
-    if (valid) {
-      gstore(P.ov_flops + v, f);
-      g = gload(P.ov_group + v);
-      const GroupDev &G = P.groups[g];
-      minor = gload(&G.minor);
-      const int32_t mid_ok_cap = gload(&G.mid_ok);
-      const int32_t nsplit = gload(&G.nsplit);
-      const int64_t ub = f < minor ? f : minor;
-      const bool mid_fit = mid_ok_cap > 0 && ub <= (int64_t)mid_ok_cap && ub <= (int64_t)bp.mid_cap;
-      if (f == 0) tier = -1;
-      else if (bp.force == 2) tier = 2;
-      else if (bp.force == 1) tier = mid_fit ? 1 : 2;
-      else if (f <= bp.tiny_max) tier = 0;
-      else if (mid_fit && nsplit > 1) tier = 1;
-      else tier = 2;
-    }
-    append(tier == 0, (int32_t)v, tiny, &counters[kCtTiny]);
-    append(tier == 1, (int32_t)v, mid, &counters[kCtMid]);
-    append(tier == 2, (int32_t)v, heavy, &counters[kCtHeavy]);
-    if (tier >= 0) {
-      tf[tier] += f;
-      ts[tier] += sent;
-    }
-    const int64_t ub = f < minor ? f : minor;
-    // per-group totals: one set of atomics per group present in the chunk
-    uint64_t pend = __ballot(valid);
-    while (pend) {
-      const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
-      const bool mine = valid && g == gx;
-      pend &= ~__ballot(mine);
-      const int64_t sf = wave_sum64(mine ? f : 0);
-      const int64_t su = wave_sum64(mine ? ub : 0);
-      const int64_t mx = wave_max64(mine ? f : 0);
-      if (l == 0) {
-        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStFlops], (unsigned long long)sf);
-        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStUb], (unsigned long long)su);
-        atomicMax((unsigned long long *)&gstat[gx * kStCount + kStMaxFlops], (unsigned long long)mx);
+      if (total == 0) continue;
+      int64_t base = 0;
+      if (l == 0) base = (int64_t)atomicAdd((unsigned long long *)&counters[kCtTiny + x], (unsigned long long)total);
+      base = __shfl(base, 0, kWave);
+      const uint64_t below = (1ull << l) - 1ull;
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        if (tier_of[i] == x) list[base + __popcll(m[i] & below)] = (int32_t)((c0 + i) * kWave + l);
+        base += __popcll(m[i]);
       }
     }
   }
+  flush_group();
   for (int x = 0; x < 3; ++x) {
     const int64_t a = wave_sum64(tf[x]);
     const int64_t b = wave_sum64(ts[x]);
@@ -405,8 +451,12 @@ __global__ void k_tier_nnz(Plan P, int64_t *counters) {
 
 // Window split points of every G vector: wsplit[t * (nsplit + 1) + c] is
 // the offset inside G(:, t) of the first id >= c * sw.
+// Split points of every G vector at the bucket boundaries (only the heavy
+// windows read them: without heavy vectors, which binning has counted by
+// now, the launch does nothing).
 __global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_nvec, int32_t nsplit, int32_t sw,
-                         int32_t *wsplit) {
+                         int32_t *wsplit, const int64_t *counters) {
+  if (counters[kCtHeavy] == 0) return;
   int64_t n = g_nvec * (nsplit + 1);
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     int64_t t = x / (nsplit + 1);
