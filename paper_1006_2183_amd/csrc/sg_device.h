@@ -340,6 +340,9 @@ __device__ __forceinline__ int owner_of(int P, int f) {
 }
 
 // Exclusive scan across the workgroup; `scratch` holds kMaxWaves + 1 int64.
+// Every thread sums the wavefront totals before its own wavefront (at most
+// 16 broadcast reads) instead of one thread scanning them between two
+// barriers; the last barrier keeps `scratch` intact until all have read it.
 __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *scratch, int64_t *total) {
   const int l = lane();
   const int w = threadIdx.x / kWave;
@@ -347,20 +350,15 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *scratch, 
   int64_t inc = wave_incl_scan64(x);
   if (l == kWave - 1) scratch[w] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < nw; ++i) {
-      int64_t t = scratch[i];
-      scratch[i] = run;
-      run += t;
-    }
-    scratch[nw] = run;
+  int64_t before = 0, all = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int64_t t = scratch[i];
+    before += i < w ? t : 0;
+    all += t;
   }
+  *total = all;
   __syncthreads();
-  int64_t r = scratch[w] + inc - x;
-  *total = scratch[nw];
-  __syncthreads();
-  return r;
+  return before + inc - x;
 }
 
 __device__ __forceinline__ int64_t block_sum(int64_t x, int64_t *scratch) {
