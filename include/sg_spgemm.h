@@ -143,6 +143,16 @@ typedef struct {
  *                    planned to fit it, so a larger budget means fewer,
  *                    wider windows (0 = lds_bytes). The persistent launch
  *                    uses the larger of the two budgets.
+ *   entry_mb         heavy tier: MiB of workspace for per-window entry
+ *                    records (the G range of every streamed entry inside a
+ *                    window, and its S value), written once by the symbolic
+ *                    phase so that the numeric walk reads one record per entry
+ *                    instead of the entry, its G vector and its window split
+ *                    points in turn; windows beyond the budget, and vectors
+ *                    fed by several products, walk the operands (0 = off, the
+ *                    default: building them costs the symbolic phase about
+ *                    what they save one numeric run, so they pay only for a
+ *                    plan whose numeric phase is replayed)
  */
 typedef struct {
     int32_t tiny_max_flops;
@@ -159,6 +169,7 @@ typedef struct {
     int32_t bitmap_mb;
     int32_t heavy_threads;
     int32_t heavy_lds_bytes;
+    int32_t entry_mb;
 } sg_tuning;
 
 /* Host-side sizes of one output, valid when sg_spgemm_symbolic returns. */

@@ -59,7 +59,8 @@ class sg_tuning(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("xcd_ranges", ctypes.c_int32),
                 ("bitmap_mb", ctypes.c_int32),
                 ("heavy_threads", ctypes.c_int32),
-                ("heavy_lds_bytes", ctypes.c_int32)]
+                ("heavy_lds_bytes", ctypes.c_int32),
+                ("entry_mb", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -71,6 +71,9 @@ struct GroupDev {
 // One heavy-tier item: the window of split buckets [b0, b1) of output
 // vector v (position q in the heavy list) of group g, whose entries start at
 // `pos` inside the group's output arrays.
+// With entry records, rbase >= 0 is the first of the window's nrec records
+// (one per stored S entry of v: the entry's G range inside the window and
+// its S value), written once by the symbolic phase.
 struct ItemDev {
   int32_t v;
   int32_t g;
@@ -78,7 +81,8 @@ struct ItemDev {
   int32_t b1;
   int64_t pos;
   int32_t q;
-  int32_t pad;
+  int32_t nrec;
+  int64_t rbase;
 };
 
 struct OutDev {
@@ -148,6 +152,10 @@ struct Plan {
   uint32_t *hbits;           // kept id bitmaps of the first nkeep heavy vectors
   int64_t hstride;           // 32-bit words per kept bitmap
   int64_t nkeep;
+  int64_t *rec_g;            // entry records: first G position of the entry's products in the window
+  int32_t *rec_len;          //   their count
+  void *rec_sv;              //   the entry's S value
+  int64_t rec_cap;           // records the workspace holds
   int32_t mid_cap;           // max entries of a mid-tier vector
   int32_t mid_kind;          // 0 bitmap-rank, 1 hash
   int32_t lds_words;         // dynamic LDS size in 32-bit words

@@ -226,6 +226,11 @@ struct Layout {
   int64_t *pbase;
   int64_t *part;
   uint32_t *hbits;
+  int32_t *vsent;
+  int64_t *rcnt, *rbase;
+  int64_t *rec_g;
+  int32_t *rec_len;
+  void *rec_sv;
   size_t bytes;
 };
 
@@ -238,6 +243,8 @@ struct Shape {
   int32_t nrange = 1;      // XCD ranges of the heavy windows
   int64_t hstride = 0;     // words of a kept heavy bitmap (widest rank-mode group)
   int64_t nkeep = 0;       // heavy vectors whose bitmaps the workspace can keep
+  int64_t rec_cap = 0;     // entry records of heavy windows the workspace holds
+  int32_t slot_bytes = 0;  // value bytes of the semiring
   bool dense_path = false;
   std::vector<Geom> geom;  // per group
   std::vector<int64_t> minor, major;
@@ -335,6 +342,16 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
     const int64_t budget = (int64_t)t.bitmap_mb << 20;
     sh.nkeep = std::min<int64_t>(sh.nov_max, budget / (4 * sh.hstride));
   }
+  sh.slot_bytes = slot_bytes(kind);
+  if (sh.hstride > 0 && t.entry_mb > 0) {  // rank windows exist
+    // at most one record per streamed entry and window, at most nbmax
+    // windows per vector; the budget caps the rest
+    int64_t sent = 0;
+    for (int32_t p = 0; p < nprod; ++p) sent += view(A[p], B[p]).S->nnz;
+    const int64_t per = 12 + slot_bytes(kind);
+    sh.rec_cap = std::min<int64_t>(((int64_t)t.entry_mb << 20) / per, sent * (int64_t)sh.nbmax);
+  }
+
   // products whose gathered operand is the same arrays share the AUX index,
   // and the split table too when their groups split ids the same way
   sh.wsplit_src.assign(nprod, -1);
@@ -420,6 +437,19 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.pbase = c.take<int64_t>(ngroup + 1);
   L.part = c.take<int64_t>(scan_max / kScanTile + 4);
   L.hbits = sh.nkeep > 0 ? c.take<uint32_t>(sh.nkeep * sh.hstride) : nullptr;
+  if (sh.rec_cap > 0) {
+    L.vsent = c.take<int32_t>(nov + 1);
+    L.rcnt = c.take<int64_t>(nov + 1);
+    L.rbase = c.take<int64_t>(nov + 1);
+    L.rec_g = c.take<int64_t>(sh.rec_cap);
+    L.rec_len = c.take<int32_t>(sh.rec_cap);
+    L.rec_sv = (void *)c.take<uint8_t>(sh.rec_cap * std::max(1, sh.slot_bytes));
+  } else {
+    L.vsent = nullptr;
+    L.rcnt = L.rbase = L.rec_g = nullptr;
+    L.rec_len = nullptr;
+    L.rec_sv = nullptr;
+  }
   L.bytes = c.off + 256;
   return L;
 }
@@ -467,6 +497,7 @@ void normalise(sg_tuning &t, int32_t kind) {
   if (t.bitmap_mb < 0) t.bitmap_mb = d.bitmap_mb;
   if (t.heavy_threads == 0) t.heavy_threads = t.block_threads;
   if (t.heavy_threads < 64 || t.heavy_threads > kBlockMax || t.heavy_threads % 64) t.heavy_threads = d.heavy_threads;
+  if (t.entry_mb < 0) t.entry_mb = d.entry_mb;
   if (t.heavy_lds_bytes == 0) t.heavy_lds_bytes = t.lds_bytes;
   if (t.heavy_lds_bytes < 4096 || t.heavy_lds_bytes > 160 * 1024 - 2048) t.heavy_lds_bytes = d.heavy_lds_bytes;
   t.heavy_lds_bytes &= ~7;
@@ -620,6 +651,14 @@ struct RunBatched {
   static sg_status run(sg_plan *pl, hipStream_t st) { return launch_batched<K>(pl, st); }
 };
 template <int K>
+struct RunItemRecs {
+  static sg_status run(const Plan &P, int ncu, hipStream_t st) {
+    hipLaunchKernelGGL((k_item_recs<K>), dim3((unsigned)ncu * 16), dim3(256), 0, st, P);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+  }
+};
+template <int K>
 struct RunAttr {
   static sg_status run(int bytes) { return set_lds_attr<K>(bytes); }
 };
@@ -695,6 +734,9 @@ void sg_tuning_default(int32_t kind, sg_tuning *t) {
   // unit (wider single workgroups halve the window count but not the time)
   t->heavy_threads = 512;
   t->heavy_lds_bytes = 77 * 1024;
+  // entry records cost the symbolic phase more than they save one numeric
+  // run; they pay when a plan's numeric phase is replayed many times
+  t->entry_mb = 0;
 }
 
 const char *sg_last_error(void) { return g_last_error; }
@@ -936,6 +978,10 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   P.hbits = L.hbits;
   P.hstride = sh.hstride;
   P.nkeep = sh.nkeep;
+  P.rec_g = L.rec_g;
+  P.rec_len = L.rec_len;
+  P.rec_sv = L.rec_sv;
+  P.rec_cap = sh.rec_cap;
   P.mid_cap = t.mid_max_ub;
   P.mid_kind = t.mid_kind;
   P.lds_words = t.lds_bytes / 4;
@@ -981,11 +1027,19 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   hipLaunchKernelGGL(k_group_totals, dim3((unsigned)grid_for(ngroup, 64)), dim3(64), 0, st, L.groups, ngroup,
                      L.ov_off, L.nzpos, L.gstat);
   SG_HIP(hipGetLastError());
+  // entry records: offsets per heavy vector (windows x streamed entries)
+  if (sh.rec_cap > 0) {
+    hipLaunchKernelGGL(k_rec_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                       L.heavy_nwin, sh.nov_max, L.vsent, L.rcnt);
+    SG_HIP(hipGetLastError());
+    SG_TRY(scan64(L.rcnt, sh.nov_max, L.rbase, L.part, st));
+  }
   // the window items carry their absolute output positions, so they are
   // filled once the vector offsets and the group bases are known
   hipLaunchKernelGGL(k_plan_fill, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
-                     L.ibase, sh.nov_max, L.items, L.counters);
+                     L.ibase, sh.nov_max, L.items, L.counters, L.rbase, L.vsent);
   SG_HIP(hipGetLastError());
+  if (sh.rec_cap > 0) SG_TRY(dispatch<RunItemRecs>(sr->kind, P, pl->ncu, st));
 
   SG_HIP(hipMemcpyAsync(pl->host_stats, L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount, hipMemcpyDeviceToHost,
                         st));

@@ -531,7 +531,8 @@ __global__ void k_plan_count(Plan P, int64_t cap, int64_t *nwin_out) {
   }
 }
 
-__global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, ItemDev *items, int64_t *counters) {
+__global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, ItemDev *items, int64_t *counters,
+                            const int64_t *rbase, const int32_t *vsent) {
   const int64_t nh = counters[kCtHeavy];
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = P.heavy_list[q];
@@ -539,7 +540,9 @@ __global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, ItemDev *
     const GroupDev &G = P.groups[g];
     const int64_t base = P.ov_off[v] - G.nnz_base;
     const int32_t *bc = P.bcnt + q * (int64_t)P.nbmax;
-    int64_t before = 0;
+    const int32_t ns = vsent ? vsent[q] : 0;
+    const int64_t rb = rbase ? rbase[q] : -1;
+    int64_t before = 0, j = 0;
     for (int r = 0; r < P.nrange; ++r) {
       int32_t bs, be;
       range_buckets(G, r, bs, be);
@@ -552,14 +555,92 @@ __global__ void k_plan_fill(Plan P, const int64_t *ibase, int64_t cap, ItemDev *
         it.b1 = b1;
         it.pos = base + bef;
         it.q = (int32_t)q;
-        it.pad = 0;
+        it.nrec = ns;
+        const int64_t r0 = rb + j * ns;
+        it.rbase = (G.mode == 1 && ns >= 0 && rb >= 0 && r0 + ns <= P.rec_cap) ? r0 : -1;
         items[i] = it;
         ++i;
+        ++j;
       });
       for (int32_t b = bs; b < be; ++b) before += bc[b];
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCtItems] = ibase[(int64_t)P.nrange * cap];
+}
+
+// Entry records of the heavy windows: per heavy vector q the stored S
+// entries it streams (vsent, -1 for a vector of several segments, which
+// keeps the plain walk) and the records it needs, windows x entries (rcnt,
+// scanned into the record offsets).
+__global__ void k_rec_count(Plan P, const int64_t *nwin, int64_t cap, int32_t *vsent, int64_t *rcnt) {
+  const int64_t nh = P.counters[kCtHeavy];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rc = 0;
+    if (q < nh) {
+      const int32_t v = P.heavy_list[q];
+      const int64_t s0 = P.ov_seg[v];
+      // records name no product: only single-segment vectors get them
+      if (P.ov_seg[v + 1] - s0 == 1) {
+        const ProdDev &d = P.prods[P.seg_prod[s0]];
+        const int32_t t = P.seg_svec[s0];
+        const int64_t ns = d.s_ptr[t + 1] - d.s_ptr[t];
+        int64_t w = 0;
+        for (int r = 0; r < P.nrange; ++r) w += nwin[r * cap + q];
+        vsent[q] = (int32_t)ns;
+        rc = w * ns;
+      } else {
+        vsent[q] = -1;
+      }
+    }
+    rcnt[q] = rc;
+  }
+}
+
+// One wavefront per heavy item with records: the G range of every stored S
+// entry of the vector inside the item's buckets, and the entry's S value,
+// in the order the product walk visits them.
+template <int K>
+__global__ void k_item_recs(Plan P) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  const int l = lane();
+  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t n = P.counters[kCtItems];
+  for (int64_t it = wave; it < n; it += nwaves) {
+    const ItemDev I = uload(P.items + it);
+    if (I.rbase < 0) continue;
+    int64_t j = 0;
+    const int64_t s1 = uload(P.ov_seg + I.v + 1);
+    for (int64_t s = uload(P.ov_seg + I.v); s < s1; ++s) {
+      const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+      const int32_t t = uload(P.seg_svec + s);
+      const int64_t e0 = uload(d.s_ptr + t), e1 = uload(d.s_ptr + t + 1);
+      for (int64_t e = e0 + l; e < e1; e += kWave) {
+        const int32_t k = gload(d.s_idx + e);
+        const int32_t gt = d.gres ? gload(d.gres + e) : ((k >= 0 && k < d.g_nvec) ? k : -1);
+        int64_t g = 0;
+        int32_t len = 0;
+        if (gt >= 0) {
+          const int64_t p0 = gload(d.g_ptr + gt);
+          if (d.wsplit) {
+            const int32_t *ws = d.wsplit + (int64_t)gt * (d.nsplit + 1);
+            const int32_t a = gload(ws + I.b0);
+            g = p0 + a;
+            len = gload(ws + I.b1) - a;
+          } else {
+            g = p0;
+            len = (int32_t)(gload(d.g_ptr + gt + 1) - p0);
+          }
+        }
+        const int64_t x = I.rbase + j + (e - e0);
+        gstore(P.rec_g + x, g);
+        gstore(P.rec_len + x, len);
+        if (SR::kVal) gstore((T *)P.rec_sv + x, gload((const T *)d.s_val + e));
+      }
+      j += e1 - e0;
+    }
+  }
 }
 
 // Per-group totals after the scans of counts (ov_off) and non-empty flags (nzpos).

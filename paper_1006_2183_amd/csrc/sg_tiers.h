@@ -277,6 +277,36 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
   }
 }
 
+// All products of a heavy window from its entry records [rb, rb + nrec):
+// one load level per batch of 64 entries (range and S value) instead of the
+// entry, its G vector pointer and its window split points in turn.
+template <class SR, class Act>
+__device__ __forceinline__ void for_products_recs(const Plan &P, const ProdDev &d0, int64_t rb, int32_t nrec, int wid,
+                                                  int nw, Act &act) {
+  typedef typename SR::T T;
+  const int uw = uni(wid);
+  for (int64_t eb = 0; eb < nrec; eb += kWave) {
+    const int64_t x = rb + eb + lane();
+    const bool ok = eb + lane() < nrec;
+    const int len = ok ? gload(P.rec_len + x) : 0;
+    const int64_t gb = ok ? gload(P.rec_g + x) : 0;
+    const T sv = (SR::kVal && ok) ? gload((const T *)P.rec_sv + x) : T();
+    const int incl = wave_incl_scan(len);
+    const int tot = read_lane(incl, kWave - 1);
+    if (tot == 0) continue;
+    const int f0 = (int)((int64_t)tot * uw / nw);
+    const int f1 = (int)((int64_t)tot * (uw + 1) / nw);
+    const int st = incl - len;
+    const int a = st > f0 ? st : f0;
+    const int e = incl < f1 ? incl : f1;
+    const int len2 = e > a ? e - a : 0;
+    if constexpr (Act::kFlat)
+      run_flat<SR>(len2, gb + (a - st), sv, d0.g_idx, (const T *)d0.g_val, act);
+    else
+      run_batch<SR>(len2, gb + (a - st), sv, d0.g_idx, (const T *)d0.g_val, act);
+  }
+}
+
 __device__ __forceinline__ int64_t out_offset(const Plan &P, int64_t v) {
   return uload(P.ov_off + v) - uload(&P.groups[uload(P.ov_group + v)].nnz_base);
 }
@@ -604,7 +634,8 @@ __device__ __forceinline__ int64_t rank_load_kept(const uint32_t *src, int nwds,
 
 template <int K, bool COUNT, bool WHOLE = false>
 __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
-                            uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr) {
+                            uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr, int64_t rb = -1,
+                            int32_t nrec = 0) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
@@ -744,7 +775,13 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     __syncthreads();
   }
   RankAcc<SR> accum{words, vals, lo32};
-  for_products<SR>(P, v, b0, b1, wid, nw, accum);
+  if (rb >= 0) {
+    // only single-segment vectors have records: their one product gives G
+    const ProdDev d0 = uload(P.prods + uload(P.seg_prod + uload(P.ov_seg + v)));
+    for_products_recs<SR>(P, d0, rb, nrec, wid, nw, accum);
+  } else {
+    for_products<SR>(P, v, b0, b1, wid, nw, accum);
+  }
   __syncthreads();
   // emit in three coalesced passes: the values are already dense by rank;
   // the ids are scattered by rank into the (emptied) value slots, then
@@ -1040,7 +1077,7 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
     dense_window<K, false>(P, I.v, I.b0, lo, hi, I.pos, lds, scratch, (G.sw + 31) >> 5);
   else
     rank_window<K, false>(P, I.v, lo, hi, I.b0, I.b1, I.pos, lds, scratch,
-                          I.q < P.nkeep ? P.hbits + I.q * P.hstride : nullptr);
+                          I.q < P.nkeep ? P.hbits + I.q * P.hstride : nullptr, I.rbase, I.nrec);
 }
 
 // ---------------------------------------------------------------------------

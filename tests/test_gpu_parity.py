@@ -270,3 +270,15 @@ def test_rmat_s18_sampled_rows(sg, semiring):
     else:
         err = np.abs(cval - R.val)
         assert np.all(err <= 1e-12 * np.abs(R.val))
+
+
+@pytest.mark.parametrize("entry_mb", [0, 1, 2048])
+def test_entry_records_budget(sg, entry_mb):
+    """Heavy windows with entry records (all, some within a 1 MiB budget, none) equal the oracle."""
+    semiring = "min_plus_i32"
+    A = W.rmat_matrix(12, 16, semiring, "csr", seed=21)
+    _say(f"case entry records entry_mb={entry_mb}")
+    C, info = gpu_product(sg, semiring, A, A, lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384,
+                          heavy_threads=256, entry_mb=entry_mb)
+    assert info["n_heavy_items"] > info["n_heavy"] > 0  # several windows per heavy vector
+    check(semiring, C, A, A, f"entry_mb={entry_mb}")
