@@ -507,11 +507,11 @@ void normalise(sg_tuning &t, int32_t kind) {
 template <int K>
 sg_status set_lds_attr(int bytes) {
   SG_HIP(hipFuncSetAttribute((const void *)k_mid_count<K>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_mid<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_mid<K>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_heavy_count<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_heavy_count<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, false, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
@@ -578,15 +578,15 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
     const int64_t hres = resident_blocks(pl->ncu, hnt, hlds, kWavesPerSimd);
     const unsigned hg = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(hres, I.n_heavy_items) / kXcds * kXcds);
     if (pl->has_mode[0])
-      hipLaunchKernelGGL((k_heavy<K, false, 0>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 8);
+      hipLaunchKernelGGL((k_heavy<K, 0>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 8);
     if (pl->has_mode[1])
-      hipLaunchKernelGGL((k_heavy<K, false, 1>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 16);
+      hipLaunchKernelGGL((k_heavy<K, 1>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 16);
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 0, true, st));
   }
   if (I.n_mid > 0) {
     SG_TRY(mark(pl, 1, false, st));
-    hipLaunchKernelGGL((k_mid<K, false>), dim3((unsigned)std::min<int64_t>(persist, I.n_mid)), dim3(nt), lds, st, P,
+    hipLaunchKernelGGL((k_mid<K>), dim3((unsigned)std::min<int64_t>(persist, I.n_mid)), dim3(nt), lds, st, P,
                        pl->counters + kCtNum + 3);
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 1, true, st));

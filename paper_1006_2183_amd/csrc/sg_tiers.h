@@ -1099,7 +1099,7 @@ __global__ void __launch_bounds__(1024) k_tiny(Plan P) {
   for (int64_t c0 = wave * csz; c0 < n; c0 += nwaves * csz) tiny_pack<K, COUNT>(P, c0, c0 + csz < n ? c0 + csz : n);
 }
 
-template <int K, bool COUNT>
+template <int K>
 __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_t *queue) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
@@ -1113,36 +1113,26 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_
     __syncthreads();
     if (i >= n) break;
     const int64_t v = uload(P.mid_list + i);
-    if (P.mid_kind == 0) rank_window<K, COUNT, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, COUNT ? 0 : out_offset(P, v), lds, scratch);
-    else mid_hash_vector<K, COUNT>(P, v, lds, scratch);
+    if (P.mid_kind == 0)
+      rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds,
+                                  scratch);
+    else
+      mid_hash_vector<K, false>(P, v, lds, scratch);
   }
 }
 
 // MODE selects the heavy window kind this launch handles (items of groups
 // with the other kind are skipped); a plan launches one kernel per kind used.
-// The count variant pulls heavy vectors from one queue. The numeric variant
-// keeps one queue per XCD over the windows of that XCD's id ranges
+// The numeric launch keeps one queue per XCD over the windows of that XCD's id ranges
 // (`queue` has kXcds counters); a workgroup starts with the queue of the XCD
 // it runs on, taken as blockIdx.x mod kXcds (workgroups are dispatched to
 // the dies round-robin), and then drains the others in turn.
-template <int K, bool COUNT, int MODE>
+template <int K, int MODE>
 __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int64_t *queue) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
   __shared__ int64_t s_item;
   zero_lds(lds, P.lds_words);
-  if (COUNT) {
-    const int64_t n = P.counters[kCtHeavy];
-    while (true) {
-      if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)queue, 1ull);
-      __syncthreads();
-      const int64_t i = uni(s_item);
-      __syncthreads();
-      if (i >= n) break;
-      heavy_count<K, MODE>(P, i, lds, scratch);
-    }
-    return;
-  }
   const int per_xcd = P.nrange >= kXcds ? P.nrange / kXcds : 0;
   const int home = blockIdx.x % kXcds;
   for (int d = 0; d < kXcds; ++d) {
