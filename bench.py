@@ -225,6 +225,30 @@ def _summa_diagnose(res, sg, dA, dB, sr):
     return f"{len(bad)} columns differ (first {bad[:5]}); columns where each form differs from the per-tier run: {odd}"
 
 
+def suite_small(sg, torch, W, reps=50):
+    """The small plain product (R-MAT scale 10, edge factor 8): latency-bound, so its
+    time per product (symbolic + numeric) and per graph replay of the numeric launch."""
+    from paper_1006_2183_amd import batched as BT
+    out = {"workload": "rmat_s10_ef8_AxA_plain"}
+    for sr in ("plus_times_f64", "min_plus_i32"):
+        A = W.rmat_matrix(10, 8, sr, "csr", seed=1, abcd=RMAT_ABCD)
+        dA = sg.DevMat.from_host(A, "cuda", sr)
+        def step():
+            sg.spgemm(sr, dA, dA)
+        step()
+        ms = _median_ms(torch, step, reps)
+        plan = sg.spgemm_symbolic(sr, [dA], [dA])
+        G = BT.GraphedNumeric(plan)
+        G.replay()
+        torch.cuda.synchronize()
+        ms_graph = _median_ms(torch, G.replay, reps)
+        info = plan.infos[0]
+        plan.destroy()
+        out[sr] = {"flops": info["flops"], "nnz_C": info["nnz"], "product_ms": round(ms, 4),
+                   "graph_replay_ms": round(ms_graph, 4)}
+    return out
+
+
 def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
     """One Sparse SUMMA process's share: 64 stage products of DCSC blocks, merged."""
     from paper_1006_2183_amd import batched as BT
@@ -489,7 +513,7 @@ def main():
     ap.add_argument("--no-suite", action="store_true",
                     help="skip the batched (SUMMA share, Galerkin) and served measurements")
     ap.add_argument("--suite-reps", type=int, default=3)
-    ap.add_argument("--only", choices=["summa", "galerkin", "serving"], default=None,
+    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving"], default=None,
                     help="run one of the batched/served measurements alone and print its JSON object")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-qps", default="500,2000,8000")
@@ -531,7 +555,8 @@ def main():
     import workloads as W
     sg.load_library()
 
-    suites = {"summa": ("batched_summa", lambda: suite_summa(sg, torch, W, args.suite_reps)),
+    suites = {"small": ("small_product", lambda: suite_small(sg, torch, W)),
+              "summa": ("batched_summa", lambda: suite_summa(sg, torch, W, args.suite_reps)),
               "galerkin": ("batched_galerkin", lambda: suite_galerkin(sg, torch, W, args.suite_reps)),
               "serving": ("serving", lambda: suite_serve(sg, torch, W, args.serve_requests,
                                                          [float(q) for q in args.serve_qps.split(",")]))}
