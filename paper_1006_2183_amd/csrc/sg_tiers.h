@@ -36,10 +36,14 @@ namespace sg {
 // Accumulators take a product in two steps so that the LDS reads of several
 // products can be in flight together: prep(id) issues the reads one product
 // needs and returns them as a token, commit(id, token, value) applies it.
-// Step wraps a one-step lambda.
-template <class T, class F>
+// Step wraps a one-step lambda. kFlat picks the walk (flat over the lanes
+// or lane groups per entry); kSpread has the flat walk hand neighbouring
+// lanes products nine apart, which keeps bitmap-word atomics of one
+// instruction off a common word.
+template <class T, class F, bool FLAT = false>
 struct Step {
-  static constexpr bool kFlat = false;
+  static constexpr bool kFlat = FLAT;
+  static constexpr bool kSpread = FLAT;
   F f;
   __device__ __forceinline__ uint64_t prep(int) const { return 0; }
   __device__ __forceinline__ void commit(int id, uint64_t, T v) { f(id, v); }
@@ -47,6 +51,10 @@ struct Step {
 template <class T, class F>
 __device__ __forceinline__ Step<T, F> step(F f) {
   return Step<T, F>{f};
+}
+template <class T, class F>
+__device__ __forceinline__ Step<T, F, true> flat_step(F f) {
+  return Step<T, F, true>{f};
 }
 
 // Products of one batch of (up to) 64 stored entries of S, one per lane: the
@@ -159,47 +167,70 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
 // (lane e holds `len` products at G positions [gb, gb + len) with S value
 // sv), spread flat over the lanes: product f (in entry order) goes to lane
 // f mod 64 of round f / 64, so every round but the last keeps all 64 lanes
-// busy whatever the entry lengths. A lane finds the entry of its product by
-// a binary search of the lanes' inclusive product counts, R rounds at a
-// time with all their gathers in flight before the accumulator sees any.
+// busy whatever the entry lengths. R rounds at a time have all their
+// gathers in flight before the accumulator sees any.
+// The entry of a lane's product: a round inside one entry (the common case
+// of long G vectors) reads that entry's G base and S value as scalars; a
+// round where a few entries start takes them in order with one compare per
+// lane each; otherwise a binary search of the lanes' inclusive product
+// counts. Lanes past the last product load the last product again (always
+// in range) and skip the accumulator.
 template <class SR, class Act, int R = 4>
 __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
                                          const typename SR::T *__restrict__ gval, Act &act) {
   typedef typename SR::T T;
+  constexpr int kFewStarts = 4;
   const int l = lane();
+  const int pl = Act::kSpread ? ((l * 9) & (kWave - 1)) : l;  // this lane's product within a round
   const int incl = wave_incl_scan(len);
   const int tot = read_lane(incl, kWave - 1);
   if (tot == 0) return;
   const int st = incl - len;
   const int64_t gbase = gb - st;  // G position of product f of this entry is gbase + f
+  const bool live = len > 0;
   for (int j0 = 0; j0 < tot; j0 += R * kWave) {
-    int e[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int f = j0 + k * kWave + l;
-      e[k] = owner_of(incl, f < tot ? f : tot - 1);
-    }
     int64_t g[R];
     T s4[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      g[k] = __shfl(gbase, e[k], kWave) + j0 + k * kWave + l;
-      s4[k] = __shfl(sv, e[k], kWave);
+      const int f0 = j0 + k * kWave;
+      const int r0 = f0 < tot ? f0 : tot - 1;          // first product of the round, clamped
+      const int fl = f0 + pl < tot ? f0 + pl : tot - 1;  // this lane's product, clamped
+      const int e0 = (int)__popcll(__ballot(incl <= r0));                // entry of product r0
+      const uint64_t starts = __ballot(live && st > r0 && st < f0 + kWave);  // entries starting later in the round
+      if (starts == 0) {
+        g[k] = read_lane64(gbase, e0) + fl;
+        if constexpr (SR::kVal) s4[k] = read_lane_val(sv, e0);
+        else s4[k] = T();
+      } else {
+        int e = e0;
+        if (__popcll(starts) <= kFewStarts) {
+          uint64_t m = starts;
+          while (m) {
+            const int x = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            if (fl >= read_lane(st, x)) e = x;
+          }
+        } else {
+          e = owner_of(incl, fl);
+        }
+        g[k] = __shfl(gbase, e, kWave) + fl;
+        s4[k] = __shfl(sv, e, kWave);
+      }
     }
     int32_t i4[R];
     T v4[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const bool ok = j0 + k * kWave + l < tot;
-      i4[k] = ok ? gload(gidx + g[k]) : 0;
-      v4[k] = (SR::kVal && ok) ? gload(gval + g[k]) : T();
+      i4[k] = gload(gidx + g[k]);
+      v4[k] = SR::kVal ? gload(gval + g[k]) : T();
     }
     uint64_t t4[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) t4[k] = j0 + k * kWave + l < tot ? act.prep(i4[k]) : 0;
+    for (int k = 0; k < R; ++k) t4[k] = j0 + k * kWave + pl < tot ? act.prep(i4[k]) : 0;
 #pragma unroll
     for (int k = 0; k < R; ++k)
-      if (j0 + k * kWave + l < tot) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
+      if (j0 + k * kWave + pl < tot) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -550,6 +581,7 @@ struct RankAcc {
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
   static constexpr bool kFlat = true;
+  static constexpr bool kSpread = false;  // consecutive ranks: consecutive banks
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
@@ -1005,7 +1037,7 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   const int nwds = (int)((G.minor + 31) >> 5);
   uint32_t *bits = lds;
   int32_t *lbc = (int32_t *)(lds + nwds);
-  auto mark = step<T>([&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); });
+  auto mark = flat_step<T>([&](int id, T) { atomicOr(&bits[id >> 5], 1u << (id & 31)); });
   for_products<SR>(P, v, -1, -1, wid, nw, mark);
   __syncthreads();
   const int wpb = G.sw >> 5;  // words per bucket
@@ -1146,13 +1178,20 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
       hi = P.ibase[(int64_t)(x + 1) * per_xcd * P.ibase_stride];
     }
     if (lo >= hi) continue;
-    while (true) {
-      if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
-      __syncthreads();
-      const int64_t i = lo + uni(s_item);
-      __syncthreads();
-      if (i >= hi) break;
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
+    __syncthreads();
+    int64_t i = lo + uni(s_item);
+    __syncthreads();
+    while (i < hi) {
+      // the next item is claimed before this one starts, so the queue's
+      // round trip overlaps the window instead of preceding it
+      int64_t nxt = 0;
+      if (threadIdx.x == 0) nxt = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
       heavy_item<K, MODE>(P, i, lds, scratch);
+      if (threadIdx.x == 0) s_item = nxt;
+      __syncthreads();
+      i = lo + uni(s_item);
+      __syncthreads();
     }
   }
 }
