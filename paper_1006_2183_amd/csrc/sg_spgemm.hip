@@ -541,9 +541,10 @@ sg_status launch_counts(sg_plan *pl, hipStream_t st) {
   SG_HIP(hipGetLastError());
   Plan Ph = pl->P;
   Ph.lds_words = pl->lds_heavy_count / 4;
-  const unsigned hb = (unsigned)resident_blocks(pl->ncu, nt, pl->lds_heavy_count, kWavesPerSimd);
   for (int m = 0; m < 2; ++m) {
     if (!pl->has_mode[m]) continue;
+    const unsigned hb = (unsigned)resident_blocks(pl->ncu, nt, pl->lds_heavy_count,
+                                                  m == 0 ? heavy_count_waves<0>() : heavy_count_waves<1>());
     if (m == 0)
       hipLaunchKernelGGL((k_heavy_count<K, 0>), dim3(hb), dim3(nt), pl->lds_heavy_count, st, Ph, pl->counters + kCtNum + 1);
     else

@@ -39,11 +39,13 @@ namespace sg {
 // Step wraps a one-step lambda. kFlat picks the walk (flat over the lanes
 // or lane groups per entry); kSpread has the flat walk hand neighbouring
 // lanes products nine apart, which keeps bitmap-word atomics of one
-// instruction off a common word.
+// instruction off a common word; kRounds is the flat walk's rounds in
+// flight (bitmap marks hold no values: eight fit the registers).
 template <class T, class F, bool FLAT = false>
 struct Step {
   static constexpr bool kFlat = FLAT;
   static constexpr bool kSpread = FLAT;
+  static constexpr int kRounds = 8;
   F f;
   __device__ __forceinline__ uint64_t prep(int) const { return 0; }
   __device__ __forceinline__ void commit(int id, uint64_t, T v) { f(id, v); }
@@ -175,7 +177,7 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
 // lane each; otherwise a binary search of the lanes' inclusive product
 // counts. Lanes past the last product load the last product again (always
 // in range) and skip the accumulator.
-template <class SR, class Act, int R = 4>
+template <class SR, class Act, int R = Act::kRounds>
 __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
                                          const typename SR::T *__restrict__ gval, Act &act) {
   typedef typename SR::T T;
@@ -226,11 +228,18 @@ __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv,
       v4[k] = SR::kVal ? gload(gval + g[k]) : T();
     }
     uint64_t t4[R];
+    if (j0 + R * kWave <= tot) {  // every lane's products are real: no masks
 #pragma unroll
-    for (int k = 0; k < R; ++k) t4[k] = j0 + k * kWave + pl < tot ? act.prep(i4[k]) : 0;
+      for (int k = 0; k < R; ++k) t4[k] = act.prep(i4[k]);
 #pragma unroll
-    for (int k = 0; k < R; ++k)
-      if (j0 + k * kWave + pl < tot) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
+      for (int k = 0; k < R; ++k) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; ++k) t4[k] = j0 + k * kWave + pl < tot ? act.prep(i4[k]) : 0;
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        if (j0 + k * kWave + pl < tot) act.commit(i4[k], t4[k], SR::kVal ? SR::mul(s4[k], v4[k]) : T());
+    }
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -582,18 +591,20 @@ struct RankAcc {
   typedef typename SR::Slot Slot;
   static constexpr bool kFlat = true;
   static constexpr bool kSpread = false;  // consecutive ranks: consecutive banks
+  static constexpr int kRounds = 4;       // eight measured slower (register pressure)
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
   __device__ __forceinline__ uint64_t prep(int id) const {
-    const int r = id - lo32;
-    return *(const uint64_t *)(words + 2 * (r >> 5));
+    const uint32_t r = (uint32_t)(id - lo32);
+    return *(const uint64_t *)((const char *)words + ((r >> 2) & ~7u));  // the pair of word r / 32
   }
   __device__ __forceinline__ void commit(int id, uint64_t tok, T x) {
-    const int r = id - lo32;
+    const uint32_t r = (uint32_t)(id - lo32);
     const uint32_t bits = (uint32_t)tok;
     const uint32_t pre = (uint32_t)(tok >> 32);
-    SR::acc(&vals[pre + __popc(bits & ((1u << (r & 31)) - 1u))], x);
+    // set bits of the word below bit r % 32 (the field width is taken mod 32)
+    SR::acc(&vals[pre + __popc(__builtin_amdgcn_ubfe(bits, 0u, r))], x);
   }
 };
 
@@ -704,7 +715,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     cnt = rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
     __syncthreads();
   } else if constexpr (two) {
-    auto mark = step<T>([&](int id, T) {
+    auto mark = flat_step<T>([&](int id, T) {
       const int r = id - lo32;
       const int w = r >> 5;
       atomicOr(&words[WS * w], 1u << (r & 31));
@@ -760,7 +771,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     cnt = total;
     __syncthreads();
   } else {
-    auto mark = step<T>([&](int id, T) {
+    auto mark = flat_step<T>([&](int id, T) {
       const int r = id - lo32;
       atomicOr(&words[WS * (r >> 5)], 1u << (r & 31));
     });
@@ -1221,10 +1232,14 @@ __global__ void __launch_bounds__(kBlockMax, kCountWavesPerSimd) k_mid_count(Pla
   }
 }
 
-// (the heavy count pass keeps the numeric kernels' register budget: at the
-// higher occupancy its product walk spills and runs slower)
+// The heavy count pass of rank windows (MODE 1) has the same register
+// budget: its flat walk of bitmap marks fits it without spills. Dense
+// windows (MODE 0) keep the numeric kernels' budget.
+template <int MODE>
+constexpr int heavy_count_waves() { return MODE == 1 ? kCountWavesPerSimd : kWavesPerSimd; }
+
 template <int K, int MODE>
-__global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy_count(Plan P, int64_t *queue) {
+__global__ void __launch_bounds__(kBlockMax, heavy_count_waves<MODE>()) k_heavy_count(Plan P, int64_t *queue) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
   __shared__ int64_t s_item;
