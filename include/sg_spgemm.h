@@ -144,15 +144,17 @@ typedef struct {
  *                    wider windows (0 = lds_bytes). The persistent launch
  *                    uses the larger of the two budgets.
  *   entry_mb         heavy tier: MiB of workspace for per-window entry
- *                    records (the G range of every streamed entry inside a
- *                    window, and its S value), written once by the symbolic
- *                    phase so that the numeric walk reads one record per entry
- *                    instead of the entry, its G vector and its window split
- *                    points in turn; windows beyond the budget, and vectors
- *                    fed by several products, walk the operands (0 = off, the
- *                    default: building them costs the symbolic phase about
- *                    what they save one numeric run, so they pay only for a
- *                    plan whose numeric phase is replayed)
+ *                    records (the addresses of the G slice of every streamed
+ *                    entry inside a window, and its S value), written once by
+ *                    the symbolic phase so that the numeric walk reads one
+ *                    record per entry instead of the segment's descriptors,
+ *                    the entry, its G vector and its window split points in
+ *                    turn; a vector fed by several products (the stage
+ *                    products of a SUMMA share) walks its records as one
+ *                    list. Windows beyond the budget walk the operands (0 =
+ *                    off, the default: building them costs the symbolic phase
+ *                    about what they save one numeric run, so they pay only
+ *                    for a plan whose numeric phase is replayed)
  */
 typedef struct {
     int32_t tiny_max_flops;

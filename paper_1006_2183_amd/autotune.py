@@ -3,7 +3,9 @@
 The tunable knobs are the fields of ``sg_tuning``: the tiny/mid flops
 thresholds of the binning step, the LDS bytes and workgroup size of the mid
 tier and of the heavy tier (mid capacity and heavy window width follow from
-them) and the number of persistent workgroups per compute unit.
+them), the number of persistent workgroups per compute unit and the budget
+of per-window entry records (which pay off when the numeric phase is
+replayed).
 A search times whole steps (symbolic + numeric, or numeric only for a
 structure-reusing caller) of the actual operands and keeps the fastest
 setting; candidates the library rejects are skipped. Results are cached in a
@@ -33,6 +35,7 @@ SPACE: Dict[str, List[int]] = {
     "block_threads": [256, 512],
     "mid_max_ub": [4096, 16384, 65535],
     "tiny_max_flops": [16, 32, 64],
+    "entry_mb": [0, 1024],
 }
 
 

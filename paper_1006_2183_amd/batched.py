@@ -34,7 +34,13 @@ def summa_share(semiring: str, A_blocks: Sequence[DevMat], B_blocks: Sequence[De
 
 
 def summa_share_plan(semiring: str, A_blocks, B_blocks, out_fmt: str = "dcsc", tuning=None, stream=None):
-    """The plan of ``summa_share`` (symbolic phase only), for repeated numeric phases."""
+    """The plan of ``summa_share`` (symbolic phase only), for repeated numeric phases.
+
+    A plan that is replayed many times gains from per-window entry records
+    (``entry_mb`` in the tuning): its symbolic phase writes them once and
+    every numeric phase reads one record per streamed entry instead of
+    walking the 64 stage products' descriptors.
+    """
     n = len(A_blocks)
     return B.spgemm_symbolic(semiring, list(A_blocks), list(B_blocks), [0] * n, 1, out_fmt=out_fmt,
                              tuning=tuning, stream=stream)

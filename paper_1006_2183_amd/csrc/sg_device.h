@@ -72,8 +72,9 @@ struct GroupDev {
 // vector v (position q in the heavy list) of group g, whose entries start at
 // `pos` inside the group's output arrays.
 // With entry records, rbase >= 0 is the first of the window's nrec records
-// (one per stored S entry of v: the entry's G range inside the window and
-// its S value), written once by the symbolic phase.
+// (one per stored S entry of v, over all of v's segments: the addresses of
+// the entry's G slice inside the window and its S value), written once by
+// the symbolic phase.
 struct ItemDev {
   int32_t v;
   int32_t g;
@@ -152,7 +153,8 @@ struct Plan {
   uint32_t *hbits;           // kept id bitmaps of the first nkeep heavy vectors
   int64_t hstride;           // 32-bit words per kept bitmap
   int64_t nkeep;
-  int64_t *rec_g;            // entry records: first G position of the entry's products in the window
+  int64_t *rec_gi;           // entry records: address of the first G id of the entry's products in the window
+  int64_t *rec_gv;           //   address of the first of their G values (valued semirings)
   int32_t *rec_len;          //   their count
   void *rec_sv;              //   the entry's S value
   int64_t rec_cap;           // records the workspace holds

@@ -228,7 +228,7 @@ struct Layout {
   uint32_t *hbits;
   int32_t *vsent;
   int64_t *rcnt, *rbase;
-  int64_t *rec_g;
+  int64_t *rec_gi, *rec_gv;
   int32_t *rec_len;
   void *rec_sv;
   size_t bytes;
@@ -348,7 +348,7 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
     // windows per vector; the budget caps the rest
     int64_t sent = 0;
     for (int32_t p = 0; p < nprod; ++p) sent += view(A[p], B[p]).S->nnz;
-    const int64_t per = 12 + slot_bytes(kind);
+    const int64_t per = 20 + slot_bytes(kind);  // two addresses, a count, the S value
     sh.rec_cap = std::min<int64_t>(((int64_t)t.entry_mb << 20) / per, sent * (int64_t)sh.nbmax);
   }
 
@@ -441,12 +441,13 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
     L.vsent = c.take<int32_t>(nov + 1);
     L.rcnt = c.take<int64_t>(nov + 1);
     L.rbase = c.take<int64_t>(nov + 1);
-    L.rec_g = c.take<int64_t>(sh.rec_cap);
+    L.rec_gi = c.take<int64_t>(sh.rec_cap);
+    L.rec_gv = c.take<int64_t>(sh.rec_cap);
     L.rec_len = c.take<int32_t>(sh.rec_cap);
     L.rec_sv = (void *)c.take<uint8_t>(sh.rec_cap * std::max(1, sh.slot_bytes));
   } else {
     L.vsent = nullptr;
-    L.rcnt = L.rbase = L.rec_g = nullptr;
+    L.rcnt = L.rbase = L.rec_gi = L.rec_gv = nullptr;
     L.rec_len = nullptr;
     L.rec_sv = nullptr;
   }
@@ -510,11 +511,14 @@ sg_status set_lds_attr(int bytes) {
   SG_HIP(hipFuncSetAttribute((const void *)k_mid<K>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_heavy_count<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_heavy_count<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_heavy<K, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   return SG_OK;
 }
 
@@ -579,9 +583,13 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
     const int64_t hres = resident_blocks(pl->ncu, hnt, hlds, kWavesPerSimd);
     const unsigned hg = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(hres, I.n_heavy_items) / kXcds * kXcds);
     if (pl->has_mode[0])
-      hipLaunchKernelGGL((k_heavy<K, 0>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 8);
-    if (pl->has_mode[1])
-      hipLaunchKernelGGL((k_heavy<K, 1>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 16);
+      hipLaunchKernelGGL((k_heavy<K, 0, false>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 8);
+    if (pl->has_mode[1]) {
+      if (pl->P.rec_cap > 0)
+        hipLaunchKernelGGL((k_heavy<K, 1, true>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 16);
+      else
+        hipLaunchKernelGGL((k_heavy<K, 1, false>), dim3(hg), dim3(hnt), hlds, st, Ph, pl->counters + kCtNum + 16);
+    }
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 0, true, st));
   }
@@ -615,15 +623,19 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
   SG_TRY(mark(pl, 0, false, st));
   const int mode = pl->has_mode[0] && pl->has_mode[1] ? 2 : (pl->has_mode[1] ? 1 : 0);
+  const bool recs = P.rec_cap > 0 && mode != 0;  // only rank windows (mode 1) carry records
+  const int64_t ni = I.n_heavy_items, nm = I.n_mid, ntn = I.n_tiny;
+  int64_t *q = pl->counters + kCtQueue;
   if (mode == 0)
-    hipLaunchKernelGGL((k_batched<K, 0>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
-                       (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+    hipLaunchKernelGGL((k_batched<K, 0, false>), dim3((unsigned)persist), dim3(nt), lds, st, P, q, ni, nm, ntn);
+  else if (mode == 1 && recs)
+    hipLaunchKernelGGL((k_batched<K, 1, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, q, ni, nm, ntn);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_batched<K, 1>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
-                       (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+    hipLaunchKernelGGL((k_batched<K, 1, false>), dim3((unsigned)persist), dim3(nt), lds, st, P, q, ni, nm, ntn);
+  else if (recs)
+    hipLaunchKernelGGL((k_batched<K, 2, true>), dim3((unsigned)persist), dim3(nt), lds, st, P, q, ni, nm, ntn);
   else
-    hipLaunchKernelGGL((k_batched<K, 2>), dim3((unsigned)persist), dim3(nt), lds, st, P, pl->counters + kCtQueue,
-                       (int64_t)I.n_heavy_items, (int64_t)I.n_mid, (int64_t)I.n_tiny);
+    hipLaunchKernelGGL((k_batched<K, 2, false>), dim3((unsigned)persist), dim3(nt), lds, st, P, q, ni, nm, ntn);
   SG_HIP(hipGetLastError());
   SG_TRY(mark(pl, 0, true, st));
   return SG_OK;
@@ -979,7 +991,8 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   P.hbits = L.hbits;
   P.hstride = sh.hstride;
   P.nkeep = sh.nkeep;
-  P.rec_g = L.rec_g;
+  P.rec_gi = L.rec_gi;
+  P.rec_gv = L.rec_gv;
   P.rec_len = L.rec_len;
   P.rec_sv = L.rec_sv;
   P.rec_cap = sh.rec_cap;

@@ -577,20 +577,18 @@ __global__ void k_rec_count(Plan P, const int64_t *nwin, int64_t cap, int32_t *v
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x) {
     int64_t rc = 0;
     if (q < nh) {
+      // one record per streamed entry of every segment, per window
       const int32_t v = P.heavy_list[q];
-      const int64_t s0 = P.ov_seg[v];
-      // records name no product: only single-segment vectors get them
-      if (P.ov_seg[v + 1] - s0 == 1) {
-        const ProdDev &d = P.prods[P.seg_prod[s0]];
-        const int32_t t = P.seg_svec[s0];
-        const int64_t ns = d.s_ptr[t + 1] - d.s_ptr[t];
-        int64_t w = 0;
-        for (int r = 0; r < P.nrange; ++r) w += nwin[r * cap + q];
-        vsent[q] = (int32_t)ns;
-        rc = w * ns;
-      } else {
-        vsent[q] = -1;
+      int64_t ns = 0;
+      for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
+        const ProdDev &d = P.prods[P.seg_prod[s]];
+        const int32_t t = P.seg_svec[s];
+        ns += d.s_ptr[t + 1] - d.s_ptr[t];
       }
+      int64_t w = 0;
+      for (int r = 0; r < P.nrange; ++r) w += nwin[r * cap + q];
+      vsent[q] = ns <= INT32_MAX ? (int32_t)ns : -1;
+      rc = ns <= INT32_MAX ? w * ns : 0;
     }
     rcnt[q] = rc;
   }
@@ -634,7 +632,8 @@ __global__ void k_item_recs(Plan P) {
           }
         }
         const int64_t x = I.rbase + j + (e - e0);
-        gstore(P.rec_g + x, g);
+        gstore(P.rec_gi + x, (int64_t)(d.g_idx + g));
+        if (SR::kVal) gstore(P.rec_gv + x, (int64_t)((const T *)d.g_val + g));
         gstore(P.rec_len + x, len);
         if (SR::kVal) gstore((T *)P.rec_sv + x, gload((const T *)d.s_val + e));
       }

@@ -177,21 +177,30 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
 // lane each; otherwise a binary search of the lanes' inclusive product
 // counts. Lanes past the last product load the last product again (always
 // in range) and skip the accumulator.
-template <class SR, class Act, int R = Act::kRounds>
-__device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
-                                         const typename SR::T *__restrict__ gval, Act &act) {
+// PTR: the entries come from several products, so each lane holds the
+// addresses of its entry's first G id (gb) and first G value (gv) instead
+// of a position in one product's arrays (gidx, gval unused).
+template <class SR, class Act, bool PTR, int R = Act::kRounds>
+__device__ __forceinline__ void flat_walk(int len, int64_t gb, int64_t gv, typename SR::T sv,
+                                          const int32_t *__restrict__ gidx, const typename SR::T *__restrict__ gval,
+                                          Act &act) {
   typedef typename SR::T T;
   constexpr int kFewStarts = 4;
+  constexpr bool kTwo = PTR && SR::kVal;  // a second base per entry (its values)
   const int l = lane();
   const int pl = Act::kSpread ? ((l * 9) & (kWave - 1)) : l;  // this lane's product within a round
   const int incl = wave_incl_scan(len);
   const int tot = read_lane(incl, kWave - 1);
   if (tot == 0) return;
   const int st = incl - len;
-  const int64_t gbase = gb - st;  // G position of product f of this entry is gbase + f
+  // product f of this entry: G position gbase + f, or (PTR) id at address
+  // gbase + 4 f and value at vbase + sizeof(T) f
+  const int64_t gbase = PTR ? gb - (int64_t)st * (int64_t)sizeof(int32_t) : gb - st;
+  const int64_t vbase = kTwo ? gv - (int64_t)st * (int64_t)sizeof(T) : 0;
   const bool live = len > 0;
   for (int j0 = 0; j0 < tot; j0 += R * kWave) {
     int64_t g[R];
+    int64_t gw[kTwo ? R : 1];  // value addresses (PTR with values only)
     T s4[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -200,8 +209,11 @@ __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv,
       const int fl = f0 + pl < tot ? f0 + pl : tot - 1;  // this lane's product, clamped
       const int e0 = (int)__popcll(__ballot(incl <= r0));                // entry of product r0
       const uint64_t starts = __ballot(live && st > r0 && st < f0 + kWave);  // entries starting later in the round
+      // G position (or id address) of this lane's product, from its entry's base
+      constexpr int64_t kStep = PTR ? (int64_t)sizeof(int32_t) : 1;
       if (starts == 0) {
-        g[k] = read_lane64(gbase, e0) + fl;
+        g[k] = read_lane64(gbase, e0) + (int64_t)fl * kStep;
+        if constexpr (kTwo) gw[k] = read_lane64(vbase, e0) + (int64_t)fl * (int64_t)sizeof(T);
         if constexpr (SR::kVal) s4[k] = read_lane_val(sv, e0);
         else s4[k] = T();
       } else {
@@ -216,7 +228,8 @@ __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv,
         } else {
           e = owner_of(incl, fl);
         }
-        g[k] = __shfl(gbase, e, kWave) + fl;
+        g[k] = __shfl(gbase, e, kWave) + (int64_t)fl * kStep;
+        if constexpr (kTwo) gw[k] = __shfl(vbase, e, kWave) + (int64_t)fl * (int64_t)sizeof(T);
         s4[k] = __shfl(sv, e, kWave);
       }
     }
@@ -224,8 +237,14 @@ __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv,
     T v4[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      i4[k] = gload(gidx + g[k]);
-      v4[k] = SR::kVal ? gload(gval + g[k]) : T();
+      if constexpr (PTR) {
+        i4[k] = gload((const int32_t *)g[k]);
+        if constexpr (kTwo) v4[k] = gload((const T *)gw[k]);
+        else v4[k] = T();
+      } else {
+        i4[k] = gload(gidx + g[k]);
+        v4[k] = SR::kVal ? gload(gval + g[k]) : T();
+      }
     }
     uint64_t t4[R];
     if (j0 + R * kWave <= tot) {  // every lane's products are real: no masks
@@ -242,6 +261,12 @@ __device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv,
     }
   }
   __builtin_amdgcn_wave_barrier();
+}
+
+template <class SR, class Act>
+__device__ __forceinline__ void run_flat(int len, int64_t gb, typename SR::T sv, const int32_t *__restrict__ gidx,
+                                         const typename SR::T *__restrict__ gval, Act &act) {
+  flat_walk<SR, Act, false>(len, gb, 0, sv, gidx, gval, act);
 }
 
 // Load the lane's stored S entry e of product d and describe its products:
@@ -318,18 +343,23 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
 }
 
 // All products of a heavy window from its entry records [rb, rb + nrec):
-// one load level per batch of 64 entries (range and S value) instead of the
-// entry, its G vector pointer and its window split points in turn.
+// one load level per batch of 64 entries (the addresses of the entry's G
+// slice inside the window and its S value) instead of the segment's
+// descriptors, the entry, its G vector and its window split points in turn.
+// Records name addresses, so a vector fed by several products (a SUMMA
+// share's stage products) walks them as one list.
 template <class SR, class Act>
-__device__ __forceinline__ void for_products_recs(const Plan &P, const ProdDev &d0, int64_t rb, int32_t nrec, int wid,
-                                                  int nw, Act &act) {
+__device__ __forceinline__ void for_products_recs(const Plan &P, int64_t rb, int32_t nrec, int wid, int nw,
+                                                  Act &act) {
   typedef typename SR::T T;
+  static_assert(Act::kFlat, "records feed the flat walk");
   const int uw = uni(wid);
   for (int64_t eb = 0; eb < nrec; eb += kWave) {
     const int64_t x = rb + eb + lane();
     const bool ok = eb + lane() < nrec;
     const int len = ok ? gload(P.rec_len + x) : 0;
-    const int64_t gb = ok ? gload(P.rec_g + x) : 0;
+    const int64_t gi = ok ? gload(P.rec_gi + x) : 0;
+    const int64_t gv = (SR::kVal && ok) ? gload(P.rec_gv + x) : 0;
     const T sv = (SR::kVal && ok) ? gload((const T *)P.rec_sv + x) : T();
     const int incl = wave_incl_scan(len);
     const int tot = read_lane(incl, kWave - 1);
@@ -340,10 +370,9 @@ __device__ __forceinline__ void for_products_recs(const Plan &P, const ProdDev &
     const int a = st > f0 ? st : f0;
     const int e = incl < f1 ? incl : f1;
     const int len2 = e > a ? e - a : 0;
-    if constexpr (Act::kFlat)
-      run_flat<SR>(len2, gb + (a - st), sv, d0.g_idx, (const T *)d0.g_val, act);
-    else
-      run_batch<SR>(len2, gb + (a - st), sv, d0.g_idx, (const T *)d0.g_val, act);
+    const int64_t skip = a > st ? a - st : 0;  // products of the entry before this wave's slice
+    flat_walk<SR, Act, true>(len2, gi + skip * (int64_t)sizeof(int32_t), gv + skip * (int64_t)sizeof(T), sv, nullptr,
+                             nullptr, act);
   }
 }
 
@@ -675,7 +704,7 @@ __device__ __forceinline__ int64_t rank_load_kept(const uint32_t *src, int nwds,
   return run_total;
 }
 
-template <int K, bool COUNT, bool WHOLE = false>
+template <int K, bool COUNT, bool WHOLE = false, bool RECS = false>
 __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
                             uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr, int64_t rb = -1,
                             int32_t nrec = 0) {
@@ -818,10 +847,8 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     __syncthreads();
   }
   RankAcc<SR> accum{words, vals, lo32};
-  if (rb >= 0) {
-    // only single-segment vectors have records: their one product gives G
-    const ProdDev d0 = uload(P.prods + uload(P.seg_prod + uload(P.ov_seg + v)));
-    for_products_recs<SR>(P, d0, rb, nrec, wid, nw, accum);
+  if (RECS && rb >= 0) {
+    for_products_recs<SR>(P, rb, nrec, wid, nw, accum);
   } else {
     for_products<SR>(P, v, b0, b1, wid, nw, accum);
   }
@@ -1109,7 +1136,7 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
 
 // Numeric pass of one planned heavy window (MODE 2: either window kind).
 // `it` is wave-uniform; the item's descriptor is one scalar load.
-template <int K, int MODE>
+template <int K, int MODE, bool RECS>
 __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
   const ItemDev I = uload(P.items + it);
   const GroupDev G = uload(P.groups + I.g);
@@ -1119,7 +1146,7 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
   if (MODE == 0 || (MODE == 2 && G.mode == 0))
     dense_window<K, false>(P, I.v, I.b0, lo, hi, I.pos, lds, scratch, (G.sw + 31) >> 5);
   else
-    rank_window<K, false>(P, I.v, lo, hi, I.b0, I.b1, I.pos, lds, scratch,
+    rank_window<K, false, false, RECS>(P, I.v, lo, hi, I.b0, I.b1, I.pos, lds, scratch,
                           I.q < P.nkeep ? P.hbits + I.q * P.hstride : nullptr, I.rbase, I.nrec);
 }
 
@@ -1169,8 +1196,10 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_
 // The numeric launch keeps one queue per XCD over the windows of that XCD's id ranges
 // (`queue` has kXcds counters); a workgroup starts with the queue of the XCD
 // it runs on, taken as blockIdx.x mod kXcds (workgroups are dispatched to
-// the dies round-robin), and then drains the others in turn.
-template <int K, int MODE>
+// the dies round-robin), and then drains the others in turn. RECS: the
+// plan has entry records (a separate instantiation, so plans without them
+// keep the plain walk's code).
+template <int K, int MODE, bool RECS>
 __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int64_t *queue) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t scratch[kMaxWaves + 1];
@@ -1198,7 +1227,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
       // round trip overlaps the window instead of preceding it
       int64_t nxt = 0;
       if (threadIdx.x == 0) nxt = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
-      heavy_item<K, MODE>(P, i, lds, scratch);
+      heavy_item<K, MODE, RECS>(P, i, lds, scratch);
       if (threadIdx.x == 0) s_item = nxt;
       __syncthreads();
       i = lo + uni(s_item);
@@ -1258,7 +1287,7 @@ __global__ void __launch_bounds__(kBlockMax, heavy_count_waves<MODE>()) k_heavy_
 // One persistent launch for every tier: queue items are heavy windows
 // first, then mid vectors, then chunks of 64 tiny-list positions (one chunk
 // per wavefront, packed as in tiny_pack).
-template <int K, int MODE>
+template <int K, int MODE, bool RECS>
 __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, int64_t *queue, int64_t n_items, int64_t n_mid,
                                                   int64_t n_tiny) {
   extern __shared__ uint32_t lds[];
@@ -1276,7 +1305,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
     __syncthreads();
     if (i >= total) break;
     if (i < n_items) {
-      heavy_item<K, MODE>(P, i, lds, scratch);
+      heavy_item<K, MODE, RECS>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
       const int64_t v = uload(P.mid_list + (i - n_items));
       if (P.mid_kind == 0) rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds, scratch);

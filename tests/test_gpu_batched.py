@@ -227,3 +227,25 @@ def test_summa_share_many_segments(sg, force):
         C = BT.summa_share(semiring, dA, dB, tuning=t, batched=batched).to_host()
         assert_canonical(C)
         assert_same(C, R, semiring, 1e-12, f"force {force} batched {batched}")
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
+@pytest.mark.parametrize("entry_mb", [1, 2048])
+def test_summa_share_entry_records(sg, semiring, entry_mb):
+    """Heavy windows of vectors fed by 16 stage products, walked from entry records (all, or
+    some within a 1 MiB budget), per tier launch and in the persistent launch."""
+    from paper_1006_2183_amd import batched as BT
+    scale, grid = 12, 16
+    _say(f"case summa share entry records {semiring} entry_mb={entry_mb}")
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (3, 5), semiring=semiring, seed=17)
+    b = (1 << scale) // grid
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
+    R, _ = oracle.spgemm(semiring, SA, SB)
+    for batched in (False, True):
+        t = sg.make_tuning(semiring, force_tier=2, lds_bytes=24576, block_threads=512, heavy_lds_bytes=24576,
+                           heavy_threads=512, entry_mb=entry_mb)
+        C = BT.summa_share(semiring, dA, dB, tuning=t, batched=batched).to_host()
+        assert_canonical(C)
+        assert_same(C, R, semiring, 1e-12, f"entry_mb {entry_mb} batched {batched}")

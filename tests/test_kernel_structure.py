@@ -56,7 +56,8 @@ def queue_loop_report(asm: str):
 
 def test_queue_loops_stay_convergent(tmp_path):
     rows = queue_loop_report(_asm(str(tmp_path)))
-    # 4 semirings x (mid count and numeric, heavy count and numeric per window kind, batched per kind set)
-    assert len(rows) == 36, f"expected 36 queue kernels, found {len(rows)}"
+    # 4 semirings x (mid count and numeric, heavy count per window kind, heavy numeric per window kind
+    # plus rank windows with entry records, batched per kind set plus the two with rank windows and records)
+    assert len(rows) == 48, f"expected 48 queue kernels, found {len(rows)}"
     bad = [r for r in rows if not r[1]]
     assert not bad, "queue loop restructured: " + "; ".join(f"{n}: {why}" for n, _, why in bad)
