@@ -58,10 +58,10 @@ struct GroupDev {
   int32_t sw;            // split bucket width (a multiple of 32)
   int32_t mode;          // heavy tier: 0 dense windows of one bucket, 1 rank windows of several buckets
   int32_t mid_ok;        // largest mid-tier vector of this group (0: the mid tier does not fit)
-  int32_t rank_cap;      // mode 1: most entries one window may hold
+  int32_t rank_cap;      // mode 1: LDS of one window in value slots ({bits, prefix} words plus values)
   int32_t rank_wb;       // mode 1: most buckets one window may span
   int32_t bpr;           // split buckets per XCD range (windows never cross a range)
-  int32_t pad;
+  int32_t rank_wcost;    // mode 1: value slots taken by the {bits, prefix} words of one bucket
   int64_t ov_begin;      // first output vector of this group (device-filled)
   int64_t ov_end;
   int64_t nnz_base;      // global exclusive offset of the group's first entry

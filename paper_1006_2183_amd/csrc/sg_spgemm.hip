@@ -125,7 +125,7 @@ int64_t mid_capacity(const sg_tuning &t, int32_t kind, int64_t minor) {
 
 // Heavy-tier geometry of one output id range (see GroupDev).
 struct Geom {
-  int32_t nsplit = 1, sw = 32, mode = 0, rank_cap = 0, rank_wb = 0, bpr = 1;
+  int32_t nsplit = 1, sw = 32, mode = 0, rank_cap = 0, rank_wb = 0, bpr = 1, rank_wcost = 0;
 };
 
 Geom group_geom(const sg_tuning &t, int32_t kind, int64_t minor, int win_dense) {
@@ -154,11 +154,16 @@ Geom group_geom(const sg_tuning &t, int32_t kind, int64_t minor, int win_dense) 
         ++wb;
       }
       if (count_fits && wb >= 1 && nb < INT32_MAX) {
+        // a window is bounded by its whole LDS, words and values together
+        // (8 bytes of {bits, prefix} per 32 ids of its span, sb per entry),
+        // so dense windows take more entries and sparse ones more buckets
+        // than the half-and-half split that fixed sw
         g.mode = 1;
         g.sw = (int32_t)sw;
         g.nsplit = (int32_t)nb;
-        g.rank_cap = (int32_t)cap;
-        g.rank_wb = (int32_t)wb;
+        g.rank_cap = (int32_t)(L / sb);
+        g.rank_wcost = (int32_t)((8 * (sw / 32) + sb - 1) / sb);
+        g.rank_wb = (int32_t)std::min<int64_t>(nb, (L / sb - 1) / g.rank_wcost);
         return g;
       }
     }
@@ -896,7 +901,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     G.rank_cap = ge.rank_cap;
     G.rank_wb = ge.rank_wb;
     G.bpr = ge.bpr;
-    G.pad = 0;
+    G.rank_wcost = ge.rank_wcost;
     const int64_t cap = mid_capacity(t, sr->kind, G.minor);
     G.mid_ok = cap > 0 ? (int32_t)std::min<int64_t>(cap, INT32_MAX) : 0;
     G.ov_begin = G.ov_end = G.nnz_base = G.nz_base = 0;

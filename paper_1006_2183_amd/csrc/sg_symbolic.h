@@ -474,10 +474,13 @@ __global__ void k_wsplit(const int64_t *g_ptr, const int32_t *g_idx, int64_t g_n
 
 // Heavy-tier windows of one vector inside buckets [bs, be) (one XCD range)
 // from its bucket counts. Mode 0: one window per non-empty bucket. Mode 1:
-// consecutive buckets are merged while the entries fit rank_cap and the span
-// fits rank_wb buckets; empty buckets between windows are skipped. Every
-// bucket holds at most sw <= rank_cap entries, so each window takes at least
-// one bucket. `emit` receives (b0, b1, entries of the vector before b0).
+// consecutive buckets are merged while the window's LDS (the words of its
+// span plus its values, in value slots) fits rank_cap, its span rank_wb
+// buckets and its entries kRankMaxEntries; empty buckets between windows are
+// skipped. One bucket (sw ids, at most sw entries) always fits, so each
+// window takes at least one. `emit` receives (b0, b1, entries of the vector
+// before b0).
+constexpr int64_t kRankMaxEntries = 65504;
 template <class F>
 __device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t *bc, int32_t bs, int32_t be,
                                                 int64_t before, F emit) {
@@ -494,7 +497,8 @@ __device__ __forceinline__ int64_t plan_windows(const GroupDev &G, const int32_t
       sum = bc[b];
       ++b;
     } else {
-      while (b < be && (b - b0) < G.rank_wb && sum + bc[b] <= G.rank_cap) {
+      while (b < be && (b - b0) < G.rank_wb && sum + bc[b] <= kRankMaxEntries &&
+             (int64_t)(b - b0 + 1) * G.rank_wcost + sum + bc[b] <= G.rank_cap) {
         sum += bc[b];
         ++b;
       }

@@ -278,7 +278,7 @@ def test_entry_records_budget(sg, entry_mb):
     semiring = "min_plus_i32"
     A = W.rmat_matrix(12, 16, semiring, "csr", seed=21)
     _say(f"case entry records entry_mb={entry_mb}")
-    C, info = gpu_product(sg, semiring, A, A, lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384,
+    C, info = gpu_product(sg, semiring, A, A, lds_bytes=8192, block_threads=256, heavy_lds_bytes=8192,
                           heavy_threads=256, entry_mb=entry_mb)
     assert info["n_heavy_items"] > info["n_heavy"] > 0  # several windows per heavy vector
     check(semiring, C, A, A, f"entry_mb={entry_mb}")
