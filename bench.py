@@ -479,7 +479,7 @@ def ingest_counters(root, copy_mib, workload, semiring):
             raise SystemExit(f"no copy kernel dispatch in {sub}")
         factors[ctr] = copy_bytes / (float(np.median(vals)) * 1024.0)
     per = {}
-    pat = re.compile(r"k_heavy<\d+, \d+>")  # the numeric heavy kernel (not k_heavy_count)
+    pat = re.compile(r"k_heavy<\d+, \d+(, (true|false))?>")  # the numeric heavy kernel (not k_heavy_count)
     for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         vals = [v for k, c, v, _ in _counter_rows(os.path.join(root, sub)) if c == ctr and pat.search(k)]
         if not vals:
