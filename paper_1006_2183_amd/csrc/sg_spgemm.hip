@@ -624,6 +624,19 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   Plan P = pl->P;
   P.lds_words = lds / 4;
   const sg_sym_info &I = pl->info[0];
+  if (I.n_heavy_items == 0 && I.n_mid == 0) {
+    // tiny vectors only (Galerkin triple products on grids): the tiny
+    // kernel alone is the one launch, with no LDS to cap its occupancy
+    SG_TRY(mark(pl, 0, false, st));
+    if (I.n_tiny > 0) {
+      const int64_t tp = (int64_t)pl->ncu * pl->tune.blocks_per_cu * 8;
+      hipLaunchKernelGGL((k_tiny<K, false>), dim3((unsigned)std::min<int64_t>((I.n_tiny + 3) / 4, tp)), dim3(256), 0,
+                         st, pl->P);
+      SG_HIP(hipGetLastError());
+    }
+    SG_TRY(mark(pl, 0, true, st));
+    return SG_OK;
+  }
   const int64_t persist = resident_blocks(pl->ncu, nt, lds, kWavesPerSimd);
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
   SG_TRY(mark(pl, 0, false, st));
