@@ -321,6 +321,51 @@ __device__ __forceinline__ int64_t wave_max64(int64_t x) {
 
 // Uniform read of lane o's value (o is wave-uniform).
 __device__ __forceinline__ int read_lane(int x, int o) { return __builtin_amdgcn_readlane(x, o); }
+
+// Lane l receives lane (l xor j)'s x, for a power of two j that is a
+// constant once loops are unrolled: quad permutes (1, 2) and row shifts
+// (4, 8) of DPP and the 16- and 32-lane swaps of gfx950 (16, 32), all on
+// the VALU, so a sorting network moves no data through LDS. Every lane of
+// the wavefront must be active.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, int j) {
+  const int l = lane();
+  const int v = (int)x;
+  switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    case 4: {
+      const int up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, false);  // row_shl:4, lane l + 4
+      const int dn = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, false);  // row_shr:4, lane l - 4
+      return (uint32_t)((l & 4) ? dn : up);
+    }
+    case 8: {
+      const int up = __builtin_amdgcn_mov_dpp(v, 0x108, 0xF, 0xF, false);  // row_shl:8
+      const int dn = __builtin_amdgcn_mov_dpp(v, 0x118, 0xF, 0xF, false);  // row_shr:8
+      return (uint32_t)((l & 8) ? dn : up);
+    }
+    case 16: {
+      // first result: even rows copied over the odd ones; second: odd rows over the even ones
+      const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+      return (l & 16) ? r[0] : r[1];
+    }
+    case 32: {
+      // first result: the low half in both halves; second: the high half in both
+      const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+      return (l & 32) ? r[0] : r[1];
+    }
+    default: return (uint32_t)__shfl_xor(v, j, kWave);
+  }
+}
+__device__ __forceinline__ int32_t xor_lane(int32_t x, int j) { return (int32_t)xor_lane((uint32_t)x, j); }
+__device__ __forceinline__ uint64_t xor_lane(uint64_t x, int j) {
+  return ((uint64_t)xor_lane((uint32_t)(x >> 32), j) << 32) | xor_lane((uint32_t)x, j);
+}
+__device__ __forceinline__ double xor_lane(double x, int j) {
+  return __longlong_as_double((long long)xor_lane((uint64_t)__double_as_longlong(x), j));
+}
+__device__ __forceinline__ float xor_lane(float x, int j) {
+  return __uint_as_float(xor_lane((uint32_t)__float_as_uint(x), j));
+}
 __device__ __forceinline__ int64_t read_lane64(int64_t x, int o) {
   uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, o);
   uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), o);

@@ -422,8 +422,8 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
   for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const int pk = __shfl_xor(key, j, kWave);
-      const T pv = __shfl_xor(val, j, kWave);
+      const int pk = xor_lane(key, j);
+      const T pv = SR::kVal ? xor_lane(val, j) : T();
       const bool up = (l & k) == 0;
       const bool low = (l & j) == 0;
       const bool take = low ? (up ? pk < key : pk > key) : (up ? pk > key : pk < key);
@@ -553,8 +553,8 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
       for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          const uint64_t pk = __shfl_xor(ck, jj, kWave);
-          const T pv = __shfl_xor(val, jj, kWave);
+          const uint64_t pk = xor_lane(ck, jj);
+          const T pv = SR::kVal ? xor_lane(val, jj) : T();
           const bool up = (l & k) == 0;
           const bool low = (l & jj) == 0;
           const bool take = low ? (up ? pk < ck : pk > ck) : (up ? pk > ck : pk < ck);
