@@ -278,13 +278,17 @@ __device__ __forceinline__ int64_t uni(int64_t x) {
 // Wavefront helpers (wave64).
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 
+// Inclusive sum over lanes 0..l, on the VALU with DPP: row shifts by 1, 2,
+// 4 and 8 scan each 16-lane row (lanes shifted in from outside the row read
+// 0), then the last lane of each row is added to the next row and the last
+// lane of the first half to the second half. Every lane must be active.
 __device__ __forceinline__ int wave_incl_scan(int x) {
-  const int l = lane();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    int t = __shfl_up(x, d, kWave);
-    if (l >= d) x += t;
-  }
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1 and 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
@@ -298,26 +302,6 @@ __device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
   return x;
 }
 
-__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
-}
-
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
-}
-
-__device__ __forceinline__ int64_t wave_max64(int64_t x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    int64_t t = __shfl_xor(x, d, kWave);
-    x = t > x ? t : x;
-  }
-  return x;
-}
 
 // Uniform read of lane o's value (o is wave-uniform).
 __device__ __forceinline__ int read_lane(int x, int o) { return __builtin_amdgcn_readlane(x, o); }
@@ -365,6 +349,28 @@ __device__ __forceinline__ double xor_lane(double x, int j) {
 }
 __device__ __forceinline__ float xor_lane(float x, int j) {
   return __uint_as_float(xor_lane((uint32_t)__float_as_uint(x), j));
+}
+
+// Butterfly reductions over the wavefront (every lane gets the result).
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += (int64_t)xor_lane((uint64_t)x, d);
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += xor_lane((int32_t)x, d);
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_max64(int64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const int64_t t = (int64_t)xor_lane((uint64_t)x, d);
+    x = t > x ? t : x;
+  }
+  return x;
 }
 __device__ __forceinline__ int64_t read_lane64(int64_t x, int o) {
   uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, o);
