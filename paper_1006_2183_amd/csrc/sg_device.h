@@ -351,6 +351,58 @@ __device__ __forceinline__ float xor_lane(float x, int j) {
   return __uint_as_float(xor_lane((uint32_t)__float_as_uint(x), j));
 }
 
+// One DPP move of a 64-bit value (both halves with the same control);
+// lanes without a source lane, or in rows outside ROWS, get `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t old, uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)old, (int)(uint32_t)x, CTRL, ROWS, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(old >> 32), (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_any(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int32_t dpp_any(int32_t x) { return (int32_t)dpp_any<CTRL, ROWS>((uint32_t)x); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_any(float x) { return __uint_as_float(dpp_any<CTRL, ROWS>(__float_as_uint(x))); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_any(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  return __longlong_as_double((long long)dpp64<CTRL, ROWS>(b, b));
+}
+
+// Lane l + 1's key (lane 63 gets ~key, which differs from its own).
+__device__ __forceinline__ uint64_t next_lane_key(uint64_t key) { return dpp64<0x130, 0xF>(~key, key); }  // wave_shl:1
+
+// Inclusive prefix, with the semiring's add, over each run of equal keys
+// (runs are contiguous: the keys are sorted): lane l ends with the sum of
+// its run's lanes up to l, so a run's last lane holds the run's total.
+// Steps of 1, 2, 4 and 8 lanes inside each 16-lane row, then lane 15 of a
+// row is added into the next row and lane 31 into the upper half, each
+// where the key still matches (a lane without a source sees ~key). All on
+// the VALU; every lane must be active.
+template <class SR, class T>
+__device__ __forceinline__ T seg_prefix(uint64_t key, T val) {
+  const uint64_t miss = ~key;
+#define SG_SEG_STEP(CTRL, ROWS)                                 \
+  {                                                             \
+    const uint64_t k = dpp64<CTRL, ROWS>(miss, key);            \
+    const T v = dpp_any<CTRL, ROWS>(val);                       \
+    if (k == key) val = SR::add(val, v);                        \
+  }
+  SG_SEG_STEP(0x111, 0xF)  // row_shr:1
+  SG_SEG_STEP(0x112, 0xF)  // row_shr:2
+  SG_SEG_STEP(0x114, 0xF)  // row_shr:4
+  SG_SEG_STEP(0x118, 0xF)  // row_shr:8
+  SG_SEG_STEP(0x142, 0xA)  // row_bcast:15 into rows 1 and 3
+  SG_SEG_STEP(0x143, 0xC)  // row_bcast:31 into rows 2 and 3
+#undef SG_SEG_STEP
+  return val;
+}
+
 // Butterfly reductions over the wavefront (every lane gets the result).
 __device__ __forceinline__ int64_t wave_sum64(int64_t x) {
 #pragma unroll

@@ -433,23 +433,16 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
       }
     }
   }
-  // segmented (+) of equal ids: the head lane of each run ends with its total
-  if (SR::kVal) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int kd = __shfl_down(key, d, kWave);
-      const T vd = __shfl_down(val, d, kWave);
-      if (l + d < kWave && kd == key) val = SR::add(val, vd);
-    }
-  }
-  const int prev = __shfl_up(key, 1, kWave);
-  const bool head = key != INT32_MAX && (l == 0 || prev != key);
-  const uint64_t hm = __ballot(head);
+  // segmented (+) of equal ids: the last lane of each run ends with its total
+  const uint64_t k64 = (uint64_t)(uint32_t)key;
+  if (SR::kVal) val = seg_prefix<SR>(k64, val);
+  const bool tail = key != INT32_MAX && next_lane_key(k64) != k64;
+  const uint64_t hm = __ballot(tail);
   if (COUNT) {
     if (l == 0) P.ov_cnt[v] = __popcll(hm);
     return;
   }
-  if (head) {
+  if (tail) {
     const int r = __popcll(hm & ((1ull << l) - 1ull));
     const OutDev O = uload(P.outs + uload(P.ov_group + v));
     const int64_t pos = out_offset(P, v) + r;
@@ -564,18 +557,11 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
           }
         }
       }
-      if (SR::kVal) {
-#pragma unroll
-        for (int dd = 1; dd < kWave; dd <<= 1) {
-          const uint64_t kd = __shfl_down(ck, dd, kWave);
-          const T vd = __shfl_down(val, dd, kWave);
-          if (l + dd < kWave && kd == ck) val = SR::add(val, vd);
-        }
-      }
-      const uint64_t prev = __shfl_up(ck, 1, kWave);
+      // segmented (+) of equal keys: the last lane of each run holds its total
+      if (SR::kVal) val = seg_prefix<SR>(ck, val);
       const int tag = (int)(ck >> 32);
-      const bool head = tag < kWave && (l == 0 || prev != ck);
-      const uint64_t hm = __ballot(head);
+      const bool tail = tag < kWave && next_lane_key(ck) != ck;
+      const uint64_t hm = __ballot(tail);
       // vector lane x owns the sorted lanes [Finc_x - f_x - bf, Finc_x - bf)
       const int seg_a = Finc - fp - bf;
       if (COUNT) {
@@ -584,7 +570,7 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
         const int src = tag < kWave ? tag : 0;
         const int a = __shfl(seg_a, src, kWave);
         const int64_t base = __shfl(opos, src, kWave);
-        if (head) {
+        if (tail) {
           const int64_t pos = base + __popcll(hm & lane_range(a, l));
           gstore(O.idx + pos, (int32_t)(uint32_t)ck);
           if (SR::kVal) gstore((T *)O.val + pos, val);
