@@ -276,7 +276,9 @@ __device__ __forceinline__ int64_t entries_flops(const ProdDev &d, int64_t e0, i
 // with per-tier flops and streamed entries). A wavefront takes 64
 // consecutive output vectors, one per lane: vectors with one segment of the
 // chunk's common product and at most kSerial streamed entries are summed by
-// their own lane; the others by the whole wavefront, one at a time.
+// their own lane; the others by the whole wavefront, one at a time (over
+// the entries of each segment, or one segment per lane when there are
+// kLaneSegs segments or more and they are short).
 //
 // Tiers: no multiplication, none; else forced tier if any (a forced mid
 // vector that does not fit goes heavy); else tiny up to tiny_max flops; mid
@@ -286,7 +288,8 @@ __device__ __forceinline__ int64_t entries_flops(const ProdDev &d, int64_t e0, i
 __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *counters, int32_t *tiny, int32_t *mid,
                             int32_t *heavy) {
   constexpr int kSerial = 32;
-  constexpr int kBatch = 8;  // chunks whose list appends share one atomic per tier
+  constexpr int kLaneSegs = 8;  // segments from which a vector's segments go one per lane
+  constexpr int kBatch = 8;     // chunks whose list appends share one atomic per tier
   const int l = lane();
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -347,13 +350,50 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
         coop &= coop - 1ull;
         const int64_t vx = v0 + x;
         int64_t fx = 0, sx = 0;
-        const int64_t s1 = uload(P.ov_seg + vx + 1);
-        for (int64_t s = uload(P.ov_seg + vx); s < s1; ++s) {
-          const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
-          const int32_t tt = uload(P.seg_svec + s);
-          const int64_t e0 = uload(d.s_ptr + tt), e1 = uload(d.s_ptr + tt + 1);
-          fx += entries_flops(d, e0 + l, e1, kWave);
-          sx += e1 - e0;
+        const int64_t s0x = uload(P.ov_seg + vx), s1 = uload(P.ov_seg + vx + 1);
+        // segments one after another, each one's entries across the lanes
+        auto by_segment = [&](int64_t sa, int64_t sz) {
+          for (int64_t s = sa; s < sz; ++s) {
+            const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+            const int32_t tt = uload(P.seg_svec + s);
+            const int64_t e0 = uload(d.s_ptr + tt), e1 = uload(d.s_ptr + tt + 1);
+            fx += entries_flops(d, e0 + l, e1, kWave);
+            sx += e1 - e0;
+          }
+        };
+        if (s1 - s0x >= kLaneSegs) {
+          // many segments (the stage products of a SUMMA share): 64 at a
+          // time, one per lane, so their descriptor chains run side by side;
+          // a segment of at most four entries is then summed by its lane,
+          // a longer one (a k-way merge of partials) has its entries spread
+          // across the lanes
+          int64_t lane_s = 0;
+          for (int64_t sb = s0x; sb < s1; sb += kWave) {
+            const int64_t s = sb + l;
+            int64_t e0 = 0, e1 = 0;
+            const ProdDev *dl = nullptr;
+            if (s < s1) {
+              dl = P.prods + gload(P.seg_prod + s);
+              const int32_t tt = gload(P.seg_svec + s);
+              const int64_t *sp = dl->s_ptr;
+              e0 = gload(sp + tt);
+              e1 = gload(sp + tt + 1);
+            }
+            const bool brief = e1 - e0 <= 4;
+            if (s < s1 && brief) {
+              fx += entries_flops(*dl, e0, e1, 1);
+              lane_s += e1 - e0;
+            }
+            uint64_t longer = __ballot(s < s1 && !brief);
+            while (longer) {
+              const int x = __ffsll((unsigned long long)longer) - 1;
+              longer &= longer - 1ull;
+              by_segment(sb + x, sb + x + 1);
+            }
+          }
+          sx += wave_sum64(lane_s);
+        } else {
+          by_segment(s0x, s1);
         }
         fx = wave_sum64(fx);
         if (l == x) {
