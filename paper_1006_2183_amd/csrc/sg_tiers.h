@@ -168,9 +168,10 @@ __device__ __forceinline__ void run_batch(int len, int64_t gb, typename SR::T sv
 // Products of one batch of (up to) 64 stored entries of S, one per lane
 // (lane e holds `len` products at G positions [gb, gb + len) with S value
 // sv), spread flat over the lanes: product f (in entry order) goes to lane
-// f mod 64 of round f / 64, so every round but the last keeps all 64 lanes
-// busy whatever the entry lengths. R rounds at a time have all their
-// gathers in flight before the accumulator sees any.
+// f mod 64 of round f / 64 (with Act::kSpread, lane l takes product 9 l mod
+// 64 of the round), so every round but the last keeps all 64 lanes busy
+// whatever the entry lengths. R rounds at a time have all their gathers in
+// flight before the accumulator sees any.
 // The entry of a lane's product: a round inside one entry (the common case
 // of long G vectors) reads that entry's G base and S value as scalars; a
 // round where a few entries start takes them in order with one compare per
@@ -606,7 +607,7 @@ struct RankAcc {
   typedef typename SR::Slot Slot;
   static constexpr bool kFlat = true;
   static constexpr bool kSpread = false;  // consecutive ranks: consecutive banks
-  static constexpr int kRounds = 4;       // eight measured slower (register pressure)
+  static constexpr int kRounds = 4;       // eight measured slower: more misses in flight only wait longer
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
