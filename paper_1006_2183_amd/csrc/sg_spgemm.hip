@@ -750,7 +750,10 @@ extern "C" {
 void sg_tuning_default(int32_t kind, sg_tuning *t) {
   if (!t) return;
   t->tiny_max_flops = 64;
-  t->mid_max_ub = 65535;
+  // 4-byte values leave the mid tier room for twice the entries of FP64
+  // ones; vectors beyond about 1,500 entries still run faster as heavy
+  // windows, so those semirings cap the mid tier where FP64's LDS caps it
+  t->mid_max_ub = (kind == SG_MIN_PLUS_I32 || kind == SG_PLUS_TIMES_F32) ? 1536 : 65535;
   t->mid_kind = 0;
   t->lds_bytes = 77 * 1024;
   t->block_threads = 512;

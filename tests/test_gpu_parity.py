@@ -91,9 +91,10 @@ def test_rmat_s10_default_tiers(sg, semiring, batched):
                                                                  (2, 0, 0, 4096), (2, 0, 0, 0), (2, 0, 0, 1),
                                                                  (2, 0, 1, 4096), (-1, 0, 0, 4096), (-1, 1, 1, 0)])
 def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind, bitmap_mb):
-    """Every tier on every vector it can take. 16 KB of LDS: rank windows hold 1024 (f64)
-    or 2048 (4-byte values) entries over 1K/2K-id buckets, so heavy rows split into several
-    planned windows; dense windows are ~2K ids wide over 8192 columns (the last partial).
+    """Every tier on every vector it can take. 16 KB of LDS: a rank window's words and values
+    share 2048 (f64) or 4096 (4-byte values) value slots over 1K/2K-id buckets, so heavy rows
+    split into several planned windows; dense windows are ~2K ids wide over 8192 columns (the
+    last partial).
     bitmap_mb 0 re-marks every window; 1 MiB keeps the bitmaps of only part of the heavy vectors."""
     _say(f"case forced tier {force} mid_kind {mid_kind} heavy_kind {heavy_kind} bitmap_mb {bitmap_mb} {semiring}")
     A = W.rmat_matrix(13, 8, semiring, "csr", seed=4)
