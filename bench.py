@@ -143,31 +143,71 @@ def rows_subset(A, rows):
                                  val=None if A.val is None else A.val[sel], vid=None)
 
 
+def host_info():
+    """The host the oracle runs on: CPU model, logical CPUs, and the threads the
+    all-core oracle uses (the CPUs this process may run on, at most 16: the GPU
+    box's CPU share per GPU)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail, "threads": max(1, min(16, avail))}
+
+
+def _oracle_timed(fn, threads):
+    t = time.perf_counter()
+    _, fl = fn(threads)
+    return fl, time.perf_counter() - t
+
+
 def cpu_baseline(semiring, A, total_flops, seconds):
-    """The oracle, single-threaded, on a uniform random row sample of C = A A."""
+    """The oracle on a uniform random row sample of C = A A: single-threaded, and on
+    every available host core (row slices on a thread pool, each the same C routine)."""
     import oracle
+    hi = host_info()
     rng = np.random.default_rng(7)
     n = A.nrows
-    # calibrate on a small sample, then size the sample for about `seconds`
+    # calibrate single-threaded on a small sample, then size the sample so that the
+    # single-threaded run takes about half of `seconds`
     probe = np.sort(rng.choice(n, max(64, n // 2000), replace=False))
-    t = time.perf_counter()
-    _, f0 = oracle.spgemm(semiring, rows_subset(A, probe), A)
-    dt = max(time.perf_counter() - t, 1e-3)
-    rate = f0 / dt
-    frac = min(1.0, seconds * rate / max(total_flops, 1))
+    f0, dt = _oracle_timed(lambda th: oracle.spgemm(semiring, rows_subset(A, probe), A), 1)
+    rate = f0 / max(dt, 1e-3)
+    frac = min(1.0, 0.5 * seconds * rate / max(total_flops, 1))
     k = max(64, int(round(frac * n)))
     rows = np.sort(rng.choice(n, k, replace=False))
-    t = time.perf_counter()
-    _, fl = oracle.spgemm(semiring, rows_subset(A, rows), A)
-    dt = time.perf_counter() - t
+    sub = rows_subset(A, rows)
+    fl1, dt1 = _oracle_timed(lambda th: oracle.spgemm(semiring, sub, A), 1)
+    fln, dtn = _oracle_timed(lambda th: oracle.spgemm_threads(semiring, sub, A, threads=th), hi["threads"])
     return {
-        "value": fl / dt / 1e9,
+        "value": fln / dtn / 1e9,
         "unit": "GFLOP/s",
-        "cores": 1,
+        "cores": hi["threads"],
         "kind": "oracle",
-        "sample": f"C(R,:) = A(R,:) A for {k} of {n} rows drawn uniformly (seed 7): {fl} multiplications in "
-                  f"{dt:.1f} s, single-threaded C Gustavson with a dense accumulator",
+        "single_thread_value": fl1 / dt1 / 1e9,
+        "host": hi,
+        "sample": f"C(R,:) = A(R,:) A for {k} of {n} rows drawn uniformly (seed 7): {fl1} multiplications; "
+                  f"single-threaded C Gustavson with a dense accumulator {dt1:.1f} s, on {hi['threads']} threads "
+                  f"(row slices, same routine) {dtn:.1f} s",
     }
+
+
+def cpu_rate(fn_by_threads, what):
+    """Oracle rate of one bounded sample, single-threaded and on every available core."""
+    hi = host_info()
+    fl1, dt1 = _oracle_timed(fn_by_threads, 1)
+    fln, dtn = _oracle_timed(fn_by_threads, hi["threads"])
+    return {"value": round(fln / dtn / 1e9, 4), "unit": "GFLOP/s", "cores": hi["threads"], "kind": "oracle",
+            "single_thread_value": round(fl1 / dt1 / 1e9, 4), "sample": what,
+            "seconds": {"single_thread": round(dt1, 2), "all_cores": round(dtn, 2)}}
 
 
 # ---------------------------------------------------------------------------
@@ -258,6 +298,7 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
     dA = [sg.DevMat.from_host(x, "cuda", sr) for x in a_blocks]
     dB = [sg.DevMat.from_host(x, "cuda", sr) for x in b_blocks]
     nnz_blocks = [x.nnz for x in a_blocks]
+    cpu = summa_cpu_baseline(sr, a_blocks, b_blocks, grid, (1 << scale) // grid)
     del a_blocks, b_blocks
     torch.cuda.empty_cache()
     res = {}
@@ -304,11 +345,29 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
                               "achieved_GBs": round(algo / kms / 1e6, 1) if kms > 0 else None},
         "plain": "64 x (symbolic + sync + alloc + per-tier numeric) into DCSC partials, then a 64-way merge",
         "exact": "batched == plain == graph replay (patterns exact, values within 1e-12 relative)",
+        "cpu_baseline": cpu,
     }
     plan.destroy()
     del G, res, dA, dB
     torch.cuda.empty_cache()
     return out
+
+
+def summa_cpu_baseline(sr, a_blocks, b_blocks, grid, b):
+    """The oracle on the whole share: the strip product A(I, :) A(:, J)."""
+    import oracle
+    ra, ca, va, rb, cb, vb = [], [], [], [], [], []
+    for k in range(grid):
+        A, B = a_blocks[k], b_blocks[k]
+        ra.append(A.idx.astype(np.int64)); va.append(A.val)
+        ca.append(np.repeat(A.vid.astype(np.int64), np.diff(A.ptr)) + k * b)
+        rb.append(B.idx.astype(np.int64) + k * b); vb.append(B.val)
+        cb.append(np.repeat(B.vid.astype(np.int64), np.diff(B.ptr)))
+    import workloads as W
+    SA = W.from_triples(np.concatenate(ra), np.concatenate(ca), np.concatenate(va), b, grid * b, "dcsc", sr)
+    SB = W.from_triples(np.concatenate(rb), np.concatenate(cb), np.concatenate(vb), grid * b, b, "dcsc", sr)
+    fn = lambda th: oracle.spgemm(sr, SA, SB) if th == 1 else oracle.spgemm_threads(sr, SA, SB, threads=th)
+    return cpu_rate(fn, "the whole share as one product of the DCSC strips A(I,:) A(:,J) (the block identity)")
 
 
 def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
@@ -386,6 +445,20 @@ def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
         "plain": "per instance: symbolic + sync + alloc + numeric for A P, then for R (A P)",
         "exact": "plain == grouped == tuned == graph bitwise; R A P == 4 L_(n/2) checked on one instance per size",
     }
+    import oracle
+
+    def cpu_fn(th):
+        fl = 0
+        for n in sizes:
+            L, P, R = host[n]
+            mul = (lambda a, b: oracle.spgemm(sr, a, b)) if th == 1 else \
+                (lambda a, b: oracle.spgemm_threads(sr, a, b, threads=th))
+            AP_, f1 = mul(L, P)
+            _, f2 = mul(R, AP_)
+            fl += f1 + f2
+        return None, fl
+
+    out["cpu_baseline"] = cpu_rate(cpu_fn, f"all {count} instances, each as two oracle calls A P then R (A P)")
     plan_ap.destroy()
     plan_rap.destroy()
     del G, res, Ls, Ps, Rs, AP
@@ -443,6 +516,19 @@ def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
             log(f"[bench] serving qps {qps} {name}: {line[name]}")
         out["levels"].append(line)
     out["exact"] = "every served column equals the pattern of A(:, src) (depth-0 closed form), both servers"
+    import oracle
+    import concurrent.futures as cf
+
+    def cpu_fn(th):
+        if th == 1:
+            return None, sum(oracle.spgemm(sr, A, X)[1] for X in Xs)
+        with cf.ThreadPoolExecutor(max_workers=th) as ex:
+            return None, sum(f for _, f in ex.map(lambda X: oracle.spgemm(sr, A, X), Xs))
+
+    cb = cpu_rate(cpu_fn, f"all {count} requests Y = A X, one oracle call each (requests spread over the threads)")
+    cb["requests_per_s"] = round(count / cb["seconds"]["all_cores"], 1)
+    cb["requests_per_s_single_thread"] = round(count / cb["seconds"]["single_thread"], 1)
+    out["cpu_baseline"] = cb
     del dA, dX
     torch.cuda.empty_cache()
     return out

@@ -283,8 +283,27 @@ sg_status sg_spgemm_batched(sg_plan *plan, sg_mat_out *C, void *stream);
 sg_status sg_plan_profile(sg_plan *plan, int32_t enable);
 sg_status sg_plan_kernel_times(sg_plan *plan, double *out_ms, int32_t n);
 
-/* Release a plan (host memory only; the workspace stays the caller's). */
+/*
+ * Release a plan. Host memory only: it frees the handle and makes no HIP
+ * call that waits for the device (kernel-timing events, if any were made,
+ * are destroyed), so it may be called while launches of the plan are still
+ * in flight. The workspace and the operand and output arrays stay the
+ * caller's, and must stay alive until those launches have completed.
+ */
 sg_status sg_plan_destroy(sg_plan *plan);
+
+/*
+ * Invariant counters of the checking build (the library compiled with
+ * SG_CHECK=1; sg_build_checked() returns 1 there and 0 in the normal
+ * build). Waits for the whole device, then writes up to n counters summed
+ * over every launch made with the plan so far: out[0] the work items after
+ * which a workgroup's LDS was not back to all-zero bits, out[1] the output
+ * vectors or heavy windows whose numeric phase wrote a different number of
+ * entries than the symbolic phase counted. Both are zero in a correct run,
+ * and always zero in the normal build, which compiles no checks.
+ */
+sg_status sg_plan_check(sg_plan *plan, int64_t *out, int32_t n);
+int32_t sg_build_checked(void);
 
 /*
  * Check that one operand is canonical (see the conventions above) on the

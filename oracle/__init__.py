@@ -118,6 +118,41 @@ def _vecs(M, vdt, keep):
 
 def spgemm(semiring: str, A, B):
     """Return (C, flops) for C = A (x) B; see the module docstring."""
+    return _spgemm(semiring, A, B, None)
+
+
+def spgemm_threads(semiring: str, A, B, threads: int = None, chunks_per_thread: int = 8):
+    """The same (C, flops) as ``spgemm``, computed on several host threads.
+
+    The streamed vectors (columns of B, or rows of A row-major) are cut into
+    consecutive slices; every slice runs the same single-threaded C routine
+    (its own accumulator, every output vector summed in ascending k exactly as
+    in ``spgemm``) on a thread of a pool (ctypes releases the interpreter lock
+    during the call), and the slices' outputs are concatenated in order. Only
+    the work is distributed; no output value is computed differently.
+    """
+    import concurrent.futures as cf
+    if threads is None:
+        threads = os.cpu_count() or 1
+    col = A.fmt in ("csc", "dcsc")
+    S = B if col else A
+    nvec = int(np.asarray(S.ptr).shape[0] - 1)
+    if S.fmt in ("dcsr", "dcsc") and (S.vid is None or len(S.vid) == 0):
+        nvec = 0
+    if threads <= 1 or nvec < 2:
+        return _spgemm(semiring, A, B, None)
+    # slices of about equal stored entries
+    ptr = np.asarray(S.ptr, dtype=np.int64)
+    nslices = max(1, min(nvec, threads * chunks_per_thread))
+    cuts = np.searchsorted(ptr, np.linspace(0, ptr[-1], nslices + 1)[1:-1]).tolist()
+    bounds = sorted(set([0] + [min(max(int(c), 0), nvec) for c in cuts] + [nvec]))
+    slices = list(zip(bounds[:-1], bounds[1:]))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda ab: _spgemm(semiring, A, B, ab, raw=True), slices))
+    return _assemble(semiring, A, B, parts)
+
+
+def _spgemm(semiring, A, B, rng, raw=False):
     code, vdt = SEMIRINGS[semiring]
     col = A.fmt in ("csc", "dcsc")
     if col != (B.fmt in ("csc", "dcsc")):
@@ -131,6 +166,15 @@ def spgemm(semiring: str, A, B):
         G, S, gfirst, m, major_dim = B, A, 0, B.ncols, A.nrows
     gv = _vecs(G, vdt, keep)
     sv = _vecs(S, vdt, keep)
+    t0 = 0
+    if rng is not None:
+        # slice [t0, t1) of the streamed vectors: pointer and id arrays start at
+        # t0; the entry offsets in ptr stay absolute, so idx/val are unchanged
+        t0, t1 = rng
+        sv.nvec = t1 - t0
+        sv.ptr = (sv.ptr or 0) + 8 * t0
+        if sv.vid:
+            sv.vid = sv.vid + 4 * t0
     res = _Result()
     lib = _load()
     rc = lib.orc_colwise(code, gfirst, int(m), ctypes.byref(gv), ctypes.byref(sv), ctypes.byref(res))
@@ -155,6 +199,36 @@ def spgemm(semiring: str, A, B):
         flops = int(res.flops)
     finally:
         lib.orc_free(ctypes.byref(res))
+    if S.fmt not in ("dcsr", "dcsc"):
+        vid = vid + np.int32(t0)  # a slice numbers its plain vectors from 0
+    if raw:
+        return vid, vptr, idx, val, flops
+    return _finish(A, B, S, col, major_dim, vid, vptr, idx, val, nnz, flops)
+
+
+def _assemble(semiring, A, B, parts):
+    col = A.fmt in ("csc", "dcsc")
+    S = B if col else A
+    major_dim = B.ncols if col else A.nrows
+    vids, ptrs, idxs, vals = [], [], [], []
+    off = 0
+    flops = 0
+    for vid, vptr, idx, val, f in parts:
+        vids.append(vid)
+        ptrs.append(vptr[1:] + off)
+        idxs.append(idx)
+        vals.append(val)
+        off += int(vptr[-1])
+        flops += f
+    vid = np.concatenate(vids).astype(np.int32)
+    vptr = np.concatenate([np.zeros(1, np.int64)] + ptrs)
+    idx = np.concatenate(idxs).astype(np.int32)
+    val = None if vals[0] is None else np.concatenate(vals)
+    return _finish(A, B, S, col, major_dim, vid, vptr, idx, val, off, flops)
+
+
+def _finish(A, B, S, col, major_dim, vid, vptr, idx, val, nnz, flops):
+    nv = vid.shape[0]
     doubly = S.fmt in ("dcsr", "dcsc")
     if col:
         fmt = "dcsc" if doubly else "csc"

@@ -14,6 +14,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgspgemm.so")
+# the same library built with SG_CHECK=1 (invariant counters, see sg_plan_check)
+CHECK_LIB_PATH = os.path.join(HERE, "libsgspgemm_check.so")
 
 SEMIRINGS = {"plus_times_f64": 0, "plus_times_f32": 1, "min_plus_i32": 2, "or_and_bool": 3}
 FORMATS = {"csr": 0, "csc": 1, "dcsr": 2, "dcsc": 3}
@@ -24,7 +26,7 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID_ARG", -2: "SG_ERR_DIM_MISMATCH", -3: "
 
 EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
            "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
-           "sg_validate", "sg_build_aux"]
+           "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked"]
 
 
 class SgError(RuntimeError):
@@ -80,13 +82,23 @@ class sg_sym_info(ctypes.Structure):
 
 
 _lib = None
+_libs = {}
 
 
-def load_library(path: str = LIB_PATH):
-    """Load the HIP library (no compute). Raises if it has not been built."""
+def load_library(path: Optional[str] = None):
+    """Load the HIP library (no compute). Raises if it has not been built.
+
+    The first call fixes the library the binding uses (the normal build unless
+    ``use_library`` chose another); later calls return it."""
     global _lib
-    if _lib is not None:
-        return _lib
+    if path is None:
+        if _lib is not None:
+            return _lib
+        path = LIB_PATH
+    if path in _libs:
+        if _lib is None:
+            _lib = _libs[path]
+        return _libs[path]
     # torch ships its own HIP runtime under the same soname as the system one;
     # whichever is loaded first serves the whole process, so load torch's first
     import torch  # noqa: F401
@@ -121,8 +133,25 @@ def load_library(path: str = LIB_PATH):
     lib.sg_validate.argtypes = [P(sg_mat), ctypes.c_void_p, ctypes.c_void_p]
     lib.sg_build_aux.restype = ctypes.c_int
     lib.sg_build_aux.argtypes = [P(sg_mat), ctypes.c_void_p, P(ctypes.c_int64), ctypes.c_void_p]
-    _lib = lib
+    lib.sg_plan_check.restype = ctypes.c_int
+    lib.sg_plan_check.argtypes = [ctypes.c_void_p, P(ctypes.c_int64), ctypes.c_int32]
+    lib.sg_build_checked.restype = ctypes.c_int32
+    lib.sg_build_checked.argtypes = []
+    _libs[path] = lib
+    if _lib is None:
+        _lib = lib
     return lib
+
+
+def use_library(path: str):
+    """Route every later call of this binding through the library at `path`
+    (e.g. CHECK_LIB_PATH); returns the previously used library's path."""
+    global _lib
+    prev = getattr(_lib, "_name", LIB_PATH) if _lib is not None else LIB_PATH
+    _lib = None
+    load_library(path)
+    _lib = _libs[path]
+    return prev
 
 
 def _check(status: int, where: str):
@@ -213,6 +242,14 @@ class DevMat:
         return d
 
 
+class _nullctx:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False
+
+
 def _stream(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -222,7 +259,9 @@ def _stream(stream=None):
 class Plan:
     """A symbolic plan: the library handle, its workspace and the operands it refers to."""
 
-    def __init__(self, semiring, As, Bs, group, ngroup, out_fmt, tuning, handle, ws, infos):
+    def __init__(self, semiring, As, Bs, group, ngroup, out_fmt, tuning, handle, ws, infos, stream=None):
+        self.lib = load_library()  # the library that made the handle
+        self.stream = stream
         self.semiring = semiring
         self.As, self.Bs = list(As), list(Bs)
         self.group = group
@@ -235,17 +274,27 @@ class Plan:
 
     def profile(self, enable: bool = True):
         """Record HIP events around every kernel launch of later numeric/batched calls."""
-        _check(load_library().sg_plan_profile(self.handle, 1 if enable else 0), "sg_plan_profile")
+        _check(self.lib.sg_plan_profile(self.handle, 1 if enable else 0), "sg_plan_profile")
 
     def kernel_times(self):
         """Milliseconds of the last profiled call: heavy (or persistent), mid, tiny, pointers."""
         out = (ctypes.c_double * 4)()
-        _check(load_library().sg_plan_kernel_times(self.handle, out, 4), "sg_plan_kernel_times")
+        _check(self.lib.sg_plan_kernel_times(self.handle, out, 4), "sg_plan_kernel_times")
         return {"heavy": out[0], "mid": out[1], "tiny": out[2], "ptr": out[3]}
 
+    def check(self):
+        """Invariant counters of a checking build: (LDS left dirty, count mismatches)."""
+        out = (ctypes.c_int64 * 2)()
+        _check(self.lib.sg_plan_check(self.handle, out, 2), "sg_plan_check")
+        return int(out[0]), int(out[1])
+
     def destroy(self):
+        """Release the handle (host only, never waits for the device). The workspace
+        tensor stays referenced by this object until it is garbage collected; it was
+        allocated on the plan's stream, so the caching allocator hands it out again
+        only in that stream's order."""
         if self.handle:
-            load_library().sg_plan_destroy(self.handle)
+            self.lib.sg_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -262,7 +311,12 @@ class Plan:
         return shapes
 
     def alloc_outputs(self, device="cuda") -> List[DevMat]:
-        """Exactly sized output matrices (torch allocations) for every group."""
+        """Exactly sized output matrices (torch allocations on the plan's stream) for every group."""
+        torch = _torch()
+        with torch.cuda.stream(self.stream) if self.stream is not None else _nullctx():
+            return self._alloc_outputs(device)
+
+    def _alloc_outputs(self, device):
         torch = _torch()
         vdt = _value_dtype(self.semiring)
         outs = []
@@ -339,31 +393,35 @@ def spgemm_symbolic(semiring: str, As: Sequence[DevMat], Bs: Sequence[DevMat], g
     _check(lib.sg_spgemm_workspace_size(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], tptr,
                                         ctypes.byref(sz)), "sg_spgemm_workspace_size")
     if ws is None or ws.numel() < sz.value:
-        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=As[0].ptr.device)
+        # allocated on the stream the kernels run on, so the caching allocator
+        # reuses it only in that stream's order after the plan is dropped
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            ws = torch.empty(int(sz.value), dtype=torch.uint8, device=As[0].ptr.device)
     handle = ctypes.c_void_p(0)
     infos = (sg_sym_info * ng)()
     _check(lib.sg_spgemm_symbolic(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], tptr,
                                   ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ctypes.byref(handle),
                                   infos, _stream(stream)), "sg_spgemm_symbolic")
     glist = None if group is None else [int(x) for x in group]
-    return Plan(semiring, As, Bs, glist, ng, out_fmt, tuning, handle, ws, [infos[i].as_dict() for i in range(ng)])
+    return Plan(semiring, As, Bs, glist, ng, out_fmt, tuning, handle, ws, [infos[i].as_dict() for i in range(ng)],
+                stream)
 
 
 def spgemm_numeric(plan: Plan, Cs: Sequence[DevMat], stream=None):
     arr = _out_descs(Cs)
-    _check(load_library().sg_spgemm_numeric(plan.handle, arr, _stream(stream)), "sg_spgemm_numeric")
+    _check(plan.lib.sg_spgemm_numeric(plan.handle, arr, _stream(stream)), "sg_spgemm_numeric")
 
 
 def spgemm_batched(plan: Plan, Cs: Sequence[DevMat], stream=None):
     arr = _out_descs(Cs)
-    _check(load_library().sg_spgemm_batched(plan.handle, arr, _stream(stream)), "sg_spgemm_batched")
+    _check(plan.lib.sg_spgemm_batched(plan.handle, arr, _stream(stream)), "sg_spgemm_batched")
 
 
 def spgemm(semiring: str, A: DevMat, B: DevMat, out_fmt: Optional[str] = None, tuning=None, batched=False,
            stream=None) -> DevMat:
     """C = A (x) B in one call (symbolic, allocation, numeric)."""
     plan = spgemm_symbolic(semiring, [A], [B], out_fmt=out_fmt, tuning=tuning, stream=stream)
-    C = plan.alloc_outputs(A.ptr.device)
+    C = plan.alloc_outputs(A.ptr.device)  # on the plan's stream
     (spgemm_batched if batched else spgemm_numeric)(plan, C, stream)
     plan.destroy()
     return C[0]

@@ -1,4 +1,10 @@
-"""Compile the HIP library for gfx950 (in-tree shared object, loaded via ctypes)."""
+"""Compile the HIP library for gfx950 (in-tree shared objects, loaded via ctypes).
+
+Two builds of the same source: ``libsgspgemm.so`` (the library) and
+``libsgspgemm_check.so`` (SG_CHECK=1: the same kernels plus invariant
+counters, read with sg_plan_check, for the test suite). They compile in
+parallel.
+"""
 import os
 import subprocess
 import sys
@@ -7,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "sg_spgemm.hip")
 LIB = os.path.join(HERE, "libsgspgemm.so")
+CHECK_LIB = os.path.join(HERE, "libsgspgemm_check.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -22,16 +29,24 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+def build(verbose: bool = False, check: bool = True) -> str:
+    jobs = [(LIB, [])]
+    if check:
+        jobs.append((CHECK_LIB, ["-DSG_CHECK=1"]))
+    procs = []
+    for out, extra in jobs:
+        tmp = out + ".tmp"
+        cmd = [HIPCC] + FLAGS + extra + ["-o", tmp, SRC]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((out, tmp, subprocess.Popen(cmd)))
+    for out, tmp, p in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, f"hipcc {out}")
+        os.replace(tmp, out)
     return LIB
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, check="--no-check" not in sys.argv)
     print(LIB)

@@ -23,6 +23,15 @@ constexpr int kWave = 64;
 constexpr int kXcds = 8;           // dies of an MI355X, each with its own L2
 constexpr int kMaxWaves = 16;  // 1024 threads per workgroup at most
 constexpr int kBlockMax = 1024;    // threads per workgroup of the mid/heavy/batched kernels
+// SG_CHECK=1 builds the invariant-checking variant of the library: every
+// persistent kernel verifies after each work item that its dynamic LDS is
+// back to all-zero bits, and every numeric tier compares the entries it
+// writes with the exact count the symbolic phase planned. Violations are
+// counted in the plan's counters (read with sg_plan_check); the arithmetic
+// and the results are those of the normal build.
+#ifndef SG_CHECK
+#define SG_CHECK 0
+#endif
 #ifndef SG_WAVES_PER_SIMD
 #define SG_WAVES_PER_SIMD 4
 #endif
@@ -124,7 +133,9 @@ enum Counter {
   kCtTierFlops,    // 3 entries: multiplications per tier
   kCtTierSent = kCtTierFlops + 3,  // 3 entries: streamed entries per tier
   kCtTierNnz = kCtTierSent + 3,    // 3 entries: output entries per tier
-  kCtNum = kCtTierNnz + 3
+  kCtChkLds = kCtTierNnz + 3,      // invariant-check build: items that left LDS non-zero
+  kCtChkCount,                     // invariant-check build: numeric counts that differ from the count pass
+  kCtNum
 };
 
 // Everything a numeric or count kernel reads, passed by value.
@@ -158,6 +169,7 @@ struct Plan {
   int32_t *rec_len;          //   their count
   void *rec_sv;              //   the entry's S value
   int64_t rec_cap;           // records the workspace holds
+  int64_t *chk;              // invariant-check counters (the plan's counters; written only by SG_CHECK builds)
   int32_t mid_cap;           // max entries of a mid-tier vector
   int32_t mid_kind;          // 0 bitmap-rank, 1 hash
   int32_t lds_words;         // dynamic LDS size in 32-bit words

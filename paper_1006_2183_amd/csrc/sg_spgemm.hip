@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -200,8 +201,11 @@ struct sg_plan {
   int64_t *nzpos = nullptr;
   int64_t *pbase = nullptr;
   OutDev *outs_dev = nullptr;
-  OutDev *outs_host = nullptr;  // pinned staging of the output table
-  int64_t *host_stats = nullptr;  // pinned
+  // host copies (pageable: the symbolic phase waits for its stream anyway,
+  // and a plan holds no pinned memory, whose release would synchronise the
+  // whole device)
+  std::vector<OutDev> outs_host;
+  std::vector<int64_t> host_stats;
   // optional kernel timing: events around [heavy, mid, tiny, pointers]
   bool profile = false;
   bool events_made = false;
@@ -231,6 +235,7 @@ struct Layout {
   int64_t *pbase;
   int64_t *part;
   uint32_t *hbits;
+  size_t tables_end;  // byte offset where the host-built tables end
   int32_t *vsent;
   int64_t *rcnt, *rbase;
   int64_t *rec_gi, *rec_gv;
@@ -379,10 +384,14 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   Layout L{};
   Carve c(ws);
   const int64_t nov = sh.nov_max;
+  // the host-built tables first, contiguous, so one copy uploads them
   L.prods = c.take<ProdDev>(nprod);
   L.groups = c.take<GroupDev>(ngroup);
-  L.outs = c.take<OutDev>(ngroup);
   L.vbase = c.take<int64_t>(nprod + 1);
+  L.dbase = c.take<int64_t>(ngroup + 1);
+  L.pbase = c.take<int64_t>(ngroup + 1);
+  L.tables_end = c.off;
+  L.outs = c.take<OutDev>(ngroup);
   L.counters = c.take<int64_t>(kCtNum + 24);
   L.gstat = c.take<int64_t>((int64_t)ngroup * kStCount);
   L.ov_id = c.take<int32_t>(nov);
@@ -429,7 +438,6 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
     }
   }
   int64_t scan_max = std::max<int64_t>(nov * sh.nrange + 1, sh.ndense + 1);
-  L.dbase = c.take<int64_t>(ngroup + 1);
   if (sh.dense_path) {
     L.dcnt = c.take<int64_t>(sh.ndense + 1);
     L.dflag = c.take<int64_t>(sh.ndense + 1);
@@ -439,7 +447,6 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   } else {
     L.dcnt = L.dflag = L.vpos = L.spos = L.dfill = nullptr;
   }
-  L.pbase = c.take<int64_t>(ngroup + 1);
   L.part = c.take<int64_t>(scan_max / kScanTile + 4);
   L.hbits = sh.nkeep > 0 ? c.take<uint32_t>(sh.nkeep * sh.hstride) : nullptr;
   if (sh.rec_cap > 0) {
@@ -689,9 +696,19 @@ struct RunItemRecs {
     return SG_OK;
   }
 };
+// The dynamic-LDS limit of the kernels is raised once per semiring and
+// process (to the largest budget any plan has asked for), not per plan.
 template <int K>
 struct RunAttr {
-  static sg_status run(int bytes) { return set_lds_attr<K>(bytes); }
+  static sg_status run(int bytes) {
+    static std::mutex mu;
+    static int done = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (bytes <= done) return SG_OK;
+    SG_TRY(set_lds_attr<K>(bytes));
+    done = bytes;
+    return SG_OK;
+  }
 };
 
 sg_status emit_outputs(sg_plan *pl, sg_mat_out *C, hipStream_t st) {
@@ -869,9 +886,8 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   pl->lds_mid_count = (pl->lds_mid_count + 15) & ~15;
   pl->lds_heavy_count = (pl->lds_heavy_count + 15) & ~15;
   pl->info.assign(ngroup, sg_sym_info{});
-  SG_HIP(hipHostMalloc((void **)&pl->outs_host, sizeof(OutDev) * ngroup, hipHostMallocDefault));
-  SG_HIP(hipHostMalloc((void **)&pl->host_stats, sizeof(int64_t) * ((size_t)ngroup * kStCount + kCtNum),
-                       hipHostMallocDefault));
+  pl->outs_host.assign(ngroup, OutDev{});
+  pl->host_stats.assign((size_t)ngroup * kStCount + kCtNum, 0);
   SG_TRY(dispatch<RunAttr>(sr->kind, std::max(t.lds_bytes, t.heavy_lds_bytes)));
 
   // host tables: products (ordered as given; output vectors follow group order)
@@ -924,11 +940,21 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     dbase[g + 1] = dbase[g] + sh.major[g];
     pbase[g + 1] = pbase[g] + sh.major[g] + 1;
   }
-  SG_HIP(hipMemcpyAsync(L.prods, prods.data(), sizeof(ProdDev) * nprod, hipMemcpyHostToDevice, st));
-  SG_HIP(hipMemcpyAsync(L.groups, groups.data(), sizeof(GroupDev) * ngroup, hipMemcpyHostToDevice, st));
-  SG_HIP(hipMemcpyAsync(L.vbase, vbase.data(), sizeof(int64_t) * (nprod + 1), hipMemcpyHostToDevice, st));
-  SG_HIP(hipMemcpyAsync(L.dbase, dbase.data(), sizeof(int64_t) * (ngroup + 1), hipMemcpyHostToDevice, st));
-  SG_HIP(hipMemcpyAsync(L.pbase, pbase.data(), sizeof(int64_t) * (ngroup + 1), hipMemcpyHostToDevice, st));
+  // one upload of the host-built tables, laid out as in the workspace; the
+  // image lives until the phase's closing stream synchronisation
+  std::vector<char> img(L.tables_end, 0);
+  {
+    char *base = (char *)ws;
+    auto put = [&](const void *dev, const void *src, size_t bytes) {
+      std::memcpy(img.data() + ((const char *)dev - base), src, bytes);
+    };
+    put(L.prods, prods.data(), sizeof(ProdDev) * nprod);
+    put(L.groups, groups.data(), sizeof(GroupDev) * ngroup);
+    put(L.vbase, vbase.data(), sizeof(int64_t) * (nprod + 1));
+    put(L.dbase, dbase.data(), sizeof(int64_t) * (ngroup + 1));
+    put(L.pbase, pbase.data(), sizeof(int64_t) * (ngroup + 1));
+    SG_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
+  }
   SG_TRY(fill64(L.counters, kCtNum + 24, 0, st));
   SG_TRY(fill64(L.gstat, (int64_t)ngroup * kStCount, 0, st));
   SG_TRY(fill64(L.ov_cnt, sh.nov_max + 1, 0, st));
@@ -1017,6 +1043,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   P.rec_len = L.rec_len;
   P.rec_sv = L.rec_sv;
   P.rec_cap = sh.rec_cap;
+  P.chk = L.counters;
   P.mid_cap = t.mid_max_ub;
   P.mid_kind = t.mid_kind;
   P.lds_words = t.lds_bytes / 4;
@@ -1076,15 +1103,15 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   SG_HIP(hipGetLastError());
   if (sh.rec_cap > 0) SG_TRY(dispatch<RunItemRecs>(sr->kind, P, pl->ncu, st));
 
-  SG_HIP(hipMemcpyAsync(pl->host_stats, L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount, hipMemcpyDeviceToHost,
-                        st));
-  SG_HIP(hipMemcpyAsync(pl->host_stats + (size_t)ngroup * kStCount, L.counters, sizeof(int64_t) * kCtNum,
+  SG_HIP(hipMemcpyAsync(pl->host_stats.data(), L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount,
+                        hipMemcpyDeviceToHost, st));
+  SG_HIP(hipMemcpyAsync(pl->host_stats.data() + (size_t)ngroup * kStCount, L.counters, sizeof(int64_t) * kCtNum,
                         hipMemcpyDeviceToHost, st));
   SG_HIP(hipStreamSynchronize(st));
 
-  const int64_t *cnt = pl->host_stats + (size_t)ngroup * kStCount;
+  const int64_t *cnt = pl->host_stats.data() + (size_t)ngroup * kStCount;
   for (int32_t g = 0; g < ngroup; ++g) {
-    const int64_t *s = pl->host_stats + (size_t)g * kStCount;
+    const int64_t *s = pl->host_stats.data() + (size_t)g * kStCount;
     sg_sym_info &I = pl->info[g];
     I.flops = s[kStFlops];
     I.nnz_ub = s[kStUb];
@@ -1150,11 +1177,20 @@ sg_status sg_plan_destroy(sg_plan *pl) {
   if (!pl) return SG_ERR_INVALID_ARG;
   if (pl->events_made)
     for (int i = 0; i < 8; ++i) (void)hipEventDestroy(pl->ev[i]);
-  if (pl->outs_host) (void)hipHostFree(pl->outs_host);
-  if (pl->host_stats) (void)hipHostFree(pl->host_stats);
   delete pl;
   return SG_OK;
 }
+
+sg_status sg_plan_check(sg_plan *pl, int64_t *out, int32_t n) {
+  if (!pl || !out || n < 0) return SG_ERR_INVALID_ARG;
+  int64_t h[2] = {0, 0};
+  SG_HIP(hipDeviceSynchronize());
+  SG_HIP(hipMemcpy(h, pl->counters + kCtChkLds, sizeof(h), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < n; ++i) out[i] = i < 2 ? h[i] : 0;
+  return SG_OK;
+}
+
+int32_t sg_build_checked(void) { return SG_CHECK; }
 
 sg_status sg_validate(const sg_mat *M, void *ws, void *stream) {
   if (!M || !ws) return SG_ERR_INVALID_ARG;

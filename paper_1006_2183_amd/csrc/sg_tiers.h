@@ -32,6 +32,23 @@
 
 namespace sg {
 
+// Invariant checks of the SG_CHECK build (no code in the normal build).
+// chk_lds_zero: called by every thread of a persistent workgroup between two
+// work items; counts the items after which the dynamic LDS is not all-zero.
+__device__ __forceinline__ void chk_lds_zero(const Plan &P, const uint32_t *lds) {
+  if constexpr (SG_CHECK) {
+    int bad = 0;
+    for (int i = threadIdx.x; i < P.lds_words; i += blockDim.x) bad |= lds[i] != 0u;
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicAdd((unsigned long long *)&P.chk[kCtChkLds], 1ull);
+  }
+}
+// chk_count: counts a numeric result whose entry count differs from the plan.
+__device__ __forceinline__ void chk_count(const Plan &P, bool bad) {
+  if constexpr (SG_CHECK) {
+    if (bad) atomicAdd((unsigned long long *)&P.chk[kCtChkCount], 1ull);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Accumulators take a product in two steps so that the LDS reads of several
 // products can be in flight together: prep(id) issues the reads one product
@@ -443,6 +460,7 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
     if (l == 0) P.ov_cnt[v] = __popcll(hm);
     return;
   }
+  chk_count(P, l == 0 && (int64_t)__popcll(hm) != gload(P.ov_cnt + v));
   if (tail) {
     const int r = __popcll(hm & ((1ull << l) - 1ull));
     const OutDev O = uload(P.outs + uload(P.ov_group + v));
@@ -568,6 +586,8 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
       if (COUNT) {
         if ((sel >> l) & 1ull) gstore(P.ov_cnt + v, (int64_t)__popcll(hm & lane_range(seg_a, Finc - bf)));
       } else {
+        chk_count(P, ((sel >> l) & 1ull) &&
+                         (int64_t)__popcll(hm & lane_range(seg_a, Finc - bf)) != gload(P.ov_cnt + v));
         const int src = tag < kWave ? tag : 0;
         const int a = __shfl(seg_a, src, kWave);
         const int64_t base = __shfl(opos, src, kWave);
@@ -692,7 +712,7 @@ __device__ __forceinline__ int64_t rank_load_kept(const uint32_t *src, int nwds,
 }
 
 template <int K, bool COUNT, bool WHOLE = false, bool RECS = false>
-__device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
+__device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
                             uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr, int64_t rb = -1,
                             int32_t nrec = 0) {
   typedef Sr<K> SR;
@@ -724,9 +744,9 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     // with their prefixes, without a marking pass; pattern only, the kept
     // bits are the result
     if (!SR::kVal) {
-      rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch, O.idx + out_pos, lo32);
+      const int64_t n = rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch, O.idx + out_pos, lo32);
       __syncthreads();
-      return;
+      return n;
     }
     cnt = rank_load_kept<WS>(kept + (lo >> 5), nwds, words, scratch);
     __syncthreads();
@@ -778,11 +798,11 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     if (COUNT) {
       if (tid == 0) gstore(P.ov_cnt + v, total);
       __syncthreads();
-      return;
+      return total;
     }
     if (!SR::kVal) {
       __syncthreads();
-      return;
+      return total;
     }
     cnt = total;
     __syncthreads();
@@ -806,7 +826,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
       for (int w = w0; w < w1; ++w) words[WS * w] = 0;
       if (tid == 0) gstore(P.ov_cnt + v, total);
       __syncthreads();
-      return;
+      return total;
     }
     if (!SR::kVal) {
       int64_t r = out_pos + excl;
@@ -821,7 +841,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
         words[w] = 0;
       }
       __syncthreads();
-      return;
+      return total;
     }
     {
       int run = (int)excl;
@@ -889,6 +909,7 @@ __device__ void rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, in
     ids[r] = 0;
   }
   __syncthreads();
+  return cnt;
 }
 
 // Mid tier, open-addressing hash in LDS (ids stored as id + 1, 0 = empty),
@@ -1130,11 +1151,32 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
   const int64_t lo = (int64_t)I.b0 * G.sw;
   const int64_t hi = (int64_t)I.b1 * G.sw < G.minor ? (int64_t)I.b1 * G.sw : G.minor;
   if (MODE != 2 && G.mode != MODE) return;
+  int64_t n;
   if (MODE == 0 || (MODE == 2 && G.mode == 0))
-    dense_window<K, false>(P, I.v, I.b0, lo, hi, I.pos, lds, scratch, (G.sw + 31) >> 5);
+    n = dense_window<K, false>(P, I.v, I.b0, lo, hi, I.pos, lds, scratch, (G.sw + 31) >> 5);
   else
-    rank_window<K, false, false, RECS>(P, I.v, lo, hi, I.b0, I.b1, I.pos, lds, scratch,
-                          I.q < P.nkeep ? P.hbits + I.q * P.hstride : nullptr, I.rbase, I.nrec);
+    n = rank_window<K, false, false, RECS>(P, I.v, lo, hi, I.b0, I.b1, I.pos, lds, scratch,
+                                           I.q < P.nkeep ? P.hbits + I.q * P.hstride : nullptr, I.rbase, I.nrec);
+  if constexpr (SG_CHECK) {
+    if (threadIdx.x == 0) {
+      const int32_t *bc = P.bcnt + (int64_t)I.q * P.nbmax;
+      int64_t want = 0;
+      for (int b = I.b0; b < I.b1; ++b) want += gload(bc + b);
+      chk_count(P, n != want);
+    }
+  }
+}
+
+// Numeric pass of one mid-tier vector (either accumulator).
+template <int K>
+__device__ void mid_item(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+  if (P.mid_kind == 0) {
+    const int64_t n = rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1,
+                                                  out_offset(P, v), lds, scratch);
+    chk_count(P, threadIdx.x == 0 && n != gload(P.ov_cnt + v));
+  } else {
+    mid_hash_vector<K, false>(P, v, lds, scratch);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1169,12 +1211,8 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_
     const int64_t i = uni(s_item);
     __syncthreads();
     if (i >= n) break;
-    const int64_t v = uload(P.mid_list + i);
-    if (P.mid_kind == 0)
-      rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds,
-                                  scratch);
-    else
-      mid_hash_vector<K, false>(P, v, lds, scratch);
+    mid_item<K>(P, uload(P.mid_list + i), lds, scratch);
+    chk_lds_zero(P, lds);
   }
 }
 
@@ -1215,6 +1253,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_heavy(Plan P, int6
       int64_t nxt = 0;
       if (threadIdx.x == 0) nxt = (int64_t)atomicAdd((unsigned long long *)&queue[x], 1ull);
       heavy_item<K, MODE, RECS>(P, i, lds, scratch);
+      chk_lds_zero(P, lds);
       if (threadIdx.x == 0) s_item = nxt;
       __syncthreads();
       i = lo + uni(s_item);
@@ -1245,6 +1284,7 @@ __global__ void __launch_bounds__(kBlockMax, kCountWavesPerSimd) k_mid_count(Pla
     const int64_t v = uload(P.mid_list + i);
     if (P.mid_kind == 0) rank_window<K, true, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, 0, lds, scratch);
     else mid_hash_vector<K, true>(P, v, lds, scratch);
+    chk_lds_zero(P, lds);
   }
 }
 
@@ -1268,6 +1308,7 @@ __global__ void __launch_bounds__(kBlockMax, heavy_count_waves<MODE>()) k_heavy_
     __syncthreads();
     if (i >= n) break;
     heavy_count<K, MODE>(P, i, lds, scratch);
+    chk_lds_zero(P, lds);
   }
 }
 
@@ -1294,13 +1335,12 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
     if (i < n_items) {
       heavy_item<K, MODE, RECS>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
-      const int64_t v = uload(P.mid_list + (i - n_items));
-      if (P.mid_kind == 0) rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1, out_offset(P, v), lds, scratch);
-      else mid_hash_vector<K, false>(P, v, lds, scratch);
+      mid_item<K>(P, uload(P.mid_list + (i - n_items)), lds, scratch);
     } else {
       const int64_t c0 = uni(((i - n_items - n_mid) * nw + threadIdx.x / kWave) * csz);
       if (c0 < n_tiny) tiny_pack<K, false>(P, c0, c0 + csz < n_tiny ? c0 + csz : n_tiny);
     }
+    chk_lds_zero(P, lds);
   }
 }
 

@@ -148,7 +148,8 @@ class GpuBatchExecutor:
     the batch, planned together and run as one persistent launch on one of
     `nstreams` streams (round robin)."""
 
-    def __init__(self, semiring: str, A, out_fmt: Optional[str] = None, tuning=None, nstreams: int = 2):
+    def __init__(self, semiring: str, A, out_fmt: Optional[str] = None, tuning=None, nstreams: int = 2,
+                 timing: bool = False):
         import torch
         from . import binding as B
         self.B = B
@@ -159,20 +160,31 @@ class GpuBatchExecutor:
         self.tuning = tuning
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.next = 0
+        self.timing = timing
+        self.intervals = []  # with timing: (stream index, start event, end event) per batch
 
     def launch(self, batch: Sequence[Request]):
         torch = self.torch
-        s = self.streams[self.next % len(self.streams)]
+        si = self.next % len(self.streams)
+        s = self.streams[si]
         self.next += 1
         n = len(batch)
         s.wait_stream(torch.cuda.current_stream())  # operands written on the caller's stream
         with torch.cuda.stream(s):
+            if self.timing:
+                t0 = torch.cuda.Event(enable_timing=True)
+                t0.record(s)
             plan = self.B.spgemm_symbolic(self.semiring, [self.A] * n, [r.X for r in batch], list(range(n)), n,
                                           out_fmt=self.out_fmt, tuning=self.tuning, stream=s)
             outs = plan.alloc_outputs(self.A.ptr.device)
             self.B.spgemm_batched(plan, outs, s)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=self.timing)
             ev.record(s)
+            if self.timing:
+                self.intervals.append((si, t0, ev))
+        # the handle is released at once (host only); the workspace tensor and the
+        # outputs stay referenced by the handle until the batch completes
+        plan.destroy()
         return (ev, plan, outs)
 
     def poll(self, handle) -> bool:
@@ -180,7 +192,6 @@ class GpuBatchExecutor:
 
     def finish(self, handle):
         ev, plan, outs = handle
-        plan.destroy()
         return outs
 
 

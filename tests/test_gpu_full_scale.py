@@ -1,7 +1,8 @@
 """GPU parity at the measured sizes, in the launch forms the benchmark times: the
-scale-24 SUMMA share (one persistent launch; sampled output columns against the
-oracle on the matching strips), the largest Galerkin instances (exact closed
-form) and the scale-20 served expansions (exact closed form for every column)."""
+scale-24 SUMMA share (fused persistent launch, partials then merge, graph
+replay; the whole output against the oracle on the matching strips), the
+largest Galerkin instances (exact closed form) and the scale-20 served
+expansions (exact closed form for every column)."""
 import sys
 
 import numpy as np
@@ -28,45 +29,68 @@ def sg():
     return sg
 
 
-def test_summa_share_scale24_sampled_columns(sg):
-    import torch
-    from paper_1006_2183_amd import batched as BT
-    sr, scale, grid = "plus_times_f64", 24, 64
-    _say("case SUMMA share scale 24, 64 stages")
-    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=sr, seed=24, device="cuda", fmt="dcsc")
-    b = (1 << scale) // grid
-    dA = [sg.DevMat.from_host(x, "cuda", sr) for x in a_blocks]
-    dB = [sg.DevMat.from_host(x, "cuda", sr) for x in b_blocks]
-    C = BT.summa_share(sr, dA, dB, batched=True).to_host()
-    torch.cuda.synchronize()
-    # oracle on sampled columns: the strip A(0, :) times the sampled columns of the strip A(:, 0)
-    present = np.unique(np.concatenate([x.vid for x in b_blocks]))
-    rng = np.random.default_rng(5)
-    cols = np.sort(rng.choice(present, 24, replace=False))
+def _strips(a_blocks, b_blocks, grid, b, sr):
+    """Host CSC of the strips A(I, :) (b x grid*b) and A(:, J) (grid*b x b) that the
+    stage blocks cut (input preparation for the oracle: C_IJ = A(I, :) A(:, J),
+    the block identity of Section 3.2)."""
     ra, ca, va, rb, cb, vb = [], [], [], [], [], []
     for k in range(grid):
         A, B = a_blocks[k], b_blocks[k]
         ra.append(A.idx.astype(np.int64)); va.append(A.val)
         ca.append(np.repeat(A.vid.astype(np.int64), np.diff(A.ptr)) + k * b)
-        bc = np.repeat(B.vid.astype(np.int64), np.diff(B.ptr))
-        m = np.isin(bc, cols)
-        rb.append(B.idx[m].astype(np.int64) + k * b); cb.append(np.searchsorted(cols, bc[m])); vb.append(B.val[m])
+        rb.append(B.idx.astype(np.int64) + k * b); vb.append(B.val)
+        cb.append(np.repeat(B.vid.astype(np.int64), np.diff(B.ptr)))
     SA = W.from_triples(np.concatenate(ra), np.concatenate(ca), np.concatenate(va), b, grid * b, "csc", sr)
-    SB = W.from_triples(np.concatenate(rb), np.concatenate(cb), np.concatenate(vb), grid * b, len(cols), "csc", sr)
-    R, _ = oracle.spgemm(sr, SA, SB)
-    where = {int(j): t for t, j in enumerate(C.vid)}
-    for t, j in enumerate(cols):
-        r_idx = R.idx[R.ptr[t]:R.ptr[t + 1]]
-        r_val = R.val[R.ptr[t]:R.ptr[t + 1]]
-        if r_idx.size == 0:  # every referenced A column empty: DCSC elides the column
-            assert int(j) not in where, f"column {j} should be elided"
-            continue
-        assert int(j) in where, f"column {j} missing"
-        u = where[int(j)]
-        g_idx = C.idx[C.ptr[u]:C.ptr[u + 1]]
-        g_val = C.val[C.ptr[u]:C.ptr[u + 1]]
-        assert np.array_equal(g_idx, r_idx), f"column {j} pattern"
-        assert np.all(np.abs(g_val - r_val) <= 1e-12 * np.abs(r_val)), f"column {j} values"
+    SB = W.from_triples(np.concatenate(rb), np.concatenate(cb), np.concatenate(vb), grid * b, b, "csc", sr)
+    return SA, SB
+
+
+def _assert_whole(C, R, what):
+    """Every column of the DCSC result C against the oracle's CSC result R: the same
+    stored columns (empty ones elided), ids bit-exact, values within 1e-12 relative."""
+    lens = np.diff(R.ptr)
+    nz = np.flatnonzero(lens)
+    assert np.array_equal(C.vid.astype(np.int64), nz), f"{what}: stored columns differ"
+    assert np.array_equal(np.diff(C.ptr), lens[nz]), f"{what}: column sizes differ"
+    assert np.array_equal(C.idx, R.idx), f"{what}: row ids differ"
+    err = np.abs(C.val - R.val)
+    bad = err > 1e-12 * np.abs(R.val)
+    assert not bad.any(), f"{what}: {int(bad.sum())} values beyond 1e-12"
+
+
+def test_summa_share_scale24_whole_output(sg):
+    """The whole scale-24 SUMMA share (process (0,0) of a 64 x 64 grid), in the three
+    forms the benchmark times (fused persistent launch, 64 partials then a 64-way
+    merge, graph replay of a plan with entry records), against the oracle's product
+    of the strips, column by column."""
+    import torch
+    from paper_1006_2183_amd import batched as BT
+    sr, scale, grid = "plus_times_f64", 24, 64
+    _say("case SUMMA share scale 24, 64 stages: generating")
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=sr, seed=24, device="cuda", fmt="dcsc")
+    b = (1 << scale) // grid
+    dA = [sg.DevMat.from_host(x, "cuda", sr) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", sr) for x in b_blocks]
+    _say("case SUMMA share scale 24: oracle on the strips")
+    SA, SB = _strips(a_blocks, b_blocks, grid, b, sr)
+    R, flops = oracle.spgemm_threads(sr, SA, SB)
+    _say(f"case SUMMA share scale 24: oracle done ({flops} multiplications, {R.nnz} entries); fused launch")
+    C = BT.summa_share(sr, dA, dB, batched=True).to_host()
+    _assert_whole(C, R, "fused")
+    _say("case SUMMA share scale 24: partials then merge")
+    parts = [sg.spgemm(sr, x, y, out_fmt="dcsc") for x, y in zip(dA, dB)]
+    C = BT.merge_partials(sr, parts).to_host()
+    del parts
+    _assert_whole(C, R, "partials+merge")
+    _say("case SUMMA share scale 24: graph replay with entry records")
+    plan = BT.summa_share_plan(sr, dA, dB, tuning=sg.make_tuning(sr, entry_mb=1024))
+    assert plan.infos[0]["flops"] == flops
+    G = BT.GraphedNumeric(plan)
+    for rep in range(2):
+        G.replay()
+        torch.cuda.synchronize()
+        _assert_whole(G.outputs[0].to_host(), R, f"graph replay {rep}")
+    plan.destroy()
 
 
 @pytest.mark.parametrize("n", [128, 96])

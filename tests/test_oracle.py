@@ -330,3 +330,17 @@ def test_formats_agree(semiring):
         assert_canonical(C)
         # the column-major runs accumulate in a different order than the row-major one
         assert_same(C, ref, semiring, 1e-12, f"{fa},{fb}")
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "plus_times_f32", "min_plus_i32", "or_and_bool"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "dcsr", "dcsc"])
+def test_threaded_driver_equals_serial(semiring, fmt):
+    """The threaded driver only distributes slices of the streamed vectors over
+    host threads: its output is bit-identical to the single-threaded oracle's."""
+    A = W.to_format(W.rmat_matrix(11, 8, semiring, "csr", seed=3), fmt, semiring)
+    C1, f1 = oracle.spgemm(semiring, A, A)
+    C2, f2 = oracle.spgemm_threads(semiring, A, A, threads=5, chunks_per_thread=3)
+    assert f1 == f2 and C1.fmt == C2.fmt and C1.nnz == C2.nnz
+    for k in ("ptr", "idx", "val", "vid"):
+        a, b = getattr(C1, k), getattr(C2, k)
+        assert (a is None and b is None) or np.array_equal(a, b), k

@@ -164,3 +164,41 @@ def test_gpu_alone_equals_mix():
             assert_same(mix, R, "or_and_bool")
     print(latency_stats(done), flush=True)
 
+
+
+@pytest.mark.gpu
+def test_gpu_two_batches_in_flight():
+    """Continuous batching overlaps batches on the device: a second batch is planned
+    and launched on the other stream while the first one's launch is still running
+    (its start event precedes the first batch's end event), and both results equal
+    the requests computed alone."""
+    import torch
+    import paper_1006_2183_amd as sg
+    from paper_1006_2183_amd.serve import GpuBatchExecutor
+    sg.load_library()
+    A = W.rmat_matrix(17, 16, "or_and_bool", "csc", seed=2)
+    dA = sg.DevMat.from_host(A, "cuda", "or_and_bool")
+    colcount = np.diff(A.ptr)
+    heavy = [W.bfs_frontier(A.nrows, 512, seed=300 + i, A=A, depth=1) for i in range(24)]
+    light = [W.bfs_frontier(A.nrows, 4, seed=400 + i) for i in range(4)]
+    mk = lambda i, X: Request(i, 0.0, sg.DevMat.from_host(X, "cuda", "or_and_bool"), frontier_bound(colcount, X))
+    b1 = [mk(i, X) for i, X in enumerate(heavy)]
+    b2 = [mk(100 + i, X) for i, X in enumerate(light)]
+    ex = GpuBatchExecutor("or_and_bool", dA, timing=True)
+    # warm-up (kernel loading, allocator)
+    ex.finish(ex.launch(b2))
+    torch.cuda.synchronize()
+    ex.intervals.clear()
+    h1 = ex.launch(b1)
+    h2 = ex.launch(b2)
+    torch.cuda.synchronize()
+    (s1, a1, e1), (s2, a2, e2) = ex.intervals
+    assert s1 != s2
+    gap = e1.elapsed_time(a2)  # negative: batch 2 started before batch 1 ended
+    print(f"batch 1 {a1.elapsed_time(e1):.3f} ms, batch 2 starts {gap:.3f} ms after batch 1 ends", flush=True)
+    assert gap < 0, "the second batch did not start while the first was in flight"
+    for h, reqs in ((h1, b1), (h2, b2)):
+        for r, Y in zip(reqs, ex.finish(h)):
+            alone = sg.spgemm("or_and_bool", dA, r.X).to_host()
+            Yh = Y.to_host()
+            assert np.array_equal(Yh.ptr, alone.ptr) and np.array_equal(Yh.idx, alone.idx)
