@@ -344,3 +344,82 @@ def test_threaded_driver_equals_serial(semiring, fmt):
     for k in ("ptr", "idx", "val", "vid"):
         a, b = getattr(C1, k), getattr(C2, k)
         assert (a is None and b is None) or np.array_equal(a, b), k
+
+
+# ---------------------------------------------------------------------------
+# format utilities (Sections 2.2-2.4): triples -> compressed with repeated
+# positions combined in list order, and format / orientation changes
+from oracle import convert as OC  # noqa: E402
+
+
+def _brute_coo(semiring, rows, cols, vals, nrows, ncols):
+    """Dense dictionary of positions, values combined in list order one by one."""
+    acc = {}
+    for i in range(len(rows)):
+        key = (int(rows[i]), int(cols[i]))
+        x = None if vals is None else vals[i]
+        if key not in acc:
+            acc[key] = x
+        elif semiring == "min_plus_i32":
+            acc[key] = min(acc[key], x)
+        elif x is not None:
+            acc[key] = acc[key] + x  # numpy scalar add in the value type
+    return acc
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "plus_times_f32", "min_plus_i32", "or_and_bool"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "dcsr", "dcsc"])
+def test_coo_to_compressed_brute_force(semiring, fmt):
+    rng = np.random.default_rng(11)
+    nrows, ncols, n = 13, 9, 400  # about 3.4 occurrences per position: long runs
+    rows = rng.integers(0, nrows, n)
+    cols = rng.integers(0, ncols, n)
+    vals = W.random_values(rng, n, semiring)
+    M = OC.coo_to_compressed(semiring, rows, cols, vals, nrows, ncols, fmt)
+    assert_canonical(M)
+    acc = _brute_coo(semiring, rows, cols, vals, nrows, ncols)
+    r, c, v = OC.triples(M)
+    assert len(r) == len(acc)
+    for k in range(len(r)):
+        want = acc[(int(r[k]), int(c[k]))]
+        if v is not None:
+            assert v[k] == want and v.dtype == want.dtype, (k, v[k], want)
+
+
+def test_coo_fold_order_is_left_to_right():
+    # 1 + 2^-53 + 2^-53 + ... : a left fold loses every small term, a pairwise sum keeps some
+    vals = np.array([1.0] + [2.0 ** -53] * 6)
+    M = OC.coo_to_compressed("plus_times_f64", np.zeros(7, np.int64), np.zeros(7, np.int64), vals, 1, 1, "csr")
+    assert M.val[0] == 1.0
+    M = OC.coo_to_compressed("plus_times_f64", np.zeros(7, np.int64), np.zeros(7, np.int64), vals[::-1].copy(), 1, 1,
+                             "csr")
+    assert M.val[0] == 1.0 + 6 * 2.0 ** -53
+
+
+def test_coo_to_compressed_matches_scipy_on_exact_values():
+    rng = np.random.default_rng(2)
+    rows = rng.integers(0, 300, 5000)
+    cols = rng.integers(0, 200, 5000)
+    vals = rng.integers(1, 9, 5000).astype(np.float64)  # small integers: every order sums exactly
+    M = OC.coo_to_compressed("plus_times_f64", rows, cols, vals, 300, 200, "csr")
+    S = sp.coo_matrix((vals, (rows, cols)), shape=(300, 200)).tocsr()
+    S.sum_duplicates()
+    S.sort_indices()
+    assert np.array_equal(M.ptr, S.indptr) and np.array_equal(M.idx, S.indices) and np.array_equal(M.val, S.data)
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32", "or_and_bool"])
+def test_convert_is_the_transpose_of_storage(semiring):
+    A = W.rmat_matrix(10, 8, semiring, "csr", seed=9)
+    S = sp.csr_matrix(((A.val if A.val is not None else np.ones(A.nnz)), A.idx, A.ptr), shape=(A.nrows, A.ncols))
+    for fmt in ("csc", "dcsc", "dcsr", "csr"):
+        B = OC.convert(semiring, A, fmt)
+        assert_canonical(B)
+        back = OC.convert(semiring, B, "csr")
+        assert np.array_equal(back.ptr, A.ptr) and np.array_equal(back.idx, A.idx)
+        if A.val is not None:
+            assert np.array_equal(back.val, A.val)
+    C = OC.convert(semiring, A, "csc")
+    T = S.T.tocsr()  # CSR of A^T holds the arrays of CSC of A
+    T.sort_indices()
+    assert np.array_equal(C.ptr, T.indptr) and np.array_equal(C.idx, T.indices)

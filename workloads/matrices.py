@@ -108,7 +108,8 @@ def random_values(rng: np.random.Generator, n: int, semiring: str):
 
 def from_triples(rows, cols, vals, nrows: int, ncols: int, fmt: str,
                  semiring: str = "plus_times_f64") -> SpMat:
-    """Canonical matrix from a triple list; duplicates combined in list order."""
+    """Canonical matrix from a triple list; duplicates combined in list order
+    (a left fold: ((v1 + v2) + v3) + ...)."""
     if fmt not in FORMATS:
         raise ValueError(f"unknown format {fmt}")
     rows = np.asarray(rows, dtype=np.int64)
@@ -138,14 +139,20 @@ def from_triples(rows, cols, vals, nrows: int, ncols: int, fmt: str,
         uval = None
     else:
         vs = np.asarray(vals, dtype=dt)[order]
-        if how == "sum":
-            uval = np.add.reduceat(vs, starts) if vs.size else vs
-        elif how == "min":
-            uval = np.minimum.reduceat(vs, starts) if vs.size else vs
+        if how in ("sum", "min"):
+            # left fold of each run of a repeated position, in list order
+            op = np.add if how == "sum" else np.minimum
+            uval = vs[starts].copy()
+            lens = np.diff(np.append(starts, vs.size))
+            live = np.flatnonzero(lens > 1)
+            k = 1
+            while live.size:
+                uval[live] = op(uval[live], vs[starts[live] + k])
+                k += 1
+                live = live[lens[live] > k]
+            uval = uval.astype(dt, copy=False)
         else:
             uval = None
-        if uval is not None:
-            uval = uval.astype(dt, copy=False)
     umaj = (ukey // minor_dim).astype(np.int64)
     umin = (ukey % minor_dim).astype(np.int32)
     if fmt in ("csr", "csc"):
