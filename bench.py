@@ -467,7 +467,12 @@ def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
 
 
 def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
-    """Served multi-source expansions Y = A X ((or, and)), Poisson arrivals; batched server vs FIFO."""
+    """Served multi-source expansions Y = A X ((or, and)), Poisson arrivals; batched server vs FIFO.
+
+    Requests arrive as host frontiers (one source per column); both servers build
+    the sparse operand on the device. The batched server concatenates a batch's
+    frontiers into one operand and runs one product per batch on two streams;
+    FIFO runs one plain product per request."""
     from paper_1006_2183_amd import serve as SV
     sr = "or_and_bool"
     log(f"[bench] serving: R-MAT scale {scale} bool resident, {count} requests per QPS level {qps_list}")
@@ -476,25 +481,25 @@ def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
     colcount = np.diff(A.ptr)
     rng = np.random.default_rng(seed + 100)
     ks = rng.integers(1, 513, size=count)
-    Xs, srcs = [], []
+    fronts, srcs = [], []
     for i, k in enumerate(ks):
-        X = W.bfs_frontier(A.nrows, int(k), seed=1000 + i)
-        Xs.append(X)
-        srcs.append(X.idx.astype(np.int64))  # depth 0: X(:, s) holds only source s
-    dX = [sg.DevMat.from_host(X, "cuda", sr) for X in Xs]
-    ubs = [SV.frontier_bound(colcount, X) for X in Xs]
+        src = np.random.default_rng(1000 + i).integers(0, A.nrows, size=int(k))
+        fronts.append(SV.Frontier.sources(src))
+        srcs.append(src.astype(np.int64))  # depth 0: X(:, s) holds only source s
+    ubs = [SV.frontier_bound(colcount, f) for f in fronts]
     out = {"workload": f"rmat_s{scale}_ef16_bool_csc_resident_bfs_depth0_k_U1_512", "requests": count,
            "request_flops_p50": float(np.percentile(ubs, 50)), "request_flops_p99": float(np.percentile(ubs, 99)),
+           "operand_build": "on the device from the request's host triples (sg_coo_compress / sg_coo_emit)",
            "levels": []}
     # warm both paths
-    SV.Scheduler(SV.GpuBatchExecutor(sr, dA), 1 << 26).run([SV.Request(0, 0.0, dX[0], ubs[0])])
-    SV.Scheduler(SV.FifoExecutor(sr, dA), 1 << 26).run([SV.Request(0, 0.0, dX[0], ubs[0])])
+    for ex in (SV.FrontierBatchExecutor(dA), SV.FrontierFifoExecutor(dA)):
+        SV.Scheduler(ex, 1 << 26).run([SV.Request(0, 0.0, fronts[0], ubs[0])])
     torch.cuda.synchronize()
 
     def check(done):
         # depth-0 closed form: Y(:, s) is the pattern of A(:, src_s)
         for r in done:
-            Y = r.result.to_host() if not isinstance(r.result, list) else r.result[0].to_host()
+            Y = (r.result[0] if isinstance(r.result, list) else r.result).to_host()
             src = srcs[r.rid]
             for s_ in range(len(src)):
                 ref = A.idx[A.ptr[src[s_]]:A.ptr[src[s_] + 1]]
@@ -504,8 +509,8 @@ def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
     for qps in qps_list:
         arr = W.poisson_arrivals(qps, count, seed=int(qps))
         line = {"qps": qps}
-        for name, ex, mb in (("batched", SV.GpuBatchExecutor(sr, dA), 64), ("fifo", SV.FifoExecutor(sr, dA), 1)):
-            reqs = [SV.Request(i, float(arr[i]), dX[i], ubs[i]) for i in range(count)]
+        for name, ex, mb in (("batched", SV.FrontierBatchExecutor(dA), 64), ("fifo", SV.FrontierFifoExecutor(dA), 1)):
+            reqs = [SV.Request(i, float(arr[i]), fronts[i], ubs[i]) for i in range(count)]
             sched = SV.Scheduler(ex, pool_entries=1 << 26, max_batch=mb, max_inflight=2 if mb > 1 else 1)
             done = sched.run(reqs)
             torch.cuda.synchronize()
@@ -518,18 +523,19 @@ def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
     out["exact"] = "every served column equals the pattern of A(:, src) (depth-0 closed form), both servers"
     import oracle
     import concurrent.futures as cf
+    hostX = [W.from_triples(f.rows, f.cols, None, A.nrows, f.k, "csc", sr) for f in fronts]
 
     def cpu_fn(th):
         if th == 1:
-            return None, sum(oracle.spgemm(sr, A, X)[1] for X in Xs)
+            return None, sum(oracle.spgemm(sr, A, X)[1] for X in hostX)
         with cf.ThreadPoolExecutor(max_workers=th) as ex:
-            return None, sum(f for _, f in ex.map(lambda X: oracle.spgemm(sr, A, X), Xs))
+            return None, sum(f for _, f in ex.map(lambda X: oracle.spgemm(sr, A, X), hostX))
 
     cb = cpu_rate(cpu_fn, f"all {count} requests Y = A X, one oracle call each (requests spread over the threads)")
     cb["requests_per_s"] = round(count / cb["seconds"]["all_cores"], 1)
     cb["requests_per_s_single_thread"] = round(count / cb["seconds"]["single_thread"], 1)
     out["cpu_baseline"] = cb
-    del dA, dX
+    del dA
     torch.cuda.empty_cache()
     return out
 

@@ -322,6 +322,55 @@ sg_status sg_validate(const sg_mat *M, void *ws, void *stream);
  */
 sg_status sg_build_aux(const sg_mat *M, int32_t *aux, int64_t *nchunks_out, void *stream);
 
+/*
+ * Format utilities on the device (Sections 2.2 and 2.3 define CSR/CSC and the
+ * doubly compressed DCSC/DCSR; Section 2.4 transposes an operand so that a
+ * row-major product runs column-wise).
+ *
+ * Triples -> compressed, in two calls that share `ws` (caller-owned device
+ * memory of sg_coo_workspace_size bytes; keep it and the triples unchanged
+ * between the calls):
+ *   sg_coo_compress  sorts the nnz triples (rows[i], cols[i], vals[i]) of an
+ *                    nrows x ncols matrix (device arrays; vals NULL for
+ *                    SG_OR_AND_BOOL) by (major, minor) of `fmt` with a stable
+ *                    radix sort, finds the distinct positions and returns, on
+ *                    the host after one stream synchronisation, *nnz_out
+ *                    (distinct positions) and *nvec_out (stored vectors of
+ *                    `fmt`: the major dimension for CSR/CSC, the non-empty
+ *                    vectors for DCSR/DCSC). INVALID_ARG if a triple lies
+ *                    outside the matrix.
+ *   sg_coo_emit      writes the canonical matrix into `out` (capacities at
+ *                    least nnz_out and, doubly compressed, nvec_out; pass the
+ *                    values sg_coo_compress returned). A position given
+ *                    several times is stored once, with its values combined
+ *                    by the semiring's add in list order (a left fold:
+ *                    ((v1 + v2) + v3) + ...; min for (min,+), or for bool).
+ *                    Asynchronous.
+ */
+sg_status sg_coo_workspace_size(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, int32_t fmt,
+                                size_t *ws_bytes);
+sg_status sg_coo_compress(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, const int32_t *rows,
+                          const int32_t *cols, const void *vals, int32_t fmt, void *ws, size_t ws_bytes,
+                          int64_t *nnz_out, int64_t *nvec_out, void *stream);
+sg_status sg_coo_emit(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, int32_t fmt, void *ws,
+                      size_t ws_bytes, int64_t nnz_out, int64_t nvec_out, sg_mat_out *out, void *stream);
+
+/*
+ * Format change of a canonical matrix M into `fmt` (any of the four, same
+ * matrix), written to `out` (capacity: M->nnz entries; doubly compressed
+ * output at least the number of non-empty vectors, e.g. min(nnz, major
+ * dimension)). Between orientations this is the transpose of the storage
+ * (CSC of M holds the arrays of CSR of M^T), by a stable sort on the minor
+ * ids, so every new vector comes out with ascending ids. `ws`: device memory
+ * of sg_convert_workspace_size bytes. *nvec_out (host, may be NULL) receives
+ * the stored vectors of the output; a doubly compressed output needs one
+ * stream synchronisation to learn it, otherwise the call is asynchronous.
+ * CAPACITY if `out` is too small.
+ */
+sg_status sg_convert_workspace_size(const sg_semiring *sr, const sg_mat *M, int32_t fmt, size_t *ws_bytes);
+sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *ws, size_t ws_bytes, sg_mat_out *out,
+                     int64_t *nvec_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,4 +21,6 @@ from .binding import (  # noqa: F401
     validate,
     build_aux,
     workspace_size,
+    coo_to_sparse,
+    convert,
 )

@@ -26,7 +26,8 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID_ARG", -2: "SG_ERR_DIM_MISMATCH", -3: "
 
 EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
            "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
-           "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked"]
+           "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked", "sg_coo_workspace_size",
+           "sg_coo_compress", "sg_coo_emit", "sg_convert_workspace_size", "sg_convert"]
 
 
 class SgError(RuntimeError):
@@ -137,6 +138,19 @@ def load_library(path: Optional[str] = None):
     lib.sg_plan_check.argtypes = [ctypes.c_void_p, P(ctypes.c_int64), ctypes.c_int32]
     lib.sg_build_checked.restype = ctypes.c_int32
     lib.sg_build_checked.argtypes = []
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    lib.sg_coo_workspace_size.restype = ctypes.c_int
+    lib.sg_coo_workspace_size.argtypes = [P(sg_semiring), i64, i64, i64, ctypes.c_int32, P(ctypes.c_size_t)]
+    lib.sg_coo_compress.restype = ctypes.c_int
+    lib.sg_coo_compress.argtypes = [P(sg_semiring), i64, i64, i64, vp, vp, vp, ctypes.c_int32, vp, ctypes.c_size_t,
+                                    P(i64), P(i64), vp]
+    lib.sg_coo_emit.restype = ctypes.c_int
+    lib.sg_coo_emit.argtypes = [P(sg_semiring), i64, i64, i64, ctypes.c_int32, vp, ctypes.c_size_t, i64, i64,
+                                P(sg_mat_out), vp]
+    lib.sg_convert_workspace_size.restype = ctypes.c_int
+    lib.sg_convert_workspace_size.argtypes = [P(sg_semiring), P(sg_mat), ctypes.c_int32, P(ctypes.c_size_t)]
+    lib.sg_convert.restype = ctypes.c_int
+    lib.sg_convert.argtypes = [P(sg_semiring), P(sg_mat), ctypes.c_int32, vp, ctypes.c_size_t, P(sg_mat_out), P(i64), vp]
     _libs[path] = lib
     if _lib is None:
         _lib = lib
@@ -462,3 +476,66 @@ def build_aux(M: DevMat, stream=None):
                                        _stream(stream)), "sg_build_aux")
     assert n.value == nchunks
     return aux
+
+
+def _new_mat(semiring, fmt, nrows, ncols, nnz, nvec, device):
+    torch = _torch()
+    vdt = _value_dtype(semiring)
+    major = nrows if fmt in ("csr", "dcsr") else ncols
+    doubly = fmt in ("dcsr", "dcsc")
+    ptr = torch.empty((nvec if doubly else major) + 1, dtype=torch.int64, device=device)
+    vid = torch.empty(nvec, dtype=torch.int32, device=device) if doubly else None
+    idx = torch.empty(nnz, dtype=torch.int32, device=device)
+    val = torch.empty(nnz, dtype=vdt, device=device) if vdt is not None else None
+    return DevMat(fmt, nrows, ncols, ptr, idx, val, vid)
+
+
+def coo_to_sparse(semiring: str, rows, cols, vals, nrows: int, ncols: int, fmt: str, stream=None) -> DevMat:
+    """Canonical `fmt` matrix of device triples (int32 rows/cols, values or None), built on
+    the device; repeated positions are combined with the semiring's add in list order."""
+    torch = _torch()
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    n = int(rows.numel())
+    sz = ctypes.c_size_t(0)
+    _check(lib.sg_coo_workspace_size(ctypes.byref(sr), nrows, ncols, n, FORMATS[fmt], ctypes.byref(sz)),
+           "sg_coo_workspace_size")
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=rows.device)
+    nnz, nvec = ctypes.c_int64(0), ctypes.c_int64(0)
+    vptr = vals.data_ptr() if vals is not None and vals.numel() else None
+    _check(lib.sg_coo_compress(ctypes.byref(sr), nrows, ncols, n, rows.data_ptr() if n else None,
+                               cols.data_ptr() if n else None, vptr, FORMATS[fmt], ws.data_ptr(), ws.numel(),
+                               ctypes.byref(nnz), ctypes.byref(nvec), _stream(stream)), "sg_coo_compress")
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        M = _new_mat(semiring, fmt, nrows, ncols, int(nnz.value), int(nvec.value), rows.device)
+    out = _out_descs([M])
+    _check(lib.sg_coo_emit(ctypes.byref(sr), nrows, ncols, n, FORMATS[fmt], ws.data_ptr(), ws.numel(), nnz.value,
+                           nvec.value, out, _stream(stream)), "sg_coo_emit")
+    M._keep = ws  # the workspace is released with the matrix (stream-ordered reuse)
+    return M
+
+
+def convert(semiring: str, M: DevMat, fmt: str, stream=None) -> DevMat:
+    """M in another format (device): the transpose of the storage between orientations."""
+    torch = _torch()
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    d = M.desc()
+    sz = ctypes.c_size_t(0)
+    _check(lib.sg_convert_workspace_size(ctypes.byref(sr), ctypes.byref(d), FORMATS[fmt], ctypes.byref(sz)),
+           "sg_convert_workspace_size")
+    major = M.nrows if fmt in ("csr", "dcsr") else M.ncols
+    cap_vec = min(M.nnz, major) if fmt in ("dcsr", "dcsc") else 0
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=M.ptr.device)
+        out = _new_mat(semiring, fmt, M.nrows, M.ncols, M.nnz, cap_vec, M.ptr.device)
+    desc = _out_descs([out])
+    nv = ctypes.c_int64(0)
+    _check(lib.sg_convert(ctypes.byref(sr), ctypes.byref(d), FORMATS[fmt], ws.data_ptr(), ws.numel(), desc,
+                          ctypes.byref(nv), _stream(stream)), "sg_convert")
+    if fmt in ("dcsr", "dcsc"):
+        out.vid = out.vid[: nv.value]
+        out.ptr = out.ptr[: nv.value + 1]
+    out._keep = ws
+    return out

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include "sg_device.h"
 #include "sg_symbolic.h"
 #include "sg_tiers.h"
+#include "sg_convert.h"
 
 using namespace sg;
 
@@ -235,7 +237,8 @@ struct Layout {
   int64_t *pbase;
   int64_t *part;
   uint32_t *hbits;
-  size_t tables_end;  // byte offset where the host-built tables end
+  size_t tables_end;   // byte offset where the host-built tables end
+  int64_t zero_words;  // int64 words from `counters` on that start at zero
   int32_t *vsent;
   int64_t *rcnt, *rbase;
   int64_t *rec_gi, *rec_gv;
@@ -392,15 +395,17 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.pbase = c.take<int64_t>(ngroup + 1);
   L.tables_end = c.off;
   L.outs = c.take<OutDev>(ngroup);
+  // arrays that start at zero, contiguous: one fill clears them
   L.counters = c.take<int64_t>(kCtNum + 24);
   L.gstat = c.take<int64_t>((int64_t)ngroup * kStCount);
+  L.ov_flops = c.take<int64_t>(nov);
+  L.ov_cnt = c.take<int64_t>(nov + 1);
+  L.zero_words = (int64_t)((c.off - ((char *)L.counters - c.base)) / sizeof(int64_t));
   L.ov_id = c.take<int32_t>(nov);
   L.ov_group = c.take<int32_t>(nov);
   L.seg_prod = c.take<int32_t>(sh.nseg_max);
   L.seg_svec = c.take<int32_t>(sh.nseg_max);
   L.ov_seg = c.take<int64_t>(nov + 1);
-  L.ov_flops = c.take<int64_t>(nov);
-  L.ov_cnt = c.take<int64_t>(nov + 1);
   L.ov_off = c.take<int64_t>(nov + 1);
   L.nzflag = c.take<int64_t>(nov + 1);
   L.nzpos = c.take<int64_t>(nov + 1);
@@ -474,9 +479,15 @@ sg_status fill64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
   return SG_OK;
 }
 
-// out[0..n] = exclusive scan of in[0..n), out[n] = total.
+// out[0..n] = exclusive scan of in[0..n), out[n] = total. Up to
+// kSmallScan elements take one single-workgroup launch, more three passes.
 sg_status scan64(const int64_t *in, int64_t n, int64_t *out, int64_t *part, hipStream_t st) {
   if (n <= 0) return fill64(out, 1, 0, st);
+  if (n <= kSmallScan) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, n, out);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+  }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, part);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, part, nb);
@@ -644,7 +655,11 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
     SG_TRY(mark(pl, 0, true, st));
     return SG_OK;
   }
-  const int64_t persist = resident_blocks(pl->ncu, nt, lds, kWavesPerSimd);
+  // as many workgroups as fit the chip, but no more than there are work items
+  // (a tiny chunk holds up to 64 vectors per wavefront), so a small plan does
+  // not hold every compute unit's LDS for the length of its launch
+  const int64_t work = I.n_heavy_items + I.n_mid + (I.n_tiny + (int64_t)kWave * (nt / kWave) - 1) / (kWave * (nt / kWave));
+  const int64_t persist = std::max<int64_t>(1, std::min(resident_blocks(pl->ncu, nt, lds, kWavesPerSimd), work));
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
   SG_TRY(mark(pl, 0, false, st));
   const int mode = pl->has_mode[0] && pl->has_mode[1] ? 2 : (pl->has_mode[1] ? 1 : 0);
@@ -955,10 +970,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     put(L.pbase, pbase.data(), sizeof(int64_t) * (ngroup + 1));
     SG_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
   }
-  SG_TRY(fill64(L.counters, kCtNum + 24, 0, st));
-  SG_TRY(fill64(L.gstat, (int64_t)ngroup * kStCount, 0, st));
-  SG_TRY(fill64(L.ov_cnt, sh.nov_max + 1, 0, st));
-  SG_TRY(fill64(L.ov_flops, sh.nov_max, 0, st));
+  SG_TRY(fill64(L.counters, L.zero_words, 0, st));  // counters, group statistics, flops and counts
 
   // AUX indexes of doubly compressed gathered operands
   for (int32_t q = 0; q < nprod; ++q) {
@@ -973,13 +985,13 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
 
   // output vectors and their segments
   if (!sh.dense_path) {
-    SG_TRY(fill64(L.counters + kCtNov, 1, sh.nov_max, st));
-    SG_TRY(fill64(L.counters + kCtNseg, 1, sh.nov_max, st));
-    SG_TRY(fill64(L.ov_seg, 1, 0, st));
-    if (sh.nov_max > 0) {
+    if (sh.nov_max > 0) {  // also sets the vector and segment counts and ov_seg[0]
       hipLaunchKernelGGL(k_ov_simple, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
-                         L.prods, L.vbase, nprod, sh.nov_max, L.ov_id, L.ov_group, L.ov_seg, L.seg_prod, L.seg_svec);
+                         L.prods, L.vbase, nprod, sh.nov_max, L.ov_id, L.ov_group, L.ov_seg, L.seg_prod, L.seg_svec,
+                         L.counters);
       SG_HIP(hipGetLastError());
+    } else {
+      SG_TRY(fill64(L.ov_seg, 1, 0, st));
     }
   } else {
     SG_TRY(fill64(L.dcnt, sh.ndense + 1, 0, st));
@@ -1220,6 +1232,357 @@ sg_status sg_build_aux(const sg_mat *M, int32_t *aux, int64_t *nchunks_out, void
   hipLaunchKernelGGL(k_build_aux, dim3((unsigned)grid_for(nchunks + 1, kFillThreads)), dim3(kFillThreads), 0,
                      (hipStream_t)stream, M->vid, M->nvec, chunk, nchunks, aux);
   SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Format utilities: stable radix sort, triples -> compressed, format change.
+namespace {
+
+int bits_for(uint64_t maxkey) {
+  int b = 0;
+  while (b < 64 && (maxkey >> b) != 0) ++b;
+  return b;
+}
+
+// Buffers of one radix sort: ping-pong keys, int32 payloads and values.
+struct SortBufs {
+  uint64_t *k[2];
+  int32_t *p[2];
+  char *v[2];
+  int64_t *hist, *hoff, *part;
+};
+
+int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+void carve_sort(Carve &c, int64_t n, int vb, bool pay, SortBufs &S) {
+  for (int i = 0; i < 2; ++i) {
+    S.k[i] = c.take<uint64_t>(n);
+    S.p[i] = pay ? c.take<int32_t>(n) : nullptr;
+    S.v[i] = vb ? c.take<char>(n * vb) : nullptr;
+  }
+  const int64_t nh = 256 * std::max<int64_t>(1, sort_tiles(n));
+  S.hist = c.take<int64_t>(nh);
+  S.hoff = c.take<int64_t>(nh + 1);
+  S.part = c.take<int64_t>(std::max<int64_t>(nh, n + 1) / kScanTile + 4);
+}
+
+template <int VB, bool PAY>
+void launch_scatter(const SortBufs &S, int src, int64_t n, int shift, int64_t nt, hipStream_t st) {
+  hipLaunchKernelGGL((k_radix_scatter<VB, PAY>), dim3((unsigned)nt), dim3(kSortThreads), 0, st, S.k[src], S.p[src],
+                     (const void *)S.v[src], n, shift, nt, S.hoff, S.k[1 - src], S.p[1 - src], (void *)S.v[1 - src]);
+}
+
+// Sorts S.k[0] (with S.p[0], S.v[0]) by the low `bits` bits, stably; the
+// result is in buffer `res`.
+sg_status radix_sort(const SortBufs &S, int vb, bool pay, int64_t n, int bits, hipStream_t st, int &res) {
+  res = 0;
+  if (n <= 1) return SG_OK;
+  const int passes = std::max(1, (bits + 7) / 8);
+  const int64_t nt = sort_tiles(n);
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kSortThreads), 0, st, S.k[res], n, shift, nt, S.hist);
+    SG_TRY(scan64(S.hist, 256 * nt, S.hoff, S.part, st));
+    if (vb == 8) pay ? launch_scatter<8, true>(S, res, n, shift, nt, st) : launch_scatter<8, false>(S, res, n, shift, nt, st);
+    else if (vb == 4) pay ? launch_scatter<4, true>(S, res, n, shift, nt, st) : launch_scatter<4, false>(S, res, n, shift, nt, st);
+    else pay ? launch_scatter<0, true>(S, res, n, shift, nt, st) : launch_scatter<0, false>(S, res, n, shift, nt, st);
+    SG_HIP(hipGetLastError());
+    res = 1 - res;
+  }
+  return SG_OK;
+}
+
+// Workspace of the triples -> compressed conversion.
+struct CooWs {
+  int64_t *bad;
+  SortBufs S;
+  int64_t *head, *vhead, *upos, *vpos, *cnt;
+  size_t bytes;
+};
+
+CooWs carve_coo(void *ws, int64_t n, int64_t major_dim, int vb) {
+  CooWs W{};
+  Carve c(ws);
+  W.bad = c.take<int64_t>(32);
+  carve_sort(c, n, vb, false, W.S);
+  W.head = c.take<int64_t>(n + 1);
+  W.vhead = c.take<int64_t>(n + 1);
+  W.upos = c.take<int64_t>(n + 1);
+  W.vpos = c.take<int64_t>(n + 1);
+  W.cnt = c.take<int64_t>(major_dim + 1);
+  W.bytes = c.off + 256;
+  return W;
+}
+
+sg_status coo_args(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, int32_t fmt) {
+  if (!sr || sr->kind < SG_PLUS_TIMES_F64 || sr->kind > SG_OR_AND_BOOL || !fmt_ok(fmt)) return SG_ERR_INVALID_ARG;
+  if (nrows < 0 || ncols < 0 || nnz < 0) return SG_ERR_INVALID_ARG;
+  if (nrows >= INT32_MAX || ncols >= INT32_MAX || nnz >= ((int64_t)1 << 40)) return SG_ERR_UNSUPPORTED;
+  return SG_OK;
+}
+
+template <int K>
+struct RunCooEmit {
+  static sg_status run(const CooWs &W, int res, int64_t n, uint64_t minor_dim, int32_t dbl, sg_mat_out *out,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((k_coo_emit<K>), dim3((unsigned)grid_for(n, kFillThreads)), dim3(kFillThreads), 0, st,
+                       W.S.k[res], (const void *)W.S.v[res], n, minor_dim, W.head, W.upos, W.vhead, W.vpos, dbl,
+                       out->idx, out->val, out->vid, out->ptr, W.cnt);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+  }
+};
+
+// Workspace of a format change.
+struct ConvWs {
+  SortBufs S;
+  int64_t *flag, *pos, *cnt;
+  size_t bytes;
+};
+
+ConvWs carve_conv(void *ws, int64_t nnz, int64_t nvec, int64_t out_major, int vb) {
+  ConvWs W{};
+  Carve c(ws);
+  carve_sort(c, nnz, vb, true, W.S);
+  const int64_t nf = std::max<int64_t>(nnz, nvec) + 1;
+  W.flag = c.take<int64_t>(nf);
+  W.pos = c.take<int64_t>(nf);
+  W.cnt = c.take<int64_t>(out_major + 1);
+  W.bytes = c.off + 256;
+  return W;
+}
+
+// Copy of the entries idx/val of M (starting at ptr[0], read on the device).
+__global__ void k_copy_entries(const int64_t *ptr, const int32_t *idx, const void *val, int64_t nnz, int vb,
+                               int32_t *idx_out, void *val_out) {
+  const int64_t e0 = gload(ptr);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
+    gstore(idx_out + i, gload(idx + e0 + i));
+    if (vb == 8) gstore((uint64_t *)val_out + i, gload((const uint64_t *)val + e0 + i));
+    if (vb == 4) gstore((uint32_t *)val_out + i, gload((const uint32_t *)val + e0 + i));
+  }
+}
+
+// ptr_out[t] = ptr[t] - ptr[0] for t in [0, n].
+__global__ void k_rebase_ptr(const int64_t *ptr, int64_t n, int64_t *ptr_out) {
+  const int64_t p0 = gload(ptr);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t <= n; t += (int64_t)gridDim.x * blockDim.x)
+    gstore(ptr_out + t, gload(ptr + t) - p0);
+}
+
+// Transpose input: keys, payloads and values of the entries, from ptr[0] on.
+__global__ void k_tr_values(const int64_t *ptr, const void *val, int64_t n, int vb, void *out) {
+  const int64_t e0 = gload(ptr);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (vb == 8) gstore((uint64_t *)out + i, gload((const uint64_t *)val + e0 + i));
+    if (vb == 4) gstore((uint32_t *)out + i, gload((const uint32_t *)val + e0 + i));
+  }
+}
+
+__global__ void k_tr_keys_at(const int64_t *ptr, const int32_t *vid, const int32_t *idx, int64_t nvec, int64_t n,
+                             uint64_t *keys, int32_t *pay) {
+  const int64_t e0 = gload(ptr);
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = vector_of(ptr, nvec, e0 + x);
+    gstore(keys + x, (uint64_t)(uint32_t)gload(idx + e0 + x));
+    gstore(pay + x, vid ? gload(vid + t) : (int32_t)t);
+  }
+}
+
+sg_status out_check(const sg_mat_out *out, int32_t fmt, int64_t nrows, int64_t ncols, int64_t nnz, int64_t nvec,
+                    int32_t kind) {
+  if (!out || out->fmt != fmt || out->nrows != nrows || out->ncols != ncols) return SG_ERR_INVALID_ARG;
+  if (out->cap_nnz < nnz) return SG_ERR_CAPACITY;
+  if (!out->ptr || (nnz > 0 && !out->idx) || (nnz > 0 && kind != SG_OR_AND_BOOL && !out->val)) return SG_ERR_INVALID_ARG;
+  if (doubly(fmt)) {
+    if (out->cap_vec < nvec) return SG_ERR_CAPACITY;
+    if (nvec > 0 && !out->vid) return SG_ERR_INVALID_ARG;
+  }
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_coo_workspace_size(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, int32_t fmt,
+                                size_t *ws_bytes) {
+  if (!ws_bytes) return SG_ERR_INVALID_ARG;
+  SG_TRY(coo_args(sr, nrows, ncols, nnz, fmt));
+  const int64_t major_dim = row_major(fmt) ? nrows : ncols;
+  *ws_bytes = carve_coo(nullptr, nnz, major_dim, slot_bytes(sr->kind)).bytes;
+  return SG_OK;
+}
+
+sg_status sg_coo_compress(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, const int32_t *rows,
+                          const int32_t *cols, const void *vals, int32_t fmt, void *ws, size_t ws_bytes,
+                          int64_t *nnz_out, int64_t *nvec_out, void *stream) {
+  SG_TRY(coo_args(sr, nrows, ncols, nnz, fmt));
+  if (!ws || !nnz_out || !nvec_out) return SG_ERR_INVALID_ARG;
+  if (nnz > 0 && (!rows || !cols || (sr->kind != SG_OR_AND_BOOL && !vals))) return SG_ERR_INVALID_ARG;
+  if (((uintptr_t)ws & 255) != 0) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const bool rm = row_major(fmt);
+  const int64_t major_dim = rm ? nrows : ncols, minor_dim = rm ? ncols : nrows;
+  const int vb = slot_bytes(sr->kind);
+  CooWs W = carve_coo(ws, nnz, major_dim, vb);
+  if (ws_bytes < W.bytes) return SG_ERR_WORKSPACE;
+  int64_t h[3] = {0, 0, 0};
+  if (nnz > 0) {
+    SG_TRY(fill64(W.bad, 1, 0, st));
+    hipLaunchKernelGGL(k_coo_keys, dim3((unsigned)grid_for(nnz, kFillThreads)), dim3(kFillThreads), 0, st, rows, cols,
+                       nnz, (int32_t)rm, nrows, ncols, W.S.k[0], W.bad);
+    if (vb) {
+      hipLaunchKernelGGL(k_copy_words, dim3((unsigned)grid_for(nnz * vb / 4, kFillThreads)), dim3(kFillThreads), 0, st,
+                         (const uint32_t *)vals, (uint32_t *)W.S.v[0], nnz * vb / 4);
+    }
+    SG_HIP(hipGetLastError());
+    int res = 0;
+    const uint64_t maxkey = (uint64_t)std::max<int64_t>(1, major_dim) * (uint64_t)std::max<int64_t>(1, minor_dim) - 1;
+    SG_TRY(radix_sort(W.S, vb, false, nnz, bits_for(maxkey), st, res));
+    hipLaunchKernelGGL(k_key_heads, dim3((unsigned)grid_for(nnz, kFillThreads)), dim3(kFillThreads), 0, st, W.S.k[res],
+                       nnz, (uint64_t)std::max<int64_t>(1, minor_dim), W.head, W.vhead);
+    SG_HIP(hipGetLastError());
+    SG_TRY(scan64(W.head, nnz, W.upos, W.S.part, st));
+    SG_TRY(scan64(W.vhead, nnz, W.vpos, W.S.part, st));
+    SG_HIP(hipMemcpyAsync(&h[0], W.bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipMemcpyAsync(&h[1], W.upos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipMemcpyAsync(&h[2], W.vpos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    if (h[0] != 0) return SG_ERR_INVALID_ARG;
+  }
+  *nnz_out = h[1];
+  *nvec_out = doubly(fmt) ? h[2] : major_dim;
+  return SG_OK;
+}
+
+sg_status sg_coo_emit(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, int32_t fmt, void *ws,
+                      size_t ws_bytes, int64_t nnz_out, int64_t nvec_out, sg_mat_out *out, void *stream) {
+  SG_TRY(coo_args(sr, nrows, ncols, nnz, fmt));
+  if (!ws) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const bool rm = row_major(fmt);
+  const int64_t major_dim = rm ? nrows : ncols, minor_dim = rm ? ncols : nrows;
+  const int vb = slot_bytes(sr->kind);
+  CooWs W = carve_coo(ws, nnz, major_dim, vb);
+  if (ws_bytes < W.bytes) return SG_ERR_WORKSPACE;
+  SG_TRY(out_check(out, fmt, nrows, ncols, nnz_out, nvec_out, sr->kind));
+  const int32_t dbl = doubly(fmt) ? 1 : 0;
+  if (!dbl) SG_TRY(fill64(W.cnt, major_dim + 1, 0, st));
+  if (nnz > 0) {
+    const int passes = nnz <= 1 ? 0 : std::max(1, (bits_for((uint64_t)std::max<int64_t>(1, major_dim) *
+                                                                (uint64_t)std::max<int64_t>(1, minor_dim) - 1) + 7) / 8);
+    const int res = passes & 1;
+    SG_TRY(dispatch<RunCooEmit>(sr->kind, W, res, nnz, (uint64_t)std::max<int64_t>(1, minor_dim), dbl, out, st));
+  }
+  if (dbl) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, out->ptr + nvec_out, nnz_out);
+  } else {
+    SG_TRY(scan64(W.cnt, major_dim, out->ptr, W.S.part, st));
+  }
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+sg_status sg_convert_workspace_size(const sg_semiring *sr, const sg_mat *M, int32_t fmt, size_t *ws_bytes) {
+  if (!sr || !M || !ws_bytes || !fmt_ok(fmt)) return SG_ERR_INVALID_ARG;
+  SG_TRY(check_mat(*M, sr->kind));
+  const int64_t out_major = row_major(fmt) ? M->nrows : M->ncols;
+  *ws_bytes = carve_conv(nullptr, M->nnz, M->nvec, out_major, slot_bytes(sr->kind)).bytes;
+  return SG_OK;
+}
+
+sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *ws, size_t ws_bytes, sg_mat_out *out,
+                     int64_t *nvec_out, void *stream) {
+  if (!sr || !M || !ws || !out || !fmt_ok(fmt)) return SG_ERR_INVALID_ARG;
+  SG_TRY(check_mat(*M, sr->kind));
+  if (((uintptr_t)ws & 255) != 0) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int vb = slot_bytes(sr->kind);
+  const int64_t nnz = M->nnz, nvec = M->nvec;
+  const bool same = row_major(fmt) == row_major(M->fmt);
+  const int64_t out_major = row_major(fmt) ? M->nrows : M->ncols;
+  ConvWs W = carve_conv(ws, nnz, nvec, out_major, vb);
+  if (ws_bytes < W.bytes) return SG_ERR_WORKSPACE;
+  const unsigned gE = (unsigned)grid_for(nnz, kFillThreads), gV = (unsigned)grid_for(nvec + 1, kFillThreads);
+  int64_t nv = out_major;
+  if (same) {
+    // one orientation: the entries keep their order; only the vector index changes
+    if (!doubly(M->fmt) && !doubly(fmt)) {
+      SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, 0, sr->kind));
+      hipLaunchKernelGGL(k_rebase_ptr, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, nvec, out->ptr);
+    } else if (doubly(M->fmt) && doubly(fmt)) {
+      SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, nvec, sr->kind));
+      hipLaunchKernelGGL(k_rebase_ptr, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, nvec, out->ptr);
+      if (nvec > 0)
+        hipLaunchKernelGGL(k_copy_words, dim3(gV), dim3(kFillThreads), 0, st, (const uint32_t *)M->vid,
+                           (uint32_t *)out->vid, nvec);
+      nv = nvec;
+    } else if (doubly(fmt)) {  // plain -> doubly: keep the non-empty vectors
+      hipLaunchKernelGGL(k_vec_nonempty, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, nvec, W.flag);
+      SG_TRY(scan64(W.flag, nvec, W.pos, W.S.part, st));
+      SG_HIP(hipMemcpyAsync(&nv, W.pos + nvec, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      SG_HIP(hipStreamSynchronize(st));
+      SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, nv, sr->kind));
+      hipLaunchKernelGGL(k_compress_ptr, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, nvec, W.flag, W.pos, out->vid,
+                         out->ptr);
+      hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, out->ptr + nv, nnz);
+    } else {  // doubly -> plain: pointers of every major id
+      SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, 0, sr->kind));
+      SG_TRY(fill64(W.cnt, out_major + 1, 0, st));
+      if (nvec > 0)
+        hipLaunchKernelGGL(k_vec_counts, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, M->vid, nvec, W.cnt);
+      SG_TRY(scan64(W.cnt, out_major, out->ptr, W.S.part, st));
+    }
+    if (nnz > 0)
+      hipLaunchKernelGGL(k_copy_entries, dim3(gE), dim3(kFillThreads), 0, st, M->ptr, M->idx, M->val, nnz, vb, out->idx,
+                         out->val);
+    SG_HIP(hipGetLastError());
+  } else {
+    // the other orientation: the storage of the transpose, by a stable sort on the minor id
+    int res = 0;
+    if (nnz > 0) {
+      hipLaunchKernelGGL(k_tr_keys_at, dim3(gE), dim3(kFillThreads), 0, st, M->ptr, doubly(M->fmt) ? M->vid : nullptr,
+                         M->idx, nvec, nnz, W.S.k[0], W.S.p[0]);
+      if (vb) hipLaunchKernelGGL(k_tr_values, dim3(gE), dim3(kFillThreads), 0, st, M->ptr, M->val, nnz, vb, W.S.v[0]);
+      SG_HIP(hipGetLastError());
+      SG_TRY(radix_sort(W.S, vb, true, nnz, bits_for((uint64_t)std::max<int64_t>(1, out_major) - 1), st, res));
+    }
+    if (doubly(fmt)) {
+      if (nnz > 0) {
+        hipLaunchKernelGGL(k_key_heads, dim3(gE), dim3(kFillThreads), 0, st, W.S.k[res], nnz, (uint64_t)1, W.flag,
+                           W.pos);  // W.pos: vector heads equal run heads here; overwritten by the scan
+        SG_TRY(scan64(W.flag, nnz, W.pos, W.S.part, st));
+        SG_HIP(hipMemcpyAsync(&nv, W.pos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+      } else {
+        nv = 0;
+      }
+      SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, nv, sr->kind));
+      if (nnz > 0)
+        hipLaunchKernelGGL(k_heads_to_doubly, dim3(gE), dim3(kFillThreads), 0, st, W.S.k[res], nnz, W.flag, W.pos,
+                           out->vid, out->ptr);
+      hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, out->ptr + nv, nnz);
+    } else {
+      SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, 0, sr->kind));
+      SG_TRY(fill64(W.cnt, out_major + 1, 0, st));
+      if (nnz > 0)
+        hipLaunchKernelGGL(k_key_counts, dim3(gE), dim3(kFillThreads), 0, st, W.S.k[res], nnz, W.cnt);
+      SG_TRY(scan64(W.cnt, out_major, out->ptr, W.S.part, st));
+    }
+    if (nnz > 0) {
+      hipLaunchKernelGGL(k_copy_words, dim3(gE), dim3(kFillThreads), 0, st, (const uint32_t *)W.S.p[res],
+                         (uint32_t *)out->idx, nnz);
+      if (vb)
+        hipLaunchKernelGGL(k_copy_words, dim3((unsigned)grid_for(nnz * vb / 4, kFillThreads)), dim3(kFillThreads), 0, st,
+                           (const uint32_t *)W.S.v[res], (uint32_t *)out->val, nnz * vb / 4);
+    }
+    SG_HIP(hipGetLastError());
+  }
+  if (nvec_out) *nvec_out = nv;
   return SG_OK;
 }
 

@@ -48,6 +48,27 @@ __global__ void __launch_bounds__(1024) k_scan_partials(int64_t *part, int64_t n
   if (threadIdx.x == 0) part[nb] = carry;
 }
 
+// Small scans in one launch: 1024 threads, each sums its run of consecutive
+// elements, one block-wide scan of the run totals, then each thread writes
+// its run (n <= kSmallScan).
+constexpr int64_t kSmallScan = 16384;
+__global__ void __launch_bounds__(1024) k_scan_small(const int64_t *in, int64_t n, int64_t *out) {
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  const int64_t per = (n + blockDim.x - 1) / blockDim.x;
+  const int64_t a = (int64_t)threadIdx.x * per < n ? (int64_t)threadIdx.x * per : n;
+  const int64_t b = a + per < n ? a + per : n;
+  int64_t s = 0;
+  for (int64_t i = a; i < b; ++i) s += in[i];
+  int64_t tot;
+  int64_t run = block_excl_scan(s, scratch, &tot);
+  for (int64_t i = a; i < b; ++i) {
+    const int64_t x = in[i];
+    out[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) out[n] = tot;
+}
+
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(const int64_t *in, int64_t n, const int64_t *part,
                                                            int64_t nb, int64_t *out) {
   __shared__ int64_t scratch[kMaxWaves + 1];
@@ -90,7 +111,12 @@ __global__ void k_build_aux(const int32_t *vid, int64_t nvec, int64_t chunk, int
 // Output vector v is stored vector t of product p's S, v = vbase[p] + t.
 __global__ void k_ov_simple(const ProdDev *prods, const int64_t *vbase, int32_t nprod, int64_t nov,
                             int32_t *ov_id, int32_t *ov_group, int64_t *ov_seg, int32_t *seg_prod,
-                            int32_t *seg_svec) {
+                            int32_t *seg_svec, int64_t *counters) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counters[kCtNov] = nov;
+    counters[kCtNseg] = nov;
+    ov_seg[0] = 0;
+  }
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nov; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t lo = 0, hi = nprod - 1;
     while (lo < hi) {  // last p with vbase[p] <= v

@@ -17,7 +17,10 @@ matrix, X_r a tall-skinny frontier, (or, and) semiring). The loop
   bytes and records latency (completion - arrival).
 
 ``FifoExecutor`` runs one request per launch in arrival order, the baseline.
-The scheduler is host-only logic; executors do the device work.
+``FrontierBatchExecutor`` / ``FrontierFifoExecutor`` take requests as they
+arrive from a client (host triples of the frontier) and build the sparse
+operand on the device. The scheduler is host-only logic; executors do the
+device work.
 """
 from __future__ import annotations
 
@@ -220,7 +223,123 @@ class FifoExecutor:
         return handle
 
 
+@dataclasses.dataclass
+class Frontier:
+    """A request's right operand as it arrives from the client: the n x k frontier
+    as host triples (row ids, column ids in [0, k)); pattern only. The servers
+    below build the compressed operand on the device from these."""
+    rows: np.ndarray
+    cols: np.ndarray
+    k: int
+
+    @classmethod
+    def sources(cls, src) -> "Frontier":
+        """One source per column (a breadth-first search's first frontier)."""
+        src = np.asarray(src, dtype=np.int32)
+        return cls(src, np.arange(src.size, dtype=np.int32), int(src.size))
+
+
+class ColumnSlice:
+    """Columns [c0, c1) of a column-major device result: one request's share of a
+    batched product. ``to_host`` returns them as an n x (c1 - c0) CSC matrix."""
+
+    def __init__(self, Y, c0: int, c1: int):
+        self.Y, self.c0, self.c1 = Y, int(c0), int(c1)
+
+    def to_host(self):
+        import types
+        ptr = self.Y.ptr[self.c0:self.c1 + 1].cpu().numpy()
+        a, b = int(ptr[0]), int(ptr[-1])
+        idx = self.Y.idx[a:b].cpu().numpy()
+        val = None if self.Y.val is None else self.Y.val[a:b].cpu().numpy()
+        return types.SimpleNamespace(fmt="csc", nrows=self.Y.nrows, ncols=self.c1 - self.c0, ptr=ptr - a, idx=idx,
+                                     val=val, vid=None)
+
+
+class FrontierBatchExecutor:
+    """Continuous batching of frontier requests Y_r = A X_r ((or, and)) against a
+    resident column-major A. A batch's frontiers are concatenated column-wise into
+    one triple list (one host-to-device copy), compressed ON THE DEVICE into one
+    CSC operand X = [X_1 | X_2 | ...] (sg_coo_compress / sg_coo_emit), and
+    multiplied in ONE product Y = A X (symbolic, then the persistent launch) on one
+    of `nstreams` streams; request r receives its columns of Y. The next batch is
+    planned on the other stream while this one computes."""
+
+    def __init__(self, A, nstreams: int = 2, tuning=None, timing: bool = False):
+        import torch
+        from . import binding as B
+        self.B, self.torch, self.A, self.tuning = B, torch, A, tuning
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.next = 0
+        self.timing = timing
+        self.intervals = []
+
+    def _build(self, fronts, s):
+        torch = self.torch
+        ks = [f.k for f in fronts]
+        off = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+        rows = np.concatenate([f.rows for f in fronts]).astype(np.int32)
+        cols = np.concatenate([f.cols.astype(np.int64) + off[i] for i, f in enumerate(fronts)]).astype(np.int32)
+        host = torch.from_numpy(np.concatenate([rows, cols])).pin_memory()
+        dev = host.to(self.A.ptr.device, non_blocking=True)  # one copy, ordered on stream s
+        n = rows.size
+        X = self.B.coo_to_sparse("or_and_bool", dev[:n], dev[n:], None, self.A.nrows, int(off[-1]), "csc", stream=s)
+        return X, off
+
+    def launch(self, batch: Sequence[Request]):
+        torch = self.torch
+        si = self.next % len(self.streams)
+        s = self.streams[si]
+        self.next += 1
+        with torch.cuda.stream(s):
+            if self.timing:
+                t0 = torch.cuda.Event(enable_timing=True)
+                t0.record(s)
+            X, off = self._build([r.X for r in batch], s)
+            plan = self.B.spgemm_symbolic("or_and_bool", [self.A], [X], out_fmt="csc", tuning=self.tuning, stream=s)
+            (Y,) = plan.alloc_outputs(self.A.ptr.device)
+            self.B.spgemm_batched(plan, [Y], s)
+            ev = torch.cuda.Event(enable_timing=self.timing)
+            ev.record(s)
+            if self.timing:
+                self.intervals.append((si, t0, ev))
+        plan.destroy()  # host only; X, Y and the workspace stay referenced until completion
+        return (ev, [ColumnSlice(Y, off[i], off[i + 1]) for i in range(len(batch))], (X, plan))
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle):
+        return handle[1]
+
+
+class FrontierFifoExecutor(FrontierBatchExecutor):
+    """Baseline: one request per plain product (device-built operand, symbolic,
+    per-tier numeric launches), completed before the next one starts."""
+
+    def __init__(self, A, tuning=None):
+        super().__init__(A, nstreams=1, tuning=tuning)
+
+    def launch(self, batch: Sequence[Request]):
+        out = []
+        s = self.torch.cuda.current_stream()
+        for r in batch:
+            X, _ = self._build([r.X], s)
+            Y = self.B.spgemm("or_and_bool", self.A, X, out_fmt="csc", stream=s)
+            out.append(ColumnSlice(Y, 0, r.X.k))
+        self.torch.cuda.synchronize()
+        return out
+
+    def poll(self, handle) -> bool:
+        return True
+
+    def finish(self, handle):
+        return handle
+
+
 def frontier_bound(colcount: np.ndarray, X) -> int:
     """Symbolic output bound of A X from a host copy of A's column counts:
-    sum over the stored entries (k, s) of X of nnz(A(:, k))."""
-    return int(colcount[np.asarray(X.idx, dtype=np.int64)].sum())
+    sum over the stored entries (k, s) of X of nnz(A(:, k)) (X a matrix or a
+    Frontier)."""
+    rows = X.rows if isinstance(X, Frontier) else X.idx
+    return int(colcount[np.asarray(rows, dtype=np.int64)].sum())

@@ -1,0 +1,129 @@
+"""GPU parity of the device format utilities (through the C ABI) against the
+oracle (``oracle.convert``) and the host input generator:
+
+* triples -> CSR/CSC/DCSR/DCSC with repeated positions combined by the
+  semiring's add in list order (bit-exact: the same left fold);
+* format changes of canonical matrices, including the transpose of the
+  storage between orientations (bit-exact: no arithmetic).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import convert as OC
+from tests.helpers import assert_canonical
+
+pytestmark = pytest.mark.gpu
+
+SEMIRINGS = ["plus_times_f64", "plus_times_f32", "min_plus_i32", "or_and_bool"]
+FMTS = ["csr", "csc", "dcsr", "dcsc"]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1006_2183_amd as sg
+    sg.load_library()
+    return sg
+
+
+def _dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x) if dtype is None else np.ascontiguousarray(x, dtype=dtype)).cuda()
+
+
+def _same_exact(G, R, what):
+    G = G.to_host()
+    assert G.fmt == R.fmt, what
+    assert_canonical(G)
+    assert np.array_equal(G.ptr, R.ptr), f"{what}: ptr"
+    assert np.array_equal(G.idx, R.idx), f"{what}: idx"
+    if R.vid is not None or G.vid is not None:
+        assert np.array_equal(G.vid, R.vid), f"{what}: vid"
+    if R.val is not None:
+        assert G.val.dtype == R.val.dtype and np.array_equal(G.val, R.val), f"{what}: values"
+
+
+def _coo_case(sg, semiring, rows, cols, vals, nrows, ncols, fmt, what):
+    vt = None if vals is None else _dev(vals)
+    G = sg.coo_to_sparse(semiring, _dev(rows, np.int32), _dev(cols, np.int32), vt, nrows, ncols, fmt)
+    R = OC.coo_to_compressed(semiring, rows, cols, vals, nrows, ncols, fmt)
+    _same_exact(G, R, what)
+    return G
+
+
+@pytest.mark.parametrize("semiring", SEMIRINGS)
+@pytest.mark.parametrize("fmt", FMTS)
+def test_coo_to_sparse_repeated_positions(sg, semiring, fmt):
+    _say(f"case coo {semiring} {fmt}")
+    rng = np.random.default_rng(3)
+    # few distinct positions, many repeats (long runs, list order matters for FP)
+    n = 20000
+    rows = rng.integers(0, 37, n)
+    cols = rng.integers(0, 23, n)
+    vals = W.random_values(rng, n, semiring)
+    _coo_case(sg, semiring, rows, cols, vals, 37, 23, fmt, "repeats")
+    # several tiles and radix passes: 2^16 x 2^16 positions, R-MAT edges (hub repeats)
+    r, c = W.rmat_edges(16, 8, seed=5)
+    r, c = r.numpy(), c.numpy()
+    v = W.random_values(rng, r.size, semiring)
+    _coo_case(sg, semiring, r, c, v, 1 << 16, 1 << 16, fmt, "rmat")
+    # hypersparse: a few triples in a huge matrix, and degenerate shapes
+    _coo_case(sg, semiring, np.array([5, 5, 70000]), np.array([9, 9, 3]),
+              W.random_values(rng, 3, semiring), 1 << 20, 1 << 17, fmt, "hypersparse")
+    _coo_case(sg, semiring, np.array([0]), np.array([0]), W.random_values(rng, 1, semiring), 1, 1, fmt, "1x1")
+    _coo_case(sg, semiring, np.zeros(0, np.int64), np.zeros(0, np.int64), W.random_values(rng, 0, semiring),
+              40, 30, fmt, "empty")
+
+
+@pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
+def test_coo_matches_host_generator(sg, semiring):
+    """The device build of an R-MAT matrix equals the host generator's (the same
+    triples, repeated positions folded in generation order)."""
+    _say(f"case coo vs generator {semiring}")
+    r, c = W.rmat_edges(14, 16, seed=2)
+    vals = W.matrices.random_values(np.random.default_rng(9), r.numel(), semiring)
+    for fmt in FMTS:
+        H = W.from_triples(r.numpy(), c.numpy(), vals, 1 << 14, 1 << 14, fmt, semiring)
+        G = sg.coo_to_sparse(semiring, _dev(r.numpy(), np.int32), _dev(c.numpy(), np.int32), _dev(vals),
+                             1 << 14, 1 << 14, fmt)
+        _same_exact(G, H, f"generator {fmt}")
+
+
+@pytest.mark.parametrize("semiring", SEMIRINGS)
+def test_convert_all_format_pairs(sg, semiring):
+    _say(f"case convert {semiring}")
+    A = W.rmat_matrix(13, 8, semiring, "csr", seed=12)
+    for src in FMTS:
+        M = W.to_format(A, src, semiring)
+        dM = sg.DevMat.from_host(M, "cuda", semiring)
+        for dst in FMTS:
+            G = sg.convert(semiring, dM, dst)
+            _same_exact(G, OC.convert(semiring, M, dst), f"{src}->{dst}")
+
+
+def test_convert_large_transpose_and_edges(sg):
+    sr = "plus_times_f64"
+    _say("case convert large transpose")
+    A = W.rmat_matrix(18, 16, sr, "csr", seed=1)
+    dA = sg.DevMat.from_host(A, "cuda", sr)
+    G = sg.convert(sr, dA, "csc")
+    _same_exact(G, OC.convert(sr, A, "csc"), "s18 csr->csc")
+    # transposing twice gives the operand back
+    back = sg.convert(sr, G, "csr")
+    _same_exact(back, A, "s18 round trip")
+    # rectangular with empty vectors and an all-empty matrix
+    R = W.random_sparse(300, 7, 0.05, sr, "csr", 4)
+    for dst in FMTS:
+        _same_exact(sg.convert(sr, sg.DevMat.from_host(R, "cuda", sr), dst), OC.convert(sr, R, dst), f"rect {dst}")
+    E = W.random_sparse(40, 30, 0.0, sr, "dcsc", 1)
+    for dst in FMTS:
+        _same_exact(sg.convert(sr, sg.DevMat.from_host(E, "cuda", sr), dst), OC.convert(sr, E, dst), f"empty {dst}")
