@@ -423,3 +423,38 @@ def test_convert_is_the_transpose_of_storage(semiring):
     T = S.T.tocsr()  # CSR of A^T holds the arrays of CSC of A
     T.sort_indices()
     assert np.array_equal(C.ptr, T.indptr) and np.array_equal(C.idx, T.indices)
+
+
+# ---------------------------------------------------------------------------
+# masked multi-level BFS (Section 6.2.2)
+from oracle import bfs as OB  # noqa: E402
+
+
+def test_bfs_levels_match_scipy_depths():
+    """Depth of every reached vertex equals scipy's BFS depth (from its
+    predecessor tree) on the graph whose edge k -> i is A(i, k)."""
+    from scipy.sparse import csgraph
+    A = W.rmat_matrix(10, 4, "or_and_bool", "csc", seed=13)
+    G = sp.csc_matrix((np.ones(A.nnz), A.idx, A.ptr), shape=(A.nrows, A.ncols))
+    src = [0, 5, 77, 1023]
+    lv = OB.bfs_levels(A, src)
+    for c, s in enumerate(src):
+        order, pred = csgraph.breadth_first_order(G.T.tocsr(), s, directed=True, return_predecessors=True)
+        depth = {int(s): 0}
+        for v in order[1:]:
+            depth[int(v)] = depth[int(pred[v])] + 1
+        mine = {int(v): d for d, L in enumerate(lv[c]) for v in L}
+        assert mine == depth
+
+
+def test_bfs_levels_on_a_path_and_a_cycle():
+    # path 0 -> 1 -> 2 -> 3 (A(i, k) = 1 for i = k + 1), and the cycle closing it
+    n = 4
+    P = W.from_triples(np.arange(1, n), np.arange(0, n - 1), None, n, n, "csc", "or_and_bool")
+    lv = OB.bfs_levels(P, [0, 2])
+    assert [list(x) for x in lv[0]] == [[0], [1], [2], [3]]
+    assert [list(x) for x in lv[1]] == [[2], [3]]
+    C = W.from_triples(np.array([1, 2, 3, 0]), np.array([0, 1, 2, 3]), None, n, n, "csc", "or_and_bool")
+    lv = OB.bfs_levels(C, [1])
+    assert [list(x) for x in lv[0]] == [[1], [2], [3], [0]]  # the cycle back to 1 is masked out
+    assert len(OB.bfs_levels(C, [1], max_levels=2)[0]) == 3
