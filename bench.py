@@ -540,6 +540,63 @@ def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
     return out
 
 
+def suite_bfs(sg, torch, W, count, qps_list, scale=20, seed=1, kmax=32, max_levels=3):
+    """Served masked multi-level BFS (Section 6.2.2): requests of k ~ U[1, kmax] random
+    sources, each searched to depth max_levels (frontier loop: one masked product per
+    level, visited bitmaps updated on the device). Iteration-level batching (every
+    iteration one grouped masked product over all active requests, at mixed depths)
+    against a FIFO server (one request at a time, one plain masked product per level)."""
+    from paper_1006_2183_amd import bfs as BF
+    import oracle.bfs as OB
+    sr = "or_and_bool"
+    log(f"[bench] BFS serving: R-MAT scale {scale} bool, {count} requests per QPS level {qps_list}")
+    A = W.rmat_matrix(scale, 16, sr, "csc", seed=seed, device="cuda")
+    dA = sg.DevMat.from_host(A, "cuda", sr)
+    rng = np.random.default_rng(seed + 200)
+    ks = rng.integers(1, kmax + 1, size=count)
+    srcs = [np.random.default_rng(3000 + i).integers(0, A.nrows, size=int(k)) for i, k in enumerate(ks)]
+    out = {"workload": f"rmat_s{scale}_ef16_bool_csc_masked_bfs_k_U1_{kmax}_depth{max_levels}", "requests": count,
+           "levels": []}
+    # warm-up
+    BF.BfsServer(dA).run([BF.BfsRequest(0, 0.0, srcs[0], max_levels)])
+    torch.cuda.synchronize()
+    checked = 0
+    for qps in qps_list:
+        arr = W.poisson_arrivals(qps, count, seed=int(qps) + 1)
+        line = {"qps": qps}
+        for name, batched in (("batched", True), ("fifo", False)):
+            reqs = [BF.BfsRequest(i, float(arr[i]), srcs[i], max_levels) for i in range(count)]
+            srv = BF.BfsServer(dA, pool_bytes=16 << 30, max_active=64, batched=batched)
+            done = srv.run(reqs)
+            torch.cuda.synchronize()
+            st = BF.bfs_latency(done)
+            line[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            line[name]["iterations"] = srv.iterations
+            if batched:
+                mixes = [len(m) for m in srv.mix]
+                line[name]["active_per_iteration_mean"] = round(float(np.mean([sum(m.values()) for m in srv.mix])), 2)
+                line[name]["iterations_with_mixed_depths"] = int(sum(1 for x in mixes if x > 1))
+            # the first few requests of the run, level by level, against the oracle's BFS
+            for r in sorted(done, key=lambda r: r.rid)[:3]:
+                want = OB.bfs_levels(A, r.sources, max_levels=max_levels)
+                got = [Y.to_host() for Y in r.levels]
+                if len(got) != max(len(w) for w in want):
+                    raise AssertionError(f"BFS request {r.rid}: depth differs")
+                for d, Y in enumerate(got):
+                    for c in range(len(r.sources)):
+                        exp = want[c][d] if d < len(want[c]) else np.zeros(0, np.int64)
+                        if not np.array_equal(Y.idx[Y.ptr[c]:Y.ptr[c + 1]], exp):
+                            raise AssertionError(f"BFS request {r.rid} level {d} column {c} differs from the oracle")
+                checked += 1
+            log(f"[bench] BFS qps {qps} {name}: {line[name]}")
+            del done, reqs
+        out["levels"].append(line)
+    out["exact"] = f"{checked} served requests checked level by level against the oracle's BFS (bit-exact)"
+    del dA
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Counter ingestion: HBM bytes per launch from rocprofv3 --pmc passes
 
@@ -607,10 +664,12 @@ def main():
     ap.add_argument("--no-suite", action="store_true",
                     help="skip the batched (SUMMA share, Galerkin) and served measurements")
     ap.add_argument("--suite-reps", type=int, default=3)
-    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving"], default=None,
+    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving", "bfs"], default=None,
                     help="run one of the batched/served measurements alone and print its JSON object")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-qps", default="500,2000,8000")
+    ap.add_argument("--bfs-requests", type=int, default=120)
+    ap.add_argument("--bfs-qps", default="50,200")
     ap.add_argument("--ingest-counters", default=None,
                     help="directory holding fetch/, write/, cal_fetch/, cal_write/ rocprofv3 --pmc outputs: "
                          "write the measured HBM bytes per heavy launch to profiles/hbm_traffic.json and exit")
@@ -653,7 +712,9 @@ def main():
               "summa": ("batched_summa", lambda: suite_summa(sg, torch, W, args.suite_reps)),
               "galerkin": ("batched_galerkin", lambda: suite_galerkin(sg, torch, W, args.suite_reps)),
               "serving": ("serving", lambda: suite_serve(sg, torch, W, args.serve_requests,
-                                                         [float(q) for q in args.serve_qps.split(",")]))}
+                                                         [float(q) for q in args.serve_qps.split(",")])),
+              "bfs": ("served_bfs", lambda: suite_bfs(sg, torch, W, args.bfs_requests,
+                                                      [float(q) for q in args.bfs_qps.split(",")]))}
     if args.only:
         print(json.dumps({suites[args.only][0]: suites[args.only][1]()}), flush=True)
         return

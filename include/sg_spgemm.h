@@ -250,6 +250,48 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod,
                              sg_sym_info *info, void *stream);
 
 /*
+ * Output mask of one group (Section 6.2.2's breadth-first search removes the
+ * vertices already visited from each new frontier). bits is a DEVICE bitmap:
+ * bit (i, j) for output vector j (the major id: a column of column-major C)
+ * and output id i is bit i % 32 of bits[j * stride_words + i / 32];
+ * stride_words >= ceil(minor dimension / 32). complement = 1 keeps only the
+ * entries whose bit is 0 (C = (A B) with the set positions removed),
+ * complement = 0 only those whose bit is 1. bits == NULL: no mask.
+ */
+typedef struct {
+    const uint32_t *bits;
+    int64_t stride_words;
+    int32_t complement;
+    int32_t pad;
+} sg_mask;
+
+/*
+ * sg_spgemm_symbolic with an output mask per group (host array masks[ngroup]
+ * of descriptors; NULL = no masks). Every phase applies the mask: the exact
+ * sizes count only the kept entries, and the numeric phase writes only
+ * those. The bitmaps are read by the symbolic call and by every later
+ * numeric call of the plan, so they must stay unchanged (and alive) until the
+ * last numeric call has completed. The flops and nnz_ub of sg_sym_info stay
+ * those of the unmasked product. Errors: as sg_spgemm_symbolic, and
+ * INVALID_ARG for a stride below ceil(minor / 32).
+ */
+sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod,
+                                    const sg_mat *A, const sg_mat *B,
+                                    const int32_t *group, int32_t ngroup,
+                                    int32_t out_fmt, const sg_mask *masks,
+                                    const sg_tuning *tuning, void *ws,
+                                    size_t ws_bytes, sg_plan **plan,
+                                    sg_sym_info *info, void *stream);
+
+/*
+ * Mask update (a BFS's "visited |= new frontier"): for each of the n
+ * matrices M[k] (host array of descriptors of device data) sets bit (i, j) of
+ * masks[k] for every stored entry i of M[k]'s vector j, with atomic ORs on
+ * the device. One launch per 16 matrices; asynchronous.
+ */
+sg_status sg_mask_set(int32_t n, const sg_mat *M, const sg_mask *masks, void *stream);
+
+/*
  * Numeric phase: writes every C_g (host array C[ngroup] of descriptors of
  * caller-allocated device arrays with capacities >= info[g].nnz / .nvec).
  * Stream-ordered and asynchronous, with one kernel launch per tier. Output

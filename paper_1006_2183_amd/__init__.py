@@ -23,4 +23,6 @@ from .binding import (  # noqa: F401
     workspace_size,
     coo_to_sparse,
     convert,
+    Mask,
+    mask_set,
 )

@@ -27,7 +27,8 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID_ARG", -2: "SG_ERR_DIM_MISMATCH", -3: "
 EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_workspace_size", "sg_spgemm_symbolic",
            "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
            "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked", "sg_coo_workspace_size",
-           "sg_coo_compress", "sg_coo_emit", "sg_convert_workspace_size", "sg_convert"]
+           "sg_coo_compress", "sg_coo_emit", "sg_convert_workspace_size", "sg_convert", "sg_spgemm_symbolic_masked",
+           "sg_mask_set"]
 
 
 class SgError(RuntimeError):
@@ -53,6 +54,11 @@ class sg_mat_out(ctypes.Structure):
     _fields_ = [("fmt", ctypes.c_int32), ("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("cap_nnz", ctypes.c_int64), ("cap_vec", ctypes.c_int64), ("ptr", ctypes.c_void_p),
                 ("vid", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class sg_mask(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("stride_words", ctypes.c_int64), ("complement", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class sg_tuning(ctypes.Structure):
@@ -149,6 +155,12 @@ def load_library(path: Optional[str] = None):
                                 P(sg_mat_out), vp]
     lib.sg_convert_workspace_size.restype = ctypes.c_int
     lib.sg_convert_workspace_size.argtypes = [P(sg_semiring), P(sg_mat), ctypes.c_int32, P(ctypes.c_size_t)]
+    lib.sg_spgemm_symbolic_masked.restype = ctypes.c_int
+    lib.sg_spgemm_symbolic_masked.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_int32, P(sg_mask), P(sg_tuning), ctypes.c_void_p,
+                                              ctypes.c_size_t, P(ctypes.c_void_p), P(sg_sym_info), ctypes.c_void_p]
+    lib.sg_mask_set.restype = ctypes.c_int
+    lib.sg_mask_set.argtypes = [ctypes.c_int32, P(sg_mat), P(sg_mask), ctypes.c_void_p]
     lib.sg_convert.restype = ctypes.c_int
     lib.sg_convert.argtypes = [P(sg_semiring), P(sg_mat), ctypes.c_int32, vp, ctypes.c_size_t, P(sg_mat_out), P(i64), vp]
     _libs[path] = lib
@@ -391,10 +403,38 @@ def _groups(group, ngroup, nprod):
     return ctypes.cast(arr, ctypes.c_void_p), int(ngroup if ngroup is not None else max(group) + 1)
 
 
+class Mask:
+    """An output mask: a device int32/uint32 tensor of stride_words words per output
+    vector (bit i % 32 of word [j, i / 32] for output id i of vector j);
+    complement=True keeps the entries whose bit is clear."""
+
+    def __init__(self, bits, stride_words: int, complement: bool = True):
+        self.bits, self.stride_words, self.complement = bits, int(stride_words), bool(complement)
+
+    @classmethod
+    def zeros(cls, nvec: int, minor: int, device="cuda", complement: bool = True) -> "Mask":
+        torch = _torch()
+        stride = (int(minor) + 31) // 32
+        return cls(torch.zeros(int(nvec) * stride, dtype=torch.int32, device=device), stride, complement)
+
+    def desc(self) -> sg_mask:
+        return sg_mask(self.bits.data_ptr(), self.stride_words, 1 if self.complement else 0, 0)
+
+
+def mask_set(Ms: Sequence[DevMat], masks: Sequence[Mask], stream=None):
+    """Set the bits of every stored entry of Ms[k] in masks[k] (on the device)."""
+    if not Ms:
+        return
+    arr = _descs(Ms)
+    marr = (sg_mask * len(masks))(*[m.desc() for m in masks])
+    _check(load_library().sg_mask_set(len(Ms), arr, marr, _stream(stream)), "sg_mask_set")
+
+
 def spgemm_symbolic(semiring: str, As: Sequence[DevMat], Bs: Sequence[DevMat], group=None, ngroup=None,
                     out_fmt: Optional[str] = None, tuning: Optional[sg_tuning] = None, stream=None,
-                    ws=None) -> Plan:
-    """Symbolic phase (sizes, tiers, exact counts) of C_g = sum over group g of A_p B_p."""
+                    ws=None, masks: Optional[Sequence[Optional[Mask]]] = None) -> Plan:
+    """Symbolic phase (sizes, tiers, exact counts) of C_g = sum over group g of A_p B_p
+    (with masks[g] applied to C_g when given)."""
     torch = _torch()
     lib = load_library()
     sr = sg_semiring(SEMIRINGS[semiring])
@@ -413,9 +453,16 @@ def spgemm_symbolic(semiring: str, As: Sequence[DevMat], Bs: Sequence[DevMat], g
             ws = torch.empty(int(sz.value), dtype=torch.uint8, device=As[0].ptr.device)
     handle = ctypes.c_void_p(0)
     infos = (sg_sym_info * ng)()
-    _check(lib.sg_spgemm_symbolic(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], tptr,
-                                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ctypes.byref(handle),
-                                  infos, _stream(stream)), "sg_spgemm_symbolic")
+    if masks is None:
+        _check(lib.sg_spgemm_symbolic(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], tptr,
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                      ctypes.byref(handle), infos, _stream(stream)), "sg_spgemm_symbolic")
+    else:
+        marr = (sg_mask * ng)(*[(m.desc() if m is not None else sg_mask(None, 0, 0, 0)) for m in masks])
+        _check(lib.sg_spgemm_symbolic_masked(ctypes.byref(sr), len(As), A, B, garr, ng, FORMATS[out_fmt], marr, tptr,
+                                             ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                             ctypes.byref(handle), infos, _stream(stream)),
+               "sg_spgemm_symbolic_masked")
     glist = None if group is None else [int(x) for x in group]
     return Plan(semiring, As, Bs, glist, ng, out_fmt, tuning, handle, ws, [infos[i].as_dict() for i in range(ng)],
                 stream)

@@ -75,7 +75,22 @@ struct GroupDev {
   int64_t ov_end;
   int64_t nnz_base;      // global exclusive offset of the group's first entry
   int64_t nz_base;       // global count of non-empty vectors before the group
+  // optional output mask: bit (i, j) of output vector j (its major id) and
+  // output id i at mask[j * mask_stride + i / 32], bit i % 32; an entry is
+  // kept where the bit is 0 (mask_comp = 1, e.g. not yet visited) or 1
+  const uint32_t *mask;  // null: every entry is kept
+  int64_t mask_stride;   // 32-bit words per output vector
+  int32_t mask_comp;
+  int32_t mask_pad;
 };
+
+// Mask word w (ids 32 w .. 32 w + 31) of output vector j: the bits of the ids
+// the output keeps (all ones when the group has no mask).
+__device__ __forceinline__ uint32_t keep_word(const uint32_t *mask, int64_t stride, int32_t comp, int64_t j, int64_t w) {
+  if (mask == nullptr) return ~0u;
+  const uint32_t m = *(const __attribute__((address_space(1))) uint32_t *)(mask + j * stride + w);
+  return comp ? ~m : m;
+}
 
 // One heavy-tier item: the window of split buckets [b0, b1) of output
 // vector v (position q in the heavy list) of group g, whose entries start at

@@ -236,6 +236,7 @@ struct Layout {
   int64_t *dbase, *dcnt, *dflag, *vpos, *spos, *dfill;
   int64_t *pbase;
   int64_t *part;
+  int64_t part_cap;
   uint32_t *hbits;
   size_t tables_end;   // byte offset where the host-built tables end
   int64_t zero_words;  // int64 words from `counters` on that start at zero
@@ -452,7 +453,8 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   } else {
     L.dcnt = L.dflag = L.vpos = L.spos = L.dfill = nullptr;
   }
-  L.part = c.take<int64_t>(scan_max / kScanTile + 4);
+  L.part_cap = scan_max / kScanTile + 4;
+  L.part = c.take<int64_t>(L.part_cap);
   L.hbits = sh.nkeep > 0 ? c.take<uint32_t>(sh.nkeep * sh.hstride) : nullptr;
   if (sh.rec_cap > 0) {
     L.vsent = c.take<int32_t>(nov + 1);
@@ -481,7 +483,8 @@ sg_status fill64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
 
 // out[0..n] = exclusive scan of in[0..n), out[n] = total. Up to
 // kSmallScan elements take one single-workgroup launch, more three passes.
-sg_status scan64(const int64_t *in, int64_t n, int64_t *out, int64_t *part, hipStream_t st) {
+// `part` holds part_cap entries (n / kScanTile + 2 are needed).
+sg_status scan64(const int64_t *in, int64_t n, int64_t *out, int64_t *part, int64_t part_cap, hipStream_t st) {
   if (n <= 0) return fill64(out, 1, 0, st);
   if (n <= kSmallScan) {
     hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, n, out);
@@ -489,6 +492,11 @@ sg_status scan64(const int64_t *in, int64_t n, int64_t *out, int64_t *part, hipS
     return SG_OK;
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb + 1 > part_cap) {
+    snprintf(g_last_error, sizeof(g_last_error), "scan of %lld elements needs %lld partials, workspace holds %lld",
+             (long long)n, (long long)(nb + 1), (long long)part_cap);
+    return SG_ERR_WORKSPACE;
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, part);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, part, nb);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, part, nb, out);
@@ -843,6 +851,14 @@ sg_status sg_spgemm_workspace_size(const sg_semiring *sr, int32_t nprod, const s
 sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B,
                              const int32_t *group, int32_t ngroup, int32_t out_fmt, const sg_tuning *tuning, void *ws,
                              size_t ws_bytes, sg_plan **plan_out, sg_sym_info *info, void *stream) {
+  return sg_spgemm_symbolic_masked(sr, nprod, A, B, group, ngroup, out_fmt, nullptr, tuning, ws, ws_bytes, plan_out,
+                                   info, stream);
+}
+
+sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B,
+                                    const int32_t *group, int32_t ngroup, int32_t out_fmt, const sg_mask *masks,
+                                    const sg_tuning *tuning, void *ws, size_t ws_bytes, sg_plan **plan_out,
+                                    sg_sym_info *info, void *stream) {
   if (!plan_out || !info || !ws) return SG_ERR_INVALID_ARG;
   *plan_out = nullptr;
   hipStream_t st = (hipStream_t)stream;
@@ -952,6 +968,16 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     const int64_t cap = mid_capacity(t, sr->kind, G.minor);
     G.mid_ok = cap > 0 ? (int32_t)std::min<int64_t>(cap, INT32_MAX) : 0;
     G.ov_begin = G.ov_end = G.nnz_base = G.nz_base = 0;
+    G.mask = nullptr;
+    G.mask_stride = 0;
+    G.mask_comp = 0;
+    G.mask_pad = 0;
+    if (masks && masks[g].bits) {
+      if (masks[g].stride_words < (G.minor + 31) / 32) return SG_ERR_INVALID_ARG;
+      G.mask = masks[g].bits;
+      G.mask_stride = masks[g].stride_words;
+      G.mask_comp = masks[g].complement ? 1 : 0;
+    }
     dbase[g + 1] = dbase[g] + sh.major[g];
     pbase[g + 1] = pbase[g] + sh.major[g] + 1;
   }
@@ -1004,8 +1030,8 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(sh.ndense, kFillThreads)), dim3(kFillThreads), 0, st,
                        L.dcnt, sh.ndense, L.dflag);
     SG_HIP(hipGetLastError());
-    SG_TRY(scan64(L.dflag, sh.ndense, L.vpos, L.part, st));
-    SG_TRY(scan64(L.dcnt, sh.ndense, L.spos, L.part, st));
+    SG_TRY(scan64(L.dflag, sh.ndense, L.vpos, L.part, L.part_cap, st));
+    SG_TRY(scan64(L.dcnt, sh.ndense, L.spos, L.part, L.part_cap, st));
     if (sh.ndense > 0) {
       hipLaunchKernelGGL(k_dense_emit, dim3((unsigned)grid_for(sh.ndense, kFillThreads)), dim3(kFillThreads), 0, st,
                          L.dcnt, L.vpos, L.spos, sh.ndense, L.dbase, ngroup, L.ov_id, L.ov_group, L.ov_seg, L.counters);
@@ -1089,15 +1115,15 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
   hipLaunchKernelGGL(k_plan_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
                      sh.nov_max, L.heavy_nwin);
   SG_HIP(hipGetLastError());
-  SG_TRY(scan64(L.heavy_nwin, sh.nov_max * sh.nrange, L.ibase, L.part, st));
+  SG_TRY(scan64(L.heavy_nwin, sh.nov_max * sh.nrange, L.ibase, L.part, L.part_cap, st));
   hipLaunchKernelGGL(k_tier_nnz, dim3((unsigned)std::min<int64_t>(grid_for(sh.nov_max, 256), 1024)), dim3(256), 0, st, P,
                      L.counters);
   SG_HIP(hipGetLastError());
-  SG_TRY(scan64(L.ov_cnt, sh.nov_max, L.ov_off, L.part, st));
+  SG_TRY(scan64(L.ov_cnt, sh.nov_max, L.ov_off, L.part, L.part_cap, st));
   hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st,
                      L.ov_cnt, sh.nov_max, L.nzflag);
   SG_HIP(hipGetLastError());
-  SG_TRY(scan64(L.nzflag, sh.nov_max, L.nzpos, L.part, st));
+  SG_TRY(scan64(L.nzflag, sh.nov_max, L.nzpos, L.part, L.part_cap, st));
   hipLaunchKernelGGL(k_group_totals, dim3((unsigned)grid_for(ngroup, 64)), dim3(64), 0, st, L.groups, ngroup,
                      L.ov_off, L.nzpos, L.gstat);
   SG_HIP(hipGetLastError());
@@ -1106,7 +1132,7 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat 
     hipLaunchKernelGGL(k_rec_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
                        L.heavy_nwin, sh.nov_max, L.vsent, L.rcnt);
     SG_HIP(hipGetLastError());
-    SG_TRY(scan64(L.rcnt, sh.nov_max, L.rbase, L.part, st));
+    SG_TRY(scan64(L.rcnt, sh.nov_max, L.rbase, L.part, L.part_cap, st));
   }
   // the window items carry their absolute output positions, so they are
   // filled once the vector offsets and the group bases are known
@@ -1238,6 +1264,69 @@ sg_status sg_build_aux(const sg_mat *M, int32_t *aux, int64_t *nchunks_out, void
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Mask update: set bit (i, j) for every stored entry (i in vector j) of a
+// batch of matrices, one descriptor each (passed by value, up to kMaskChunk).
+namespace {
+constexpr int kMaskChunk = 16;
+struct MaskSetDesc {
+  const int64_t *ptr;
+  const int32_t *vid;
+  const int32_t *idx;
+  uint32_t *bits;
+  int64_t nvec;
+  int64_t stride;
+  int64_t ebase;  // entries of the matrices before this one
+};
+struct MaskSetChunk {
+  MaskSetDesc d[kMaskChunk];
+  int32_t n;
+};
+
+__global__ void k_mask_set(MaskSetChunk c, int64_t total) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    int m = 0;
+    while (m + 1 < c.n && c.d[m + 1].ebase <= x) ++m;
+    const MaskSetDesc &D = c.d[m];
+    const int64_t e = gload(D.ptr) + (x - D.ebase);
+    const int64_t t = vector_of(D.ptr, D.nvec, e);
+    const int64_t j = D.vid ? gload(D.vid + t) : t;
+    const int32_t i = gload(D.idx + e);
+    atomicOr(D.bits + j * D.stride + (i >> 5), 1u << (i & 31));
+  }
+}
+}  // namespace
+
+extern "C" sg_status sg_mask_set(int32_t n, const sg_mat *M, const sg_mask *masks, void *stream) {
+  if (n < 0 || (n > 0 && (!M || !masks))) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  for (int32_t a = 0; a < n; a += kMaskChunk) {
+    MaskSetChunk c;
+    std::memset(&c, 0, sizeof(c));
+    int64_t tot = 0;
+    c.n = 0;
+    for (int32_t b = a; b < n && b < a + kMaskChunk; ++b) {
+      SG_TRY(check_mat(M[b], SG_OR_AND_BOOL));
+      const int64_t minor = minor_of(M[b]);
+      if (!masks[b].bits || masks[b].stride_words < (minor + 31) / 32) return SG_ERR_INVALID_ARG;
+      if (M[b].nnz == 0) continue;
+      MaskSetDesc &D = c.d[c.n++];
+      D.ptr = M[b].ptr;
+      D.vid = doubly(M[b].fmt) ? M[b].vid : nullptr;
+      D.idx = M[b].idx;
+      D.bits = (uint32_t *)masks[b].bits;
+      D.nvec = M[b].nvec;
+      D.stride = masks[b].stride_words;
+      D.ebase = tot;
+      tot += M[b].nnz;
+    }
+    if (tot == 0) continue;
+    hipLaunchKernelGGL(k_mask_set, dim3((unsigned)grid_for(tot, kFillThreads)), dim3(kFillThreads), 0, st, c, tot);
+    SG_HIP(hipGetLastError());
+  }
+  return SG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Format utilities: stable radix sort, triples -> compressed, format change.
 namespace {
 
@@ -1253,11 +1342,13 @@ struct SortBufs {
   int32_t *p[2];
   char *v[2];
   int64_t *hist, *hoff, *part;
+  int64_t part_cap;
 };
 
 int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
-void carve_sort(Carve &c, int64_t n, int vb, bool pay, SortBufs &S) {
+// `scan_n`: the longest scan that uses S.part besides the sort's own
+void carve_sort(Carve &c, int64_t n, int vb, bool pay, SortBufs &S, int64_t scan_n) {
   for (int i = 0; i < 2; ++i) {
     S.k[i] = c.take<uint64_t>(n);
     S.p[i] = pay ? c.take<int32_t>(n) : nullptr;
@@ -1266,7 +1357,8 @@ void carve_sort(Carve &c, int64_t n, int vb, bool pay, SortBufs &S) {
   const int64_t nh = 256 * std::max<int64_t>(1, sort_tiles(n));
   S.hist = c.take<int64_t>(nh);
   S.hoff = c.take<int64_t>(nh + 1);
-  S.part = c.take<int64_t>(std::max<int64_t>(nh, n + 1) / kScanTile + 4);
+  S.part_cap = std::max<int64_t>(std::max<int64_t>(nh, n + 1), scan_n + 1) / kScanTile + 4;
+  S.part = c.take<int64_t>(S.part_cap);
 }
 
 template <int VB, bool PAY>
@@ -1285,7 +1377,7 @@ sg_status radix_sort(const SortBufs &S, int vb, bool pay, int64_t n, int bits, h
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kSortThreads), 0, st, S.k[res], n, shift, nt, S.hist);
-    SG_TRY(scan64(S.hist, 256 * nt, S.hoff, S.part, st));
+    SG_TRY(scan64(S.hist, 256 * nt, S.hoff, S.part, S.part_cap, st));
     if (vb == 8) pay ? launch_scatter<8, true>(S, res, n, shift, nt, st) : launch_scatter<8, false>(S, res, n, shift, nt, st);
     else if (vb == 4) pay ? launch_scatter<4, true>(S, res, n, shift, nt, st) : launch_scatter<4, false>(S, res, n, shift, nt, st);
     else pay ? launch_scatter<0, true>(S, res, n, shift, nt, st) : launch_scatter<0, false>(S, res, n, shift, nt, st);
@@ -1307,7 +1399,7 @@ CooWs carve_coo(void *ws, int64_t n, int64_t major_dim, int vb) {
   CooWs W{};
   Carve c(ws);
   W.bad = c.take<int64_t>(32);
-  carve_sort(c, n, vb, false, W.S);
+  carve_sort(c, n, vb, false, W.S, major_dim);
   W.head = c.take<int64_t>(n + 1);
   W.vhead = c.take<int64_t>(n + 1);
   W.upos = c.take<int64_t>(n + 1);
@@ -1346,7 +1438,7 @@ struct ConvWs {
 ConvWs carve_conv(void *ws, int64_t nnz, int64_t nvec, int64_t out_major, int vb) {
   ConvWs W{};
   Carve c(ws);
-  carve_sort(c, nnz, vb, true, W.S);
+  carve_sort(c, nnz, vb, true, W.S, std::max(nvec, out_major));
   const int64_t nf = std::max<int64_t>(nnz, nvec) + 1;
   W.flag = c.take<int64_t>(nf);
   W.pos = c.take<int64_t>(nf);
@@ -1446,8 +1538,8 @@ sg_status sg_coo_compress(const sg_semiring *sr, int64_t nrows, int64_t ncols, i
     hipLaunchKernelGGL(k_key_heads, dim3((unsigned)grid_for(nnz, kFillThreads)), dim3(kFillThreads), 0, st, W.S.k[res],
                        nnz, (uint64_t)std::max<int64_t>(1, minor_dim), W.head, W.vhead);
     SG_HIP(hipGetLastError());
-    SG_TRY(scan64(W.head, nnz, W.upos, W.S.part, st));
-    SG_TRY(scan64(W.vhead, nnz, W.vpos, W.S.part, st));
+    SG_TRY(scan64(W.head, nnz, W.upos, W.S.part, W.S.part_cap, st));
+    SG_TRY(scan64(W.vhead, nnz, W.vpos, W.S.part, W.S.part_cap, st));
     SG_HIP(hipMemcpyAsync(&h[0], W.bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SG_HIP(hipMemcpyAsync(&h[1], W.upos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SG_HIP(hipMemcpyAsync(&h[2], W.vpos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -1481,7 +1573,7 @@ sg_status sg_coo_emit(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64
   if (dbl) {
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, out->ptr + nvec_out, nnz_out);
   } else {
-    SG_TRY(scan64(W.cnt, major_dim, out->ptr, W.S.part, st));
+    SG_TRY(scan64(W.cnt, major_dim, out->ptr, W.S.part, W.S.part_cap, st));
   }
   SG_HIP(hipGetLastError());
   return SG_OK;
@@ -1523,7 +1615,7 @@ sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *
       nv = nvec;
     } else if (doubly(fmt)) {  // plain -> doubly: keep the non-empty vectors
       hipLaunchKernelGGL(k_vec_nonempty, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, nvec, W.flag);
-      SG_TRY(scan64(W.flag, nvec, W.pos, W.S.part, st));
+      SG_TRY(scan64(W.flag, nvec, W.pos, W.S.part, W.S.part_cap, st));
       SG_HIP(hipMemcpyAsync(&nv, W.pos + nvec, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       SG_HIP(hipStreamSynchronize(st));
       SG_TRY(out_check(out, fmt, M->nrows, M->ncols, nnz, nv, sr->kind));
@@ -1535,7 +1627,7 @@ sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *
       SG_TRY(fill64(W.cnt, out_major + 1, 0, st));
       if (nvec > 0)
         hipLaunchKernelGGL(k_vec_counts, dim3(gV), dim3(kFillThreads), 0, st, M->ptr, M->vid, nvec, W.cnt);
-      SG_TRY(scan64(W.cnt, out_major, out->ptr, W.S.part, st));
+      SG_TRY(scan64(W.cnt, out_major, out->ptr, W.S.part, W.S.part_cap, st));
     }
     if (nnz > 0)
       hipLaunchKernelGGL(k_copy_entries, dim3(gE), dim3(kFillThreads), 0, st, M->ptr, M->idx, M->val, nnz, vb, out->idx,
@@ -1555,7 +1647,7 @@ sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *
       if (nnz > 0) {
         hipLaunchKernelGGL(k_key_heads, dim3(gE), dim3(kFillThreads), 0, st, W.S.k[res], nnz, (uint64_t)1, W.flag,
                            W.pos);  // W.pos: vector heads equal run heads here; overwritten by the scan
-        SG_TRY(scan64(W.flag, nnz, W.pos, W.S.part, st));
+        SG_TRY(scan64(W.flag, nnz, W.pos, W.S.part, W.S.part_cap, st));
         SG_HIP(hipMemcpyAsync(&nv, W.pos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         SG_HIP(hipStreamSynchronize(st));
       } else {
@@ -1571,7 +1663,7 @@ sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *
       SG_TRY(fill64(W.cnt, out_major + 1, 0, st));
       if (nnz > 0)
         hipLaunchKernelGGL(k_key_counts, dim3(gE), dim3(kFillThreads), 0, st, W.S.k[res], nnz, W.cnt);
-      SG_TRY(scan64(W.cnt, out_major, out->ptr, W.S.part, st));
+      SG_TRY(scan64(W.cnt, out_major, out->ptr, W.S.part, W.S.part_cap, st));
     }
     if (nnz > 0) {
       hipLaunchKernelGGL(k_copy_words, dim3(gE), dim3(kFillThreads), 0, st, (const uint32_t *)W.S.p[res],

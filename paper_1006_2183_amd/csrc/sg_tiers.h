@@ -49,6 +49,28 @@ __device__ __forceinline__ void chk_count(const Plan &P, bool bad) {
   }
 }
 
+// The output mask of vector v (its group's mask at v's major id).
+struct MaskRef {
+  const uint32_t *m;
+  int64_t stride;
+  int64_t j;
+  int32_t comp;
+  __device__ __forceinline__ bool on() const { return m != nullptr; }
+  // bits of the ids [32 w, 32 w + 32) the output keeps
+  __device__ __forceinline__ uint32_t word(int64_t w) const { return keep_word(m, stride, comp, j, w); }
+  __device__ __forceinline__ bool keeps(int64_t id) const { return m == nullptr || ((word(id >> 5) >> (id & 31)) & 1u); }
+};
+__device__ __forceinline__ MaskRef mask_of(const Plan &P, int64_t v) {
+  const int32_t g = uload(P.ov_group + v);
+  MaskRef r{uload(&P.groups[g].mask), 0, 0, 0};
+  if (r.m) {
+    r.stride = uload(&P.groups[g].mask_stride);
+    r.comp = uload(&P.groups[g].mask_comp);
+    r.j = uload(P.ov_id + v);
+  }
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Accumulators take a product in two steps so that the LDS reads of several
 // products can be in flight together: prep(id) issues the reads one product
@@ -454,7 +476,9 @@ __device__ void tiny_vector(const Plan &P, int64_t v) {
   // segmented (+) of equal ids: the last lane of each run ends with its total
   const uint64_t k64 = (uint64_t)(uint32_t)key;
   if (SR::kVal) val = seg_prefix<SR>(k64, val);
-  const bool tail = key != INT32_MAX && next_lane_key(k64) != k64;
+  bool tail = key != INT32_MAX && next_lane_key(k64) != k64;
+  const MaskRef mk = mask_of(P, v);
+  if (mk.on() && tail) tail = mk.keeps(key);
   const uint64_t hm = __ballot(tail);
   if (COUNT) {
     if (l == 0) P.ov_cnt[v] = __popcll(hm);
@@ -503,8 +527,10 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
   int64_t v = -1;
   int32_t p = -1, t = 0;
   int f = 0;
+  int32_t jv = 0;  // the vector's output major id (for masked groups)
   if (has) {
     v = gload(P.tiny_list + c0 + l);
+    jv = gload(P.ov_id + v);
     const int64_t s0 = gload(P.ov_seg + v), s1 = gload(P.ov_seg + v + 1);
     f = (int)gload(P.ov_flops + v);
     if (s1 - s0 == 1) {
@@ -527,6 +553,13 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
     const int fp = pack ? f : 0, np = pack ? ne : 0;
     const int Finc = wave_incl_scan(fp), Einc = wave_incl_scan(np);
     const OutDev O = uload(P.outs + d.group);
+    const uint32_t *gmask = uload(&P.groups[d.group].mask);
+    int64_t gstride = 0;
+    int32_t gcomp = 0;
+    if (gmask) {
+      gstride = uload(&P.groups[d.group].mask_stride);
+      gcomp = uload(&P.groups[d.group].mask_comp);
+    }
     int64_t opos = 0;
     if (!COUNT && pack) opos = gload(P.ov_off + v) - uload(&P.groups[d.group].nnz_base);
     uint64_t rem = __ballot(pack);
@@ -579,7 +612,12 @@ __device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
       // segmented (+) of equal keys: the last lane of each run holds its total
       if (SR::kVal) val = seg_prefix<SR>(ck, val);
       const int tag = (int)(ck >> 32);
-      const bool tail = tag < kWave && next_lane_key(ck) != ck;
+      bool tail = tag < kWave && next_lane_key(ck) != ck;
+      if (gmask) {
+        const int64_t jt = __shfl(jv, tag < kWave ? tag : 0, kWave);
+        const uint32_t id = (uint32_t)ck;
+        if (tail) tail = (keep_word(gmask, gstride, gcomp, jt, id >> 5) >> (id & 31)) & 1u;
+      }
       const uint64_t hm = __ballot(tail);
       // vector lane x owns the sorted lanes [Finc_x - f_x - bf, Finc_x - bf)
       const int seg_a = Finc - fp - bf;
@@ -631,6 +669,7 @@ struct RankAcc {
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
+  bool masked;  // the output mask removed ids from the bitmap: skip their products
   __device__ __forceinline__ uint64_t prep(int id) const {
     const uint32_t r = (uint32_t)(id - lo32);
     return *(const uint64_t *)((const char *)words + ((r >> 2) & ~7u));  // the pair of word r / 32
@@ -639,6 +678,7 @@ struct RankAcc {
     const uint32_t r = (uint32_t)(id - lo32);
     const uint32_t bits = (uint32_t)tok;
     const uint32_t pre = (uint32_t)(tok >> 32);
+    if (masked && !((bits >> (r & 31)) & 1u)) return;
     // set bits of the word below bit r % 32 (the field width is taken mod 32)
     SR::acc(&vals[pre + __popc(__builtin_amdgcn_ubfe(bits, 0u, r))], x);
   }
@@ -737,6 +777,8 @@ __device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi,
   const int tw0 = tid * tper < ntop ? tid * tper : ntop;
   const int tw1 = tw0 + tper < ntop ? tw0 + tper : ntop;
   const OutDev O = uload(P.outs + uload(P.ov_group + v));
+  const MaskRef mk = mask_of(P, v);
+  const int64_t w0lo = lo >> 5;  // mask word of the window's first 32 ids
   int64_t cnt = 0;  // entries of the window
 
   if (!COUNT && kept) {
@@ -765,6 +807,7 @@ __device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi,
       while (tb) {
         const int w = (tw << 5) + __ffs(tb) - 1;
         tb &= tb - 1;
+        if (mk.on()) words[WS * w] &= mk.word(w0lo + w);  // drop the ids the output mask excludes
         local += __popc(words[WS * w]);
       }
     }
@@ -819,7 +862,10 @@ __device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi,
     const int w0 = tid * per < nwds ? tid * per : nwds;
     const int w1 = w0 + per < nwds ? w0 + per : nwds;
     int local = 0;
-    for (int w = w0; w < w1; ++w) local += __popc(words[WS * w]);
+    for (int w = w0; w < w1; ++w) {
+      if (mk.on() && words[WS * w]) words[WS * w] &= mk.word(w0lo + w);  // the output mask's exclusions
+      local += __popc(words[WS * w]);
+    }
     int64_t total;
     const int64_t excl = block_excl_scan(local, scratch, &total);
     if (COUNT) {
@@ -853,7 +899,7 @@ __device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi,
     cnt = total;
     __syncthreads();
   }
-  RankAcc<SR> accum{words, vals, lo32};
+  RankAcc<SR> accum{words, vals, lo32, mk.on()};
   if (RECS && rb >= 0) {
     for_products_recs<SR>(P, rb, nrec, wid, nw, accum);
   } else {
@@ -946,10 +992,11 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
   });
   for_products<SR>(P, v, -1, -1, wid, nw, ins);
   __syncthreads();
+  const MaskRef mk = mask_of(P, v);
   if (COUNT) {
     int64_t local = 0;
     for (int i = tid; i < ts; i += nt) {
-      local += keys[i] != 0;
+      local += keys[i] != 0 && mk.keeps(keys[i] - 1u);
       keys[i] = 0;
     }
     const int64_t total = block_sum(local, scratch);
@@ -957,9 +1004,9 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
     __syncthreads();
     return;
   }
-  // empty slots sort last
+  // empty slots, and ids the output mask excludes, sort last
   for (int i = tid; i < ts; i += nt)
-    if (keys[i] == 0) keys[i] = 0xFFFFFFFFu;
+    if (keys[i] == 0 || !mk.keeps(keys[i] - 1u)) keys[i] = 0xFFFFFFFFu;
   __syncthreads();
   for (int k = 2; k <= ts; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -1022,8 +1069,13 @@ __device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int
   const int per = (nwf + nt - 1) / nt;
   const int w0 = tid * per < nwf ? tid * per : nwf;
   const int w1 = w0 + per < nwf ? w0 + per : nwf;
+  const MaskRef mk = mask_of(P, v);
+  const int64_t wlo = lo >> 5;
   int local = 0;
-  for (int w = w0; w < w1; ++w) local += __popc(flags[w]);
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t f = flags[w];
+    local += __popc(mk.on() && f ? f & mk.word(wlo + w) : f);
+  }
   int64_t total;
   const int64_t excl = block_excl_scan(local, scratch, &total);
   if (COUNT) {
@@ -1035,16 +1087,18 @@ __device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int
   int64_t r = out_pos + excl;
   for (int w = w0; w < w1; ++w) {
     uint32_t b = flags[w];
+    const uint32_t keep = mk.on() && b ? mk.word(wlo + w) : ~0u;
     while (b) {
       const int bit = __ffs(b) - 1;
       b &= b - 1;
       const int x = (w << 5) + bit;
-      gstore(O.idx + r, lo32 + x);
+      const bool out = (keep >> bit) & 1u;  // masked ids are only cleared
+      if (out) gstore(O.idx + r, lo32 + x);
       if (SR::kVal) {
-        gstore((T *)O.val + r, SR::dec(vals[x]));
+        if (out) gstore((T *)O.val + r, SR::dec(vals[x]));
         vals[x] = Slot();
       }
-      ++r;
+      r += out;
     }
     flags[w] = 0;
   }
@@ -1097,6 +1151,7 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
   const int w0 = tid * per < nwds ? tid * per : nwds;
   const int w1 = w0 + per < nwds ? w0 + per : nwds;
   const bool vec = ((((uintptr_t)bits) | (keep ? (uintptr_t)keep : 0)) & 15) == 0;
+  const MaskRef mk = mask_of(P, v);
   int bk_run = -1, acc = 0;
   for (int w = w0; w < w1; w += 4) {
     uint32_t x[4];
@@ -1106,15 +1161,21 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
       x[1] = q.y;
       x[2] = q.z;
       x[3] = q.w;
-      if (keep) gstore((u32x4 *)(keep + w), q);
       if (q.x | q.y | q.z | q.w) *(u32x4 *)&bits[w] = u32x4{0u, 0u, 0u, 0u};
+      if (mk.on()) {  // the output mask's exclusions leave the counts and the kept bitmap
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (x[j]) x[j] &= mk.word(w + j);
+      }
+      if (keep) gstore((u32x4 *)(keep + w), u32x4{x[0], x[1], x[2], x[3]});
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         x[j] = w + j < w1 ? bits[w + j] : 0u;
         if (w + j < w1) {
-          if (keep) gstore(keep + w + j, x[j]);
           if (x[j]) bits[w + j] = 0;
+          if (mk.on() && x[j]) x[j] &= mk.word(w + j);
+          if (keep) gstore(keep + w + j, x[j]);
         }
       }
     }
