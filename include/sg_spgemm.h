@@ -284,6 +284,36 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod,
                                     sg_sym_info *info, void *stream);
 
 /*
+ * Fused chain products C_p = X_p Y_p Z_p for p in [0, nprod) (host arrays of
+ * descriptors of device data, all CSR or all CSC, plain compressed), each
+ * into its own output C_p (format out_fmt, the operands' orientation). The
+ * intermediate product is never written to memory: for every output vector
+ * (a column of C column-major, a row row-major) one wavefront or one
+ * workgroup forms that vector of the inner product (Y Z(:, j), or X(i, :) Y)
+ * in registers or LDS, merges it, and immediately multiplies the outer
+ * operand by it (the triple products of multigrid setup, R A P, which the
+ * paper's Section 8 names as the next step). The result equals the two-call
+ * product X (Y Z), column-major, or (X Y) Z, row-major: the intermediate
+ * vector is merged before the second stage exactly as the two calls would
+ * write it.
+ *
+ * The plan is a normal sg_plan: sg_spgemm_numeric / sg_spgemm_batched
+ * recompute every C_p from the current operand VALUES (the structure must
+ * stay the same), so the symbolic phase of a setup is reused across repeated
+ * setups with new values, and the numeric phase can be captured in a graph.
+ * sg_sym_info per product: flops counts the multiplications of both stages,
+ * nnz_ub the sum over output vectors of min(unmerged fused multiplications,
+ * minor dimension). Errors: as sg_spgemm_symbolic; UNSUPPORTED for doubly
+ * compressed operands, and for an output vector whose intermediate or result
+ * exceeds the LDS-resident tier (the message gives the limit).
+ */
+sg_status sg_chain_workspace_size(const sg_semiring *sr, int32_t nprod, const sg_mat *X, const sg_mat *Y,
+                                  const sg_mat *Z, int32_t out_fmt, const sg_tuning *tuning, size_t *ws_bytes);
+sg_status sg_chain_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat *X, const sg_mat *Y, const sg_mat *Z,
+                            int32_t out_fmt, const sg_tuning *tuning, void *ws, size_t ws_bytes, sg_plan **plan,
+                            sg_sym_info *info, void *stream);
+
+/*
  * Mask update (a BFS's "visited |= new frontier"): for each of the n
  * matrices M[k] (host array of descriptors of device data) sets bit (i, j) of
  * masks[k] for every stored entry i of M[k]'s vector j, with atomic ORs on

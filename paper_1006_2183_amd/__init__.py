@@ -25,4 +25,5 @@ from .binding import (  # noqa: F401
     convert,
     Mask,
     mask_set,
+    chain_symbolic,
 )

@@ -9,6 +9,8 @@
   (C = (+)_k I C_k column-major), a k-way merge on the same accumulators.
 * ``galerkin_rap``: R (A P) for many uneven instances (graph contraction and
   multigrid coarsening, Section 6.2.3), two grouped plans (A P, then R (AP)).
+* ``galerkin_fused``: the same triple products as one fused chain plan: the
+  intermediate A P is never written to memory.
 * ``GraphedNumeric``: captures the persistent batched launches of one plan
   or a chain of plans in a HIP graph; each replay recomputes the outputs
   from the current operand values (same structure), with no host work.
@@ -102,6 +104,25 @@ def galerkin_plans(semiring: str, Rs: Sequence[DevMat], As: Sequence[DevMat], Ps
     B.spgemm_batched(plan_ap, AP, stream)
     plan_rap = B.spgemm_symbolic(semiring, list(Rs), AP, list(range(n)), n, tuning=tuning, stream=stream)
     return plan_ap, AP, plan_rap
+
+
+def galerkin_chain_plan(semiring: str, Rs: Sequence[DevMat], As: Sequence[DevMat], Ps: Sequence[DevMat], tuning=None,
+                        stream=None):
+    """One fused plan for every instance's R_i A_i P_i: the products A P are never
+    written; the plan's numeric phase (plain, batched or graph-replayed) recomputes
+    every R A P from the current values of R, A and P, so a repeated setup with new
+    values reuses this symbolic phase."""
+    return B.chain_symbolic(semiring, list(Rs), list(As), list(Ps), tuning=tuning, stream=stream)
+
+
+def galerkin_fused(semiring: str, Rs: Sequence[DevMat], As: Sequence[DevMat], Ps: Sequence[DevMat], tuning=None,
+                   batched: bool = True, stream=None) -> List[DevMat]:
+    """R_i A_i P_i for every instance, fused (one plan, one output per instance)."""
+    plan = galerkin_chain_plan(semiring, Rs, As, Ps, tuning=tuning, stream=stream)
+    C = plan.alloc_outputs(As[0].ptr.device)
+    (B.spgemm_batched if batched else B.spgemm_numeric)(plan, C, stream)
+    plan.destroy()
+    return C
 
 
 class GraphedNumeric:

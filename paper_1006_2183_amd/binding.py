@@ -28,7 +28,7 @@ EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_
            "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
            "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked", "sg_coo_workspace_size",
            "sg_coo_compress", "sg_coo_emit", "sg_convert_workspace_size", "sg_convert", "sg_spgemm_symbolic_masked",
-           "sg_mask_set"]
+           "sg_mask_set", "sg_chain_workspace_size", "sg_chain_symbolic"]
 
 
 class SgError(RuntimeError):
@@ -159,6 +159,13 @@ def load_library(path: Optional[str] = None):
     lib.sg_spgemm_symbolic_masked.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), ctypes.c_void_p,
                                               ctypes.c_int32, ctypes.c_int32, P(sg_mask), P(sg_tuning), ctypes.c_void_p,
                                               ctypes.c_size_t, P(ctypes.c_void_p), P(sg_sym_info), ctypes.c_void_p]
+    lib.sg_chain_workspace_size.restype = ctypes.c_int
+    lib.sg_chain_workspace_size.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), P(sg_mat), ctypes.c_int32,
+                                            P(sg_tuning), P(ctypes.c_size_t)]
+    lib.sg_chain_symbolic.restype = ctypes.c_int
+    lib.sg_chain_symbolic.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), P(sg_mat), ctypes.c_int32,
+                                      P(sg_tuning), ctypes.c_void_p, ctypes.c_size_t, P(ctypes.c_void_p), P(sg_sym_info),
+                                      ctypes.c_void_p]
     lib.sg_mask_set.restype = ctypes.c_int
     lib.sg_mask_set.argtypes = [ctypes.c_int32, P(sg_mat), P(sg_mask), ctypes.c_void_p]
     lib.sg_convert.restype = ctypes.c_int
@@ -586,3 +593,30 @@ def convert(semiring: str, M: DevMat, fmt: str, stream=None) -> DevMat:
         out.ptr = out.ptr[: nv.value + 1]
     out._keep = ws
     return out
+
+
+def chain_symbolic(semiring: str, Xs: Sequence[DevMat], Ys: Sequence[DevMat], Zs: Sequence[DevMat],
+                   out_fmt: Optional[str] = None, tuning: Optional[sg_tuning] = None, stream=None) -> Plan:
+    """Plan of the fused chains C_p = X_p Y_p Z_p (one output per chain): the
+    intermediate products are never written. Numeric calls as for any plan."""
+    torch = _torch()
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    out_fmt = out_fmt or Xs[0].fmt
+    X, Y, Z = _descs(Xs), _descs(Ys), _descs(Zs)
+    n = len(Xs)
+    sz = ctypes.c_size_t(0)
+    tptr = ctypes.byref(tuning) if tuning is not None else None
+    _check(lib.sg_chain_workspace_size(ctypes.byref(sr), n, X, Y, Z, FORMATS[out_fmt], tptr, ctypes.byref(sz)),
+           "sg_chain_workspace_size")
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=Xs[0].ptr.device)
+    handle = ctypes.c_void_p(0)
+    infos = (sg_sym_info * n)()
+    _check(lib.sg_chain_symbolic(ctypes.byref(sr), n, X, Y, Z, FORMATS[out_fmt], tptr, ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_size_t(ws.numel()), ctypes.byref(handle), infos, _stream(stream)),
+           "sg_chain_symbolic")
+    plan = Plan(semiring, list(Xs), list(Zs), None, n, out_fmt, tuning, handle, ws, [infos[i].as_dict() for i in range(n)],
+                stream)
+    plan.operands = (list(Xs), list(Ys), list(Zs))  # the plan refers to all three
+    return plan

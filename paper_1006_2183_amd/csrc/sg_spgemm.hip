@@ -16,6 +16,7 @@
 #include "sg_symbolic.h"
 #include "sg_tiers.h"
 #include "sg_convert.h"
+#include "sg_chain.h"
 
 using namespace sg;
 
@@ -214,6 +215,11 @@ struct sg_plan {
   bool timed = false;
   bool ran[4] = {false, false, false, false};
   hipEvent_t ev[8];
+  // fused chain plans (sg_chain_symbolic)
+  bool chain = false;
+  const ChainDev *chains = nullptr;
+  int chain_ts = 0;   // hash slots per stage of the chain mid tier
+  int lds_chain = 0;  // its dynamic LDS bytes
 };
 
 namespace {
@@ -550,6 +556,8 @@ sg_status set_lds_attr(int bytes) {
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   SG_HIP(hipFuncSetAttribute((const void *)k_batched<K, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_chain_mid<K, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  SG_HIP(hipFuncSetAttribute((const void *)k_chain_mid<K, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
   return SG_OK;
 }
 
@@ -730,6 +738,41 @@ struct RunAttr {
     if (bytes <= done) return SG_OK;
     SG_TRY(set_lds_attr<K>(bytes));
     done = bytes;
+    return SG_OK;
+  }
+};
+
+// Launches of a fused chain plan: tiny vectors one wavefront each, mid
+// vectors one workgroup each from a queue; COUNT = the symbolic count pass.
+template <int K>
+struct RunChain {
+  static sg_status run(sg_plan *pl, bool count, hipStream_t st) {
+    const sg_sym_info &I = pl->info[0];
+    const int64_t ntiny = count ? pl->nov_max : I.n_tiny;
+    const int64_t nmid = count ? pl->nov_max : I.n_mid;
+    const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
+    if (ntiny > 0) {
+      const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ntiny + 3) / 4, persist * 16));
+      if (count) hipLaunchKernelGGL((k_chain_tiny<K, true>), dim3(g), dim3(256), 0, st, pl->P, pl->chains, pl->gstat);
+      else hipLaunchKernelGGL((k_chain_tiny<K, false>), dim3(g), dim3(256), 0, st, pl->P, pl->chains, pl->gstat);
+      SG_HIP(hipGetLastError());
+    }
+    if (nmid > 0) {
+      int64_t *q = pl->counters + kCtNum + (count ? 0 : 3);
+      SG_TRY(fill64(q, 1, 0, st));
+      Plan Pc = pl->P;
+      Pc.lds_words = pl->lds_chain / 4;
+      const int nt = pl->tune.block_threads;
+      const unsigned g = (unsigned)std::max<int64_t>(
+          1, std::min<int64_t>(resident_blocks(pl->ncu, nt, pl->lds_chain, kWavesPerSimd), nmid));
+      if (count)
+        hipLaunchKernelGGL((k_chain_mid<K, true>), dim3(g), dim3(nt), pl->lds_chain, st, Pc, pl->chains, q,
+                           pl->chain_ts, pl->gstat);
+      else
+        hipLaunchKernelGGL((k_chain_mid<K, false>), dim3(g), dim3(nt), pl->lds_chain, st, Pc, pl->chains, q,
+                           pl->chain_ts, pl->gstat);
+      SG_HIP(hipGetLastError());
+    }
     return SG_OK;
   }
 };
@@ -1177,6 +1220,7 @@ sg_status sg_spgemm_numeric(sg_plan *pl, sg_mat_out *C, void *stream) {
   if (!pl) return SG_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   SG_TRY(emit_outputs(pl, C, st));
+  if (pl->chain) return dispatch<RunChain>(pl->kind, pl, false, st);
   return dispatch<RunNumeric>(pl->kind, pl, st);
 }
 
@@ -1184,6 +1228,7 @@ sg_status sg_spgemm_batched(sg_plan *pl, sg_mat_out *C, void *stream) {
   if (!pl) return SG_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   SG_TRY(emit_outputs(pl, C, st));
+  if (pl->chain) return dispatch<RunChain>(pl->kind, pl, false, st);
   return dispatch<RunBatched>(pl->kind, pl, st);
 }
 
@@ -1258,6 +1303,285 @@ sg_status sg_build_aux(const sg_mat *M, int32_t *aux, int64_t *nchunks_out, void
   hipLaunchKernelGGL(k_build_aux, dim3((unsigned)grid_for(nchunks + 1, kFillThreads)), dim3(kFillThreads), 0,
                      (hipStream_t)stream, M->vid, M->nvec, chunk, nchunks, aux);
   SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------------------------
+// Fused chain products C_p = X_p Y_p Z_p (the intermediate is never written).
+namespace {
+
+struct ChainLayout {
+  ProdDev *prods;
+  ChainDev *chains;
+  GroupDev *groups;
+  int64_t *vbase, *pbase;
+  size_t tables_end;
+  OutDev *outs;
+  int64_t *counters, *gstat, *ov_flops, *ov_cnt, *bound;
+  int64_t zero_words;
+  int32_t *ov_id, *ov_group, *seg_prod, *seg_svec, *tiny, *mid;
+  int64_t *ov_seg, *ov_off, *nzflag, *nzpos, *part;
+  int64_t part_cap;
+  size_t bytes;
+};
+
+ChainLayout carve_chain(void *ws, int32_t nprod, int64_t nov, int64_t ndense_ptr) {
+  ChainLayout L{};
+  Carve c(ws);
+  L.prods = c.take<ProdDev>(nprod);
+  L.chains = c.take<ChainDev>(nprod);
+  L.groups = c.take<GroupDev>(nprod);
+  L.vbase = c.take<int64_t>(nprod + 1);
+  L.pbase = c.take<int64_t>(nprod + 1);
+  L.tables_end = c.off;
+  L.outs = c.take<OutDev>(nprod);
+  L.counters = c.take<int64_t>(kCtNum + 24);
+  L.gstat = c.take<int64_t>((int64_t)nprod * kStCount);
+  L.ov_flops = c.take<int64_t>(nov);
+  L.ov_cnt = c.take<int64_t>(nov + 1);
+  L.bound = c.take<int64_t>(nov);
+  L.zero_words = (int64_t)((c.off - ((char *)L.counters - c.base)) / sizeof(int64_t));
+  L.ov_id = c.take<int32_t>(nov);
+  L.ov_group = c.take<int32_t>(nov);
+  L.seg_prod = c.take<int32_t>(nov);
+  L.seg_svec = c.take<int32_t>(nov);
+  L.tiny = c.take<int32_t>(nov);
+  L.mid = c.take<int32_t>(nov);
+  L.ov_seg = c.take<int64_t>(nov + 1);
+  L.ov_off = c.take<int64_t>(nov + 1);
+  L.nzflag = c.take<int64_t>(nov + 1);
+  L.nzpos = c.take<int64_t>(nov + 1);
+  L.part_cap = std::max<int64_t>(nov + 1, ndense_ptr) / kScanTile + 4;
+  L.part = c.take<int64_t>(L.part_cap);
+  L.bytes = c.off + 256;
+  return L;
+}
+
+// Hash slots per stage of the chain mid tier: the largest power of two whose
+// two hashes and intermediate (ts / 2 entries) fit the LDS budget.
+int chain_slots(const sg_tuning &t, int32_t kind) {
+  const int64_t sb = std::max(4, slot_bytes(kind));
+  auto bytes = [&](int64_t ts) { return 2 * ts * 4 + (ts / 2) * 4 + (2 * ts + ts / 2) * sb; };
+  int64_t ts = 64;
+  while (bytes(ts * 2) <= t.lds_bytes) ts *= 2;
+  return (int)ts;
+}
+
+sg_status chain_check(const sg_semiring *sr, int32_t nprod, const sg_mat *X, const sg_mat *Y, const sg_mat *Z,
+                      int32_t out_fmt, int64_t &nov) {
+  if (!sr || sr->kind < SG_PLUS_TIMES_F64 || sr->kind > SG_OR_AND_BOOL) return SG_ERR_INVALID_ARG;
+  if (nprod < 1 || !X || !Y || !Z || !fmt_ok(out_fmt)) return SG_ERR_INVALID_ARG;
+  const bool rm = row_major(out_fmt);
+  nov = 0;
+  for (int32_t p = 0; p < nprod; ++p) {
+    for (const sg_mat *M : {&X[p], &Y[p], &Z[p]}) {
+      SG_TRY(check_mat(*M, sr->kind));
+      if (row_major(M->fmt) != rm || doubly(M->fmt)) return SG_ERR_UNSUPPORTED;
+    }
+    if (X[p].ncols != Y[p].nrows || Y[p].ncols != Z[p].nrows) return SG_ERR_DIM_MISMATCH;
+    nov += rm ? X[p].nrows : Z[p].ncols;
+  }
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_chain_workspace_size(const sg_semiring *sr, int32_t nprod, const sg_mat *X, const sg_mat *Y,
+                                  const sg_mat *Z, int32_t out_fmt, const sg_tuning *tuning, size_t *ws_bytes) {
+  (void)tuning;
+  if (!ws_bytes) return SG_ERR_INVALID_ARG;
+  int64_t nov = 0;
+  SG_TRY(chain_check(sr, nprod, X, Y, Z, out_fmt, nov));
+  int64_t ndp = 0;
+  for (int32_t p = 0; p < nprod; ++p) ndp += (row_major(out_fmt) ? X[p].nrows : Z[p].ncols) + 1;
+  *ws_bytes = carve_chain(nullptr, nprod, nov, ndp).bytes;
+  return SG_OK;
+}
+
+sg_status sg_chain_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat *X, const sg_mat *Y, const sg_mat *Z,
+                            int32_t out_fmt, const sg_tuning *tuning, void *ws, size_t ws_bytes, sg_plan **plan_out,
+                            sg_sym_info *info, void *stream) {
+  if (!plan_out || !info || !ws) return SG_ERR_INVALID_ARG;
+  *plan_out = nullptr;
+  int64_t nov = 0;
+  SG_TRY(chain_check(sr, nprod, X, Y, Z, out_fmt, nov));
+  if (((uintptr_t)ws & 255) != 0) return SG_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const bool rm = row_major(out_fmt);
+  sg_tuning t;
+  if (tuning) t = *tuning; else sg_tuning_default(sr->kind, &t);
+  normalise(t, sr->kind);
+  int64_t ndp = 0;
+  for (int32_t p = 0; p < nprod; ++p) ndp += (rm ? X[p].nrows : Z[p].ncols) + 1;
+  ChainLayout L = carve_chain(ws, nprod, nov, ndp);
+  if (ws_bytes < L.bytes) return SG_ERR_WORKSPACE;
+
+  sg_plan *pl = new (std::nothrow) sg_plan();
+  if (!pl) return SG_ERR_OOM;
+  struct Guard {
+    sg_plan *p;
+    ~Guard() {
+      if (p) sg_plan_destroy(p);
+    }
+  } guard{pl};
+  pl->kind = sr->kind;
+  pl->nprod = pl->ngroup = nprod;
+  pl->out_fmt = out_fmt;
+  pl->tune = t;
+  pl->ncu = device_cus();
+  pl->nov_max = nov;
+  pl->ndense_ptr = ndp;
+  pl->chain = true;
+  pl->chains = L.chains;
+  pl->chain_ts = chain_slots(t, sr->kind);
+  pl->lds_chain = (2 * pl->chain_ts * 4 + (pl->chain_ts / 2) * 4 +
+                   (2 * pl->chain_ts + pl->chain_ts / 2) * std::max(4, slot_bytes(sr->kind)) + 15) & ~15;
+  pl->info.assign(nprod, sg_sym_info{});
+  pl->outs_host.assign(nprod, OutDev{});
+  pl->host_stats.assign((size_t)nprod * kStCount + kCtNum, 0);
+  SG_TRY(dispatch<RunAttr>(sr->kind, std::max({t.lds_bytes, t.heavy_lds_bytes, pl->lds_chain})));
+
+  std::vector<ProdDev> prods(nprod);
+  std::vector<ChainDev> chains(nprod);
+  std::vector<GroupDev> groups(nprod);
+  std::vector<int64_t> vbase(nprod + 1, 0), pbase(nprod + 1, 0);
+  for (int32_t p = 0; p < nprod; ++p) {
+    // column-major: S = Z, G1 = Y, G2 = X; row-major: S = X, G1 = Y, G2 = Z
+    const sg_mat &S = rm ? X[p] : Z[p];
+    const sg_mat &G1 = Y[p];
+    const sg_mat &G2 = rm ? Z[p] : X[p];
+    ProdDev d{};
+    d.s_ptr = S.ptr;
+    d.s_idx = S.idx;
+    d.s_val = S.val;
+    d.s_nvec = S.nvec;
+    d.group = p;
+    d.nsplit = 1;
+    prods[p] = d;
+    ChainDev c{};
+    c.s_ptr = S.ptr;
+    c.s_idx = S.idx;
+    c.s_val = S.val;
+    c.s_nvec = S.nvec;
+    c.g1_ptr = G1.ptr;
+    c.g1_idx = G1.idx;
+    c.g1_val = G1.val;
+    c.g1_nvec = G1.nvec;
+    c.g2_ptr = G2.ptr;
+    c.g2_idx = G2.idx;
+    c.g2_val = G2.val;
+    c.g2_nvec = G2.nvec;
+    c.t_minor = minor_of(G1);
+    c.group = p;
+    chains[p] = c;
+    GroupDev G{};
+    G.minor = rm ? Z[p].ncols : X[p].nrows;
+    G.major = rm ? X[p].nrows : Z[p].ncols;
+    G.nsplit = 1;
+    G.sw = 32;
+    groups[p] = G;
+    vbase[p + 1] = vbase[p] + S.nvec;
+    pbase[p + 1] = pbase[p] + G.major + 1;
+    pl->out_minor.push_back(G.minor);
+    pl->out_major.push_back(G.major);
+  }
+  std::vector<char> img(L.tables_end, 0);
+  {
+    char *base = (char *)ws;
+    auto put = [&](const void *dev, const void *src, size_t bytes) {
+      std::memcpy(img.data() + ((const char *)dev - base), src, bytes);
+    };
+    put(L.prods, prods.data(), sizeof(ProdDev) * nprod);
+    put(L.chains, chains.data(), sizeof(ChainDev) * nprod);
+    put(L.groups, groups.data(), sizeof(GroupDev) * nprod);
+    put(L.vbase, vbase.data(), sizeof(int64_t) * (nprod + 1));
+    put(L.pbase, pbase.data(), sizeof(int64_t) * (nprod + 1));
+    SG_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
+  }
+  SG_TRY(fill64(L.counters, L.zero_words, 0, st));
+  if (nov > 0) {
+    hipLaunchKernelGGL(k_ov_simple, dim3((unsigned)grid_for(nov, kFillThreads)), dim3(kFillThreads), 0, st, L.prods,
+                       L.vbase, nprod, nov, L.ov_id, L.ov_group, L.ov_seg, L.seg_prod, L.seg_svec, L.counters);
+  } else {
+    SG_TRY(fill64(L.ov_seg, 1, 0, st));
+  }
+  hipLaunchKernelGGL(k_group_ranges, dim3((unsigned)grid_for(nprod, 64)), dim3(64), 0, st, L.ov_group, L.counters,
+                     L.groups, nprod);
+  SG_HIP(hipGetLastError());
+
+  Plan &P = pl->P;
+  P.prods = L.prods;
+  P.groups = L.groups;
+  P.outs = L.outs;
+  P.ov_id = L.ov_id;
+  P.ov_group = L.ov_group;
+  P.ov_seg = L.ov_seg;
+  P.seg_prod = L.seg_prod;
+  P.seg_svec = L.seg_svec;
+  P.ov_flops = L.ov_flops;
+  P.ov_cnt = L.ov_cnt;
+  P.ov_off = L.ov_off;
+  P.counters = L.counters;
+  P.tiny_list = L.tiny;
+  P.mid_list = L.mid;
+  P.chk = L.counters;
+  P.lds_words = t.lds_bytes / 4;
+  P.nbmax = 1;
+  P.nrange = 1;
+  pl->counters = L.counters;
+  pl->gstat = L.gstat;
+  pl->nzpos = L.nzpos;
+  pl->pbase = L.pbase;
+  pl->outs_dev = L.outs;
+
+  if (nov > 0) {
+    const int64_t waves = std::min<int64_t>((nov + kWave - 1) / kWave, (int64_t)pl->ncu * 32);
+    BinParams bp{t.tiny_max_flops, 0, t.force_tier};
+    const int32_t cap = pl->chain_ts / 2;
+    hipLaunchKernelGGL(k_chain_flops, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, L.chains, bp, cap, cap,
+                       L.bound, L.gstat, L.counters, L.tiny, L.mid);
+    SG_HIP(hipGetLastError());
+    SG_TRY(dispatch<RunChain>(sr->kind, pl, true, st));
+  }
+  SG_TRY(scan64(L.ov_cnt, nov, L.ov_off, L.part, L.part_cap, st));
+  hipLaunchKernelGGL(k_nonzero_flag, dim3((unsigned)grid_for(std::max<int64_t>(nov, 1), kFillThreads)),
+                     dim3(kFillThreads), 0, st, L.ov_cnt, nov, L.nzflag);
+  SG_TRY(scan64(L.nzflag, nov, L.nzpos, L.part, L.part_cap, st));
+  hipLaunchKernelGGL(k_group_totals, dim3((unsigned)grid_for(nprod, 64)), dim3(64), 0, st, L.groups, nprod, L.ov_off,
+                     L.nzpos, L.gstat);
+  SG_HIP(hipGetLastError());
+  SG_HIP(hipMemcpyAsync(pl->host_stats.data(), L.gstat, sizeof(int64_t) * (size_t)nprod * kStCount,
+                        hipMemcpyDeviceToHost, st));
+  SG_HIP(hipMemcpyAsync(pl->host_stats.data() + (size_t)nprod * kStCount, L.counters, sizeof(int64_t) * kCtNum,
+                        hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  const int64_t *cnt = pl->host_stats.data() + (size_t)nprod * kStCount;
+  if (cnt[kCtBad] > 0) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "%lld output vectors need more than the fused tiers hold (%d entries per stage)", (long long)cnt[kCtBad],
+             pl->chain_ts / 2);
+    return SG_ERR_UNSUPPORTED;
+  }
+  for (int32_t g = 0; g < nprod; ++g) {
+    const int64_t *sg_ = pl->host_stats.data() + (size_t)g * kStCount;
+    sg_sym_info &I = pl->info[g];
+    I.flops = sg_[kStFlops];
+    I.nnz_ub = sg_[kStUb];
+    I.nnz = sg_[kStNnz];
+    I.max_vec_flops = sg_[kStMaxFlops];
+    I.n_out_vec = sg_[kStOutVec];
+    I.nvec = doubly(out_fmt) ? sg_[kStNvec] : pl->out_major[g];
+    I.n_tiny = cnt[kCtTiny];
+    I.n_mid = cnt[kCtMid];
+    info[g] = I;
+  }
+  guard.p = nullptr;
+  *plan_out = pl;
   return SG_OK;
 }
 
