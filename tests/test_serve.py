@@ -176,10 +176,12 @@ def test_gpu_two_batches_in_flight():
     import paper_1006_2183_amd as sg
     from paper_1006_2183_amd.serve import GpuBatchExecutor
     sg.load_library()
-    A = W.rmat_matrix(17, 16, "or_and_bool", "csc", seed=2)
+    # the first batch holds about 270 M multiplications (several ms on the device), so
+    # the host plans and launches the second one while it runs
+    A = W.rmat_matrix(18, 16, "or_and_bool", "csc", seed=2)
     dA = sg.DevMat.from_host(A, "cuda", "or_and_bool")
     colcount = np.diff(A.ptr)
-    heavy = [W.bfs_frontier(A.nrows, 512, seed=300 + i, A=A, depth=1) for i in range(24)]
+    heavy = [W.bfs_frontier(A.nrows, 512, seed=300 + i, A=A, depth=1) for i in range(48)]
     light = [W.bfs_frontier(A.nrows, 4, seed=400 + i) for i in range(4)]
     mk = lambda i, X: Request(i, 0.0, sg.DevMat.from_host(X, "cuda", "or_and_bool"), frontier_bound(colcount, X))
     b1 = [mk(i, X) for i, X in enumerate(heavy)]
