@@ -425,12 +425,50 @@ def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
     torch.cuda.synchronize()
     for i in range(count):
         _same(G.outputs[i], res["plain"][i], 0.0, f"Galerkin graph instance {i}")
+    # fused chain: one plan, A P never written; its symbolic phase is reused by replays
+    plan_f = BT.galerkin_chain_plan(sr, Rs, Ls, Ps)
+    GF = BT.GraphedNumeric(plan_f)
+    GF.replay()
+    torch.cuda.synchronize()
+    for i in range(count):
+        _same(GF.outputs[i], res["plain"][i], 0.0, f"Galerkin fused graph instance {i}")
+
+    def fused():
+        res["fused"] = BT.galerkin_fused(sr, Rs, Ls, Ps, batched=True)
+
+    fused()
+    for i in range(count):
+        _same(res["fused"][i], res["plain"][i], 0.0, f"Galerkin fused instance {i}")
     ms_plain = _median_ms(torch, plain, reps)
     ms_batched = _median_ms(torch, batched, reps)
     ms_tuned = _median_ms(torch, tuned, reps)
     ms_graph = _median_ms(torch, G.replay, max(reps, 5))
+    ms_fused = _median_ms(torch, fused, reps)
+    ms_fgraph = _median_ms(torch, GF.replay, max(reps, 5))
+    plan_f.profile(True)
+    sg.spgemm_batched(plan_f, GF.outputs)
+    kt = plan_f.kernel_times()
+    flops_f = sum(i["flops"] for i in plan_f.infos)
+    nnz_f = sum(i["nnz"] for i in plan_f.infos)
+    # algorithmic bytes of the fused launch: stream P (4 + 8 per entry, 8 per
+    # pointer), the pointer pair of every gathered A and R vector, gather the
+    # entries of both stages (12 per multiplication), write R A P (12 per entry)
+    nnzP = sum(int(P.nnz) for P in Ps)
+    nvecP = sum(int(P.nvec) for P in Ps)
+    algo_f = 12 * nnzP + 8 * nvecP + 16 * flops_f // 4 + 12 * flops_f + 12 * nnz_f
+    launch_f = kt["tiny"] + kt["mid"]
+    out_fused = {"graph_replay_ms": round(ms_fgraph, 3), "plan_and_numeric_ms": round(ms_fused, 3),
+                 "flops": int(flops_f), "graph_GFLOPs": round(flops_f / ms_fgraph / 1e6, 2),
+                 "graph_vs_two_launch_graph": round(ms_graph / ms_fgraph, 2),
+                 "tiers": {"tiny": plan_f.infos[0]["n_tiny"], "mid": plan_f.infos[0]["n_mid"]},
+                 "launch_ms": round(launch_f, 4),
+                 "algorithmic_bytes": int(algo_f),
+                 "achieved_GBs": round(algo_f / launch_f / 1e6, 1) if launch_f > 0 else None,
+                 "exact": "fused == plain bitwise (R A P == 4 L_(n/2) on every instance)"}
+    plan_f.destroy()
     out = {
         "workload": f"galerkin_rap_7pt_{count}_instances_n_in_32_48_64_96_128_f64",
+        "fused_chain": out_fused,
         "sizes": sizes, "flops": int(flops),
         "nnz_RAP": int(sum(i["nnz"] for i in plan_rap.infos)),
         "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batched, 3), "tuned_ms": round(ms_tuned, 3),

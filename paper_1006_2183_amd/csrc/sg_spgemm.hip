@@ -753,9 +753,11 @@ struct RunChain {
     const int64_t persist = (int64_t)pl->ncu * pl->tune.blocks_per_cu;
     if (ntiny > 0) {
       const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ntiny + 3) / 4, persist * 16));
+      if (!count) SG_TRY(mark(pl, 2, false, st));
       if (count) hipLaunchKernelGGL((k_chain_tiny<K, true>), dim3(g), dim3(256), 0, st, pl->P, pl->chains, pl->gstat);
       else hipLaunchKernelGGL((k_chain_tiny<K, false>), dim3(g), dim3(256), 0, st, pl->P, pl->chains, pl->gstat);
       SG_HIP(hipGetLastError());
+      if (!count) SG_TRY(mark(pl, 2, true, st));
     }
     if (nmid > 0) {
       int64_t *q = pl->counters + kCtNum + (count ? 0 : 3);
@@ -765,6 +767,7 @@ struct RunChain {
       const int nt = pl->tune.block_threads;
       const unsigned g = (unsigned)std::max<int64_t>(
           1, std::min<int64_t>(resident_blocks(pl->ncu, nt, pl->lds_chain, kWavesPerSimd), nmid));
+      if (!count) SG_TRY(mark(pl, 1, false, st));
       if (count)
         hipLaunchKernelGGL((k_chain_mid<K, true>), dim3(g), dim3(nt), pl->lds_chain, st, Pc, pl->chains, q,
                            pl->chain_ts, pl->gstat);
@@ -772,6 +775,7 @@ struct RunChain {
         hipLaunchKernelGGL((k_chain_mid<K, false>), dim3(g), dim3(nt), pl->lds_chain, st, Pc, pl->chains, q,
                            pl->chain_ts, pl->gstat);
       SG_HIP(hipGetLastError());
+      if (!count) SG_TRY(mark(pl, 1, true, st));
     }
     return SG_OK;
   }
