@@ -32,13 +32,21 @@ import numpy as np
 from . import binding as B
 
 
+_staging = None
+
+
 def sources_frontier(sources, n: int, stream=None):
-    """X_0: the n x k boolean frontier with sources[c] in column c, built on the device."""
+    """X_0: the n x k boolean frontier with sources[c] in column c, built on the device
+    from one host-to-device copy of its triples."""
     import torch
+    from .serve import PinnedStaging
+    global _staging
+    if _staging is None:
+        _staging = PinnedStaging()
     src = np.asarray(sources, dtype=np.int32)
     k = int(src.size)
-    host = torch.from_numpy(np.concatenate([src, np.arange(k, dtype=np.int32)])).pin_memory()
-    dev = host.to("cuda", non_blocking=True)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    dev = _staging.to_device(np.concatenate([src, np.arange(k, dtype=np.int32)]), "cuda", st)
     return B.coo_to_sparse("or_and_bool", dev[:k], dev[k:], None, n, k, "csc", stream=stream)
 
 

@@ -331,7 +331,11 @@ __device__ void chain_mid(const Plan &P, const ChainDev *chains, int64_t v, uint
   const OutDev O = uload(P.outs + C.group);
   const int64_t base = out_offset(P, v);
   const int64_t cnt = gload(P.ov_cnt + v);
-  chk_count(P, tid == 0 && ((cnt > 0 && k2[cnt - 1] == 0xFFFFFFFFu) || (cnt < ts && k2[cnt] != 0xFFFFFFFFu)));
+  if constexpr (SG_CHECK) {
+    // exactly cnt keys: slot cnt - 1 holds one, slot cnt is empty (read before any slot is cleared)
+    chk_count(P, tid == 0 && ((cnt > 0 && k2[cnt - 1] == 0xFFFFFFFFu) || (cnt < ts && k2[cnt] != 0xFFFFFFFFu)));
+    __syncthreads();
+  }
   for (int i = tid; i < ts; i += nt) {
     if (i < cnt) {
       gstore(O.idx + base + i, (int32_t)(k2[i] - 1u));

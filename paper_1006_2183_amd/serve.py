@@ -146,10 +146,40 @@ def latency_stats(reqs: Sequence[Request]) -> Dict[str, float]:
 
 
 # ---------------------------------------------------------------------------
+class PinnedStaging:
+    """A reusable pinned host buffer for host-to-device copies on one stream: grown
+    (allocated) only when a larger copy comes; before it is overwritten, the host
+    waits for the event of the previous copy (normally long complete), so copies
+    never read a buffer the host is rewriting. No per-copy pinned allocation, whose
+    release could synchronise the device."""
+
+    def __init__(self):
+        self.buf = None
+        self.done = None
+
+    def to_device(self, arr: np.ndarray, device, stream):
+        import torch
+        if self.done is not None:
+            self.done.synchronize()
+        n = arr.size
+        if self.buf is None or self.buf.numel() < n:
+            self.buf = torch.empty(max(n, 1024), dtype=torch.int32, pin_memory=True)
+        self.buf[:n].numpy()[:] = arr
+        with torch.cuda.stream(stream):
+            dev = self.buf[:n].to(device, non_blocking=True)
+            self.done = torch.cuda.Event()
+            self.done.record(stream)
+        return dev
+
+
 class GpuBatchExecutor:
     """Each batch is one grouped product: C_r = A (x) X_r for every request r of
     the batch, planned together and run as one persistent launch on one of
-    `nstreams` streams (round robin)."""
+    `nstreams` streams (round robin). Request operands must be complete on the
+    device when submitted; the executor synchronises once when it is created,
+    and never makes its streams wait on the caller's stream per batch (on ROCm
+    an event of the legacy default stream waits for every stream's work, which
+    would serialise the batches)."""
 
     def __init__(self, semiring: str, A, out_fmt: Optional[str] = None, tuning=None, nstreams: int = 2,
                  timing: bool = False):
@@ -165,6 +195,7 @@ class GpuBatchExecutor:
         self.next = 0
         self.timing = timing
         self.intervals = []  # with timing: (stream index, start event, end event) per batch
+        torch.cuda.synchronize()
 
     def launch(self, batch: Sequence[Request]):
         torch = self.torch
@@ -172,7 +203,6 @@ class GpuBatchExecutor:
         s = self.streams[si]
         self.next += 1
         n = len(batch)
-        s.wait_stream(torch.cuda.current_stream())  # operands written on the caller's stream
         with torch.cuda.stream(s):
             if self.timing:
                 t0 = torch.cuda.Event(enable_timing=True)
@@ -270,18 +300,19 @@ class FrontierBatchExecutor:
         from . import binding as B
         self.B, self.torch, self.A, self.tuning = B, torch, A, tuning
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.staging = [PinnedStaging() for _ in range(nstreams)]
         self.next = 0
         self.timing = timing
         self.intervals = []
+        torch.cuda.synchronize()
 
-    def _build(self, fronts, s):
+    def _build(self, fronts, s, si=0):
         torch = self.torch
         ks = [f.k for f in fronts]
         off = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
         rows = np.concatenate([f.rows for f in fronts]).astype(np.int32)
         cols = np.concatenate([f.cols.astype(np.int64) + off[i] for i, f in enumerate(fronts)]).astype(np.int32)
-        host = torch.from_numpy(np.concatenate([rows, cols])).pin_memory()
-        dev = host.to(self.A.ptr.device, non_blocking=True)  # one copy, ordered on stream s
+        dev = self.staging[si].to_device(np.concatenate([rows, cols]), self.A.ptr.device, s)  # one copy on s
         n = rows.size
         X = self.B.coo_to_sparse("or_and_bool", dev[:n], dev[n:], None, self.A.nrows, int(off[-1]), "csc", stream=s)
         return X, off
@@ -295,7 +326,7 @@ class FrontierBatchExecutor:
             if self.timing:
                 t0 = torch.cuda.Event(enable_timing=True)
                 t0.record(s)
-            X, off = self._build([r.X for r in batch], s)
+            X, off = self._build([r.X for r in batch], s, si)
             plan = self.B.spgemm_symbolic("or_and_bool", [self.A], [X], out_fmt="csc", tuning=self.tuning, stream=s)
             (Y,) = plan.alloc_outputs(self.A.ptr.device)
             self.B.spgemm_batched(plan, [Y], s)
