@@ -443,6 +443,23 @@ sg_status sg_convert_workspace_size(const sg_semiring *sr, const sg_mat *M, int3
 sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *ws, size_t ws_bytes, sg_mat_out *out,
                      int64_t *nvec_out, void *stream);
 
+/*
+ * sg_convert for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same format change and the same results, with the workspace taken
+ * from a fixed device array of this library instead of a caller buffer
+ * (sg_convert_static_bytes() bytes, 64 MiB, one array per GPU, held until
+ * the process ends; its device address is looked up once per GPU). The call
+ * allocates nothing. A matrix whose workspace (sg_convert_workspace_size)
+ * exceeds the array is refused with SG_ERR_WORKSPACE and a message in
+ * sg_last_error. All calls on one GPU share the array: calls that overlap on
+ * one GPU (other streams or threads) race and must be serialised by the
+ * caller. Arguments and the other errors as sg_convert.
+ */
+sg_status sg_convert_static(const sg_semiring *sr, const sg_mat *M, int32_t fmt, sg_mat_out *out,
+                            int64_t *nvec_out, void *stream);
+size_t sg_convert_static_bytes(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,8 @@ EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_
            "sg_spgemm_numeric", "sg_spgemm_batched", "sg_plan_profile", "sg_plan_kernel_times", "sg_plan_destroy",
            "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked", "sg_coo_workspace_size",
            "sg_coo_compress", "sg_coo_emit", "sg_convert_workspace_size", "sg_convert", "sg_spgemm_symbolic_masked",
-           "sg_mask_set", "sg_chain_workspace_size", "sg_chain_symbolic"]
+           "sg_mask_set", "sg_chain_workspace_size", "sg_chain_symbolic", "sg_convert_static",
+           "sg_convert_static_bytes"]
 
 
 class SgError(RuntimeError):
@@ -166,6 +167,10 @@ def load_library(path: Optional[str] = None):
     lib.sg_chain_symbolic.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), P(sg_mat), ctypes.c_int32,
                                       P(sg_tuning), ctypes.c_void_p, ctypes.c_size_t, P(ctypes.c_void_p), P(sg_sym_info),
                                       ctypes.c_void_p]
+    lib.sg_convert_static.restype = ctypes.c_int
+    lib.sg_convert_static.argtypes = [P(sg_semiring), P(sg_mat), ctypes.c_int32, P(sg_mat_out), P(i64), vp]
+    lib.sg_convert_static_bytes.restype = ctypes.c_size_t
+    lib.sg_convert_static_bytes.argtypes = []
     lib.sg_mask_set.restype = ctypes.c_int
     lib.sg_mask_set.argtypes = [ctypes.c_int32, P(sg_mat), P(sg_mask), ctypes.c_void_p]
     lib.sg_convert.restype = ctypes.c_int
@@ -620,3 +625,29 @@ def chain_symbolic(semiring: str, Xs: Sequence[DevMat], Ys: Sequence[DevMat], Zs
                 stream)
     plan.operands = (list(Xs), list(Ys), list(Zs))  # the plan refers to all three
     return plan
+
+
+def convert_into(semiring: str, M: DevMat, out: DevMat, static: bool = False, stream=None) -> int:
+    """M in the format of the caller-allocated `out` (capacities: M's entries; doubly
+    compressed output at least min(nnz, major) vectors). static=True uses the
+    library's fixed workspace (sg_convert_static: no allocation at all); otherwise a
+    workspace tensor is allocated. Returns the output's stored vectors."""
+    torch = _torch()
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    d = M.desc()
+    desc = _out_descs([out])
+    nv = ctypes.c_int64(0)
+    if static:
+        _check(lib.sg_convert_static(ctypes.byref(sr), ctypes.byref(d), FORMATS[out.fmt], desc, ctypes.byref(nv),
+                                     _stream(stream)), "sg_convert_static")
+        return int(nv.value)
+    sz = ctypes.c_size_t(0)
+    _check(lib.sg_convert_workspace_size(ctypes.byref(sr), ctypes.byref(d), FORMATS[out.fmt], ctypes.byref(sz)),
+           "sg_convert_workspace_size")
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=M.ptr.device)
+    _check(lib.sg_convert(ctypes.byref(sr), ctypes.byref(d), FORMATS[out.fmt], ws.data_ptr(), ws.numel(), desc,
+                          ctypes.byref(nv), _stream(stream)), "sg_convert")
+    out._keep = ws
+    return int(nv.value)

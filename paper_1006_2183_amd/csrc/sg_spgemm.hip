@@ -2007,3 +2007,51 @@ sg_status sg_convert(const sg_semiring *sr, const sg_mat *M, int32_t fmt, void *
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Format change without any allocation: the workspace is a fixed device
+// array of this library (one per GPU), for callers that cannot allocate.
+#define SG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) char scratch[SG_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (its host-side name
+// is only a stand-in), looked up once per device.
+sg_status scratch_address(void **out) {
+  int dev = 0;
+  SG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SG_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    SG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SG_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SG_OK;
+}
+}  // namespace
+
+extern "C" sg_status sg_convert_static(const sg_semiring *sr, const sg_mat *M, int32_t fmt, sg_mat_out *out,
+                                       int64_t *nvec_out, void *stream) {
+  if (!sr || !M || !out || !fmt_ok(fmt)) return SG_ERR_INVALID_ARG;
+  SG_TRY(check_mat(*M, sr->kind));
+  const int64_t out_major = row_major(fmt) ? M->nrows : M->ncols;
+  const size_t need = carve_conv(nullptr, M->nnz, M->nvec, out_major, slot_bytes(sr->kind)).bytes;
+  if (need > SG_STATIC_SCRATCH_BYTES) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "sg_convert_static: this matrix needs %zu bytes of workspace, the static workspace holds %zu", need,
+             (size_t)SG_STATIC_SCRATCH_BYTES);
+    return SG_ERR_WORKSPACE;
+  }
+  void *ws = nullptr;
+  SG_TRY(scratch_address(&ws));
+  return sg_convert(sr, M, fmt, ws, SG_STATIC_SCRATCH_BYTES, out, nvec_out, stream);
+}
+
+extern "C" size_t sg_convert_static_bytes(void) { return SG_STATIC_SCRATCH_BYTES; }
