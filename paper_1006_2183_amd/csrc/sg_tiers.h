@@ -423,7 +423,7 @@ __device__ __forceinline__ int64_t out_offset(const Plan &P, int64_t v) {
 // ---------------------------------------------------------------------------
 // Tiny tier: one wavefront, at most 64 products.
 template <int K, bool COUNT>
-__device__ void tiny_vector(const Plan &P, int64_t v) {
+__device__ __forceinline__ void tiny_vector(const Plan &P, int64_t v) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   const int l = lane();
@@ -519,7 +519,7 @@ __device__ __forceinline__ int64_t tiny_chunk(int64_t n, int64_t waves) {
 }
 
 template <int K, bool COUNT>
-__device__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
+__device__ __forceinline__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   const int l = lane();
@@ -659,7 +659,10 @@ __device__ __forceinline__ int64_t align2(int64_t w) { return (w + 1) & ~(int64_
 // the whole range (mid tier); else only the products in split buckets
 // [b0, b1) are taken. COUNT writes the number of entries to ov_cnt[v]; the
 // numeric variant writes them at out_pos.
-template <class SR>
+// MASKED: the output mask removed ids from the bitmap, so products of those
+// ids are skipped (a separate instantiation: the unmasked walk keeps no test
+// in its innermost loop).
+template <class SR, bool MASKED = false>
 struct RankAcc {
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
@@ -669,7 +672,6 @@ struct RankAcc {
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
-  bool masked;  // the output mask removed ids from the bitmap: skip their products
   __device__ __forceinline__ uint64_t prep(int id) const {
     const uint32_t r = (uint32_t)(id - lo32);
     return *(const uint64_t *)((const char *)words + ((r >> 2) & ~7u));  // the pair of word r / 32
@@ -678,7 +680,7 @@ struct RankAcc {
     const uint32_t r = (uint32_t)(id - lo32);
     const uint32_t bits = (uint32_t)tok;
     const uint32_t pre = (uint32_t)(tok >> 32);
-    if (masked && !((bits >> (r & 31)) & 1u)) return;
+    if (MASKED && !((bits >> (r & 31)) & 1u)) return;
     // set bits of the word below bit r % 32 (the field width is taken mod 32)
     SR::acc(&vals[pre + __popc(__builtin_amdgcn_ubfe(bits, 0u, r))], x);
   }
@@ -752,7 +754,7 @@ __device__ __forceinline__ int64_t rank_load_kept(const uint32_t *src, int nwds,
 }
 
 template <int K, bool COUNT, bool WHOLE = false, bool RECS = false>
-__device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
+__device__ __forceinline__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi, int b0, int b1, int64_t out_pos,
                             uint32_t *lds, int64_t *scratch, const uint32_t *kept = nullptr, int64_t rb = -1,
                             int32_t nrec = 0) {
   typedef Sr<K> SR;
@@ -899,11 +901,14 @@ __device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi,
     cnt = total;
     __syncthreads();
   }
-  RankAcc<SR> accum{words, vals, lo32, mk.on()};
-  if (RECS && rb >= 0) {
-    for_products_recs<SR>(P, rb, nrec, wid, nw, accum);
+  if (mk.on()) {
+    RankAcc<SR, true> accum{words, vals, lo32};
+    if (RECS && rb >= 0) for_products_recs<SR>(P, rb, nrec, wid, nw, accum);
+    else for_products<SR>(P, v, b0, b1, wid, nw, accum);
   } else {
-    for_products<SR>(P, v, b0, b1, wid, nw, accum);
+    RankAcc<SR, false> accum{words, vals, lo32};
+    if (RECS && rb >= 0) for_products_recs<SR>(P, rb, nrec, wid, nw, accum);
+    else for_products<SR>(P, v, b0, b1, wid, nw, accum);
   }
   __syncthreads();
   // emit in three coalesced passes: the values are already dense by rank;
@@ -963,7 +968,7 @@ __device__ int64_t rank_window(const Plan &P, int64_t v, int64_t lo, int64_t hi,
 __device__ __forceinline__ uint32_t hash_id(uint32_t id, int logts) { return (id * 0x9E3779B1u) >> (32 - logts); }
 
 template <int K, bool COUNT>
-__device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+__device__ __forceinline__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   typedef typename SR::Slot Slot;
@@ -1046,7 +1051,7 @@ __device__ void mid_hash_vector(const Plan &P, int64_t v, uint32_t *lds, int64_t
 // Heavy tier, dense LDS accumulator (flag bit + value per id) over the ids
 // [lo, hi) of split bucket c. COUNT returns the number of entries.
 template <int K, bool COUNT>
-__device__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int64_t hi, int64_t out_pos,
+__device__ __forceinline__ int64_t dense_window(const Plan &P, int64_t v, int c, int64_t lo, int64_t hi, int64_t out_pos,
                                 uint32_t *lds, int64_t *scratch, int wcap) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
@@ -1206,7 +1211,7 @@ __device__ void heavy_count(const Plan &P, int64_t q, uint32_t *lds, int64_t *sc
 // Numeric pass of one planned heavy window (MODE 2: either window kind).
 // `it` is wave-uniform; the item's descriptor is one scalar load.
 template <int K, int MODE, bool RECS>
-__device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
+__device__ __forceinline__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *scratch) {
   const ItemDev I = uload(P.items + it);
   const GroupDev G = uload(P.groups + I.g);
   const int64_t lo = (int64_t)I.b0 * G.sw;
@@ -1230,7 +1235,7 @@ __device__ void heavy_item(const Plan &P, int64_t it, uint32_t *lds, int64_t *sc
 
 // Numeric pass of one mid-tier vector (either accumulator).
 template <int K>
-__device__ void mid_item(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+__device__ __forceinline__ void mid_item(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
   if (P.mid_kind == 0) {
     const int64_t n = rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1,
                                                   out_offset(P, v), lds, scratch);

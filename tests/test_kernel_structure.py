@@ -10,6 +10,13 @@ hang). This test checks the assembly: no loop header lies between the
 atomic and its two barriers (the atomic sits in the queue loop, which is
 the outermost loop or, for the per-XCD queues, the loop inside the one over
 the XCDs' queues).
+
+A second check: no kernel calls a device function. The kernels take the plan
+descriptor by value and the tier functions take it by reference; a call that
+is not inlined makes the compiler copy the whole descriptor into per-lane
+scratch memory at kernel entry and read every field from there, which
+slowed the single persistent launch by about a quarter when the output-mask
+code pushed the tier functions past the inliner's size limit.
 """
 import os
 import re
@@ -20,6 +27,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_1006_2183_amd", "csrc", "sg_spgemm.hip")
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    return _asm(str(tmp_path_factory.mktemp("asm")))
 
 
 def _asm(tmp_path):
@@ -54,10 +66,25 @@ def queue_loop_report(asm: str):
     return rows
 
 
-def test_queue_loops_stay_convergent(tmp_path):
-    rows = queue_loop_report(_asm(str(tmp_path)))
+def test_queue_loops_stay_convergent(asm):
+    rows = queue_loop_report(asm)
     # 4 semirings x (mid count and numeric, heavy count per window kind, heavy numeric per window kind
     # plus rank windows with entry records, batched per kind set plus the two with rank windows and records)
     assert len(rows) == 48, f"expected 48 queue kernels, found {len(rows)}"
     bad = [r for r in rows if not r[1]]
     assert not bad, "queue loop restructured: " + "; ".join(f"{n}: {why}" for n, _, why in bad)
+
+
+def calls_report(asm: str):
+    """(kernel, called symbols) for every kernel whose body makes a call."""
+    rows = []
+    for m in re.finditer(r"^(_ZN2sg\d+k_\S*):.*?s_endpgm", asm, re.S | re.M):
+        body = m.group(0)
+        if "s_swappc_b64" in body:
+            rows.append((m.group(1), sorted(set(re.findall(r"(_Z\w+)@rel32@lo", body)))))
+    return rows
+
+
+def test_kernels_make_no_calls(asm):
+    bad = calls_report(asm)
+    assert not bad, "kernels calling device functions: " + "; ".join(f"{k} -> {c}" for k, c in bad)
