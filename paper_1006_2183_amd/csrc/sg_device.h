@@ -184,6 +184,8 @@ struct Plan {
   int32_t *rec_len;          //   their count
   void *rec_sv;              //   the entry's S value
   int64_t rec_cap;           // records the workspace holds
+  const int64_t *mid_rb;     // mid-tier vector i (mid_list order): its first record, or -1 (plain walk)
+  const int32_t *mid_nrec;   //   its record count (its stored S entries)
   int64_t *chk;              // invariant-check counters (the plan's counters; written only by SG_CHECK builds)
   int32_t mid_cap;           // max entries of a mid-tier vector
   int32_t mid_kind;          // 0 bitmap-rank, 1 hash

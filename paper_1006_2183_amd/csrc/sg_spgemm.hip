@@ -248,6 +248,8 @@ struct Layout {
   int64_t zero_words;  // int64 words from `counters` on that start at zero
   int32_t *vsent;
   int64_t *rcnt, *rbase;
+  int64_t *mcnt, *mbase, *mid_rb;  // mid-tier records: counts, their scan, final bases
+  int32_t *mid_nrec;
   int64_t *rec_gi, *rec_gv;
   int32_t *rec_len;
   void *rec_sv;
@@ -364,12 +366,13 @@ void make_shape(int32_t kind, int32_t nprod, const sg_mat *A, const sg_mat *B, c
   }
   sh.slot_bytes = slot_bytes(kind);
   if (sh.hstride > 0 && t.entry_mb > 0) {  // rank windows exist
-    // at most one record per streamed entry and window, at most nbmax
-    // windows per vector; the budget caps the rest
+    // at most one record per streamed entry and window (at most nbmax
+    // windows per heavy vector), or per streamed entry of a mid-tier
+    // vector; the budget caps the rest
     int64_t sent = 0;
     for (int32_t p = 0; p < nprod; ++p) sent += view(A[p], B[p]).S->nnz;
     const int64_t per = 20 + slot_bytes(kind);  // two addresses, a count, the S value
-    sh.rec_cap = std::min<int64_t>(((int64_t)t.entry_mb << 20) / per, sent * (int64_t)sh.nbmax);
+    sh.rec_cap = std::min<int64_t>(((int64_t)t.entry_mb << 20) / per, sent * ((int64_t)sh.nbmax + 1));
   }
 
   // products whose gathered operand is the same arrays share the AUX index,
@@ -466,6 +469,10 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
     L.vsent = c.take<int32_t>(nov + 1);
     L.rcnt = c.take<int64_t>(nov + 1);
     L.rbase = c.take<int64_t>(nov + 1);
+    L.mcnt = c.take<int64_t>(nov + 1);
+    L.mbase = c.take<int64_t>(nov + 1);
+    L.mid_rb = c.take<int64_t>(nov + 1);
+    L.mid_nrec = c.take<int32_t>(nov + 1);
     L.rec_gi = c.take<int64_t>(sh.rec_cap);
     L.rec_gv = c.take<int64_t>(sh.rec_cap);
     L.rec_len = c.take<int32_t>(sh.rec_cap);
@@ -473,6 +480,8 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   } else {
     L.vsent = nullptr;
     L.rcnt = L.rbase = L.rec_gi = L.rec_gv = nullptr;
+    L.mcnt = L.mbase = L.mid_rb = nullptr;
+    L.mid_nrec = nullptr;
     L.rec_len = nullptr;
     L.rec_sv = nullptr;
   }
@@ -723,6 +732,14 @@ template <int K>
 struct RunItemRecs {
   static sg_status run(const Plan &P, int ncu, hipStream_t st) {
     hipLaunchKernelGGL((k_item_recs<K>), dim3((unsigned)ncu * 16), dim3(256), 0, st, P);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+  }
+};
+template <int K>
+struct RunMidRecs {
+  static sg_status run(const Plan &P, int ncu, hipStream_t st) {
+    hipLaunchKernelGGL((k_mid_recs<K>), dim3((unsigned)ncu * 16), dim3(256), 0, st, P);
     SG_HIP(hipGetLastError());
     return SG_OK;
   }
@@ -1128,6 +1145,8 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
   P.rec_len = L.rec_len;
   P.rec_sv = L.rec_sv;
   P.rec_cap = sh.rec_cap;
+  P.mid_rb = L.mid_rb;
+  P.mid_nrec = L.mid_nrec;
   P.chk = L.counters;
   P.mid_cap = t.mid_max_ub;
   P.mid_kind = t.mid_kind;
@@ -1186,7 +1205,18 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
   hipLaunchKernelGGL(k_plan_fill, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
                      L.ibase, sh.nov_max, L.items, L.counters, L.rbase, L.vsent);
   SG_HIP(hipGetLastError());
-  if (sh.rec_cap > 0) SG_TRY(dispatch<RunItemRecs>(sr->kind, P, pl->ncu, st));
+  if (sh.rec_cap > 0) {
+    SG_TRY(dispatch<RunItemRecs>(sr->kind, P, pl->ncu, st));
+    // the mid-tier vectors' records follow the heavy items' ones
+    hipLaunchKernelGGL(k_mid_rec_count, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                       sh.nov_max, L.mcnt);
+    SG_HIP(hipGetLastError());
+    SG_TRY(scan64(L.mcnt, sh.nov_max, L.mbase, L.part, L.part_cap, st));
+    hipLaunchKernelGGL(k_mid_rec_base, dim3((unsigned)grid_for(sh.nov_max, kFillThreads)), dim3(kFillThreads), 0, st, P,
+                       sh.nov_max, L.rbase + sh.nov_max, L.mcnt, L.mbase, L.mid_rb, L.mid_nrec);
+    SG_HIP(hipGetLastError());
+    SG_TRY(dispatch<RunMidRecs>(sr->kind, P, pl->ncu, st));
+  }
 
   SG_HIP(hipMemcpyAsync(pl->host_stats.data(), L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount,
                         hipMemcpyDeviceToHost, st));

@@ -664,51 +664,104 @@ __global__ void k_rec_count(Plan P, const int64_t *nwin, int64_t cap, int32_t *v
   }
 }
 
-// One wavefront per heavy item with records: the G range of every stored S
-// entry of the vector inside the item's buckets, and the entry's S value,
-// in the order the product walk visits them.
+// The records of output vector v from record rb on: the G range of every
+// stored S entry of the vector (inside split buckets [b0, b1), or the whole
+// G vector for b0 < 0), and the entry's S value, in the order the product
+// walk visits them. One wavefront, lanes over the entries.
 template <int K>
-__global__ void k_item_recs(Plan P) {
+__device__ __forceinline__ void vector_recs(const Plan &P, int64_t v, int32_t b0, int32_t b1, int64_t rb) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   const int l = lane();
+  int64_t j = 0;
+  const int64_t s1 = uload(P.ov_seg + v + 1);
+  for (int64_t s = uload(P.ov_seg + v); s < s1; ++s) {
+    const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+    const int32_t t = uload(P.seg_svec + s);
+    const int64_t e0 = uload(d.s_ptr + t), e1 = uload(d.s_ptr + t + 1);
+    for (int64_t e = e0 + l; e < e1; e += kWave) {
+      const int32_t k = gload(d.s_idx + e);
+      const int32_t gt = d.gres ? gload(d.gres + e) : ((k >= 0 && k < d.g_nvec) ? k : -1);
+      int64_t g = 0;
+      int32_t len = 0;
+      if (gt >= 0) {
+        const int64_t p0 = gload(d.g_ptr + gt);
+        if (b0 >= 0 && d.wsplit) {
+          const int32_t *ws = d.wsplit + (int64_t)gt * (d.nsplit + 1);
+          const int32_t a = gload(ws + b0);
+          g = p0 + a;
+          len = gload(ws + b1) - a;
+        } else {
+          g = p0;
+          len = (int32_t)(gload(d.g_ptr + gt + 1) - p0);
+        }
+      }
+      const int64_t x = rb + j + (e - e0);
+      gstore(P.rec_gi + x, (int64_t)(d.g_idx + g));
+      if (SR::kVal) gstore(P.rec_gv + x, (int64_t)((const T *)d.g_val + g));
+      gstore(P.rec_len + x, len);
+      if (SR::kVal) gstore((T *)P.rec_sv + x, gload((const T *)d.s_val + e));
+    }
+    j += e1 - e0;
+  }
+}
+
+// One wavefront per heavy item with records (the G ranges inside the item's
+// buckets).
+template <int K>
+__global__ void k_item_recs(Plan P) {
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int64_t n = P.counters[kCtItems];
   for (int64_t it = wave; it < n; it += nwaves) {
     const ItemDev I = uload(P.items + it);
     if (I.rbase < 0) continue;
-    int64_t j = 0;
-    const int64_t s1 = uload(P.ov_seg + I.v + 1);
-    for (int64_t s = uload(P.ov_seg + I.v); s < s1; ++s) {
-      const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
-      const int32_t t = uload(P.seg_svec + s);
-      const int64_t e0 = uload(d.s_ptr + t), e1 = uload(d.s_ptr + t + 1);
-      for (int64_t e = e0 + l; e < e1; e += kWave) {
-        const int32_t k = gload(d.s_idx + e);
-        const int32_t gt = d.gres ? gload(d.gres + e) : ((k >= 0 && k < d.g_nvec) ? k : -1);
-        int64_t g = 0;
-        int32_t len = 0;
-        if (gt >= 0) {
-          const int64_t p0 = gload(d.g_ptr + gt);
-          if (d.wsplit) {
-            const int32_t *ws = d.wsplit + (int64_t)gt * (d.nsplit + 1);
-            const int32_t a = gload(ws + I.b0);
-            g = p0 + a;
-            len = gload(ws + I.b1) - a;
-          } else {
-            g = p0;
-            len = (int32_t)(gload(d.g_ptr + gt + 1) - p0);
-          }
-        }
-        const int64_t x = I.rbase + j + (e - e0);
-        gstore(P.rec_gi + x, (int64_t)(d.g_idx + g));
-        if (SR::kVal) gstore(P.rec_gv + x, (int64_t)((const T *)d.g_val + g));
-        gstore(P.rec_len + x, len);
-        if (SR::kVal) gstore((T *)P.rec_sv + x, gload((const T *)d.s_val + e));
+    vector_recs<K>(P, I.v, I.b0, I.b1, I.rbase);
+  }
+}
+
+// Records of the mid-tier vectors: per mid vector i its stored S entries
+// (mcnt, scanned into mbase), placed after the heavy items' records (whose
+// total is *heavy_total).
+__global__ void k_mid_rec_count(Plan P, int64_t cap, int64_t *mcnt) {
+  const int64_t nm = P.counters[kCtMid];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t ns = 0;
+    if (i < nm) {
+      const int32_t v = P.mid_list[i];
+      for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
+        const ProdDev &d = P.prods[P.seg_prod[s]];
+        const int32_t t = P.seg_svec[s];
+        ns += d.s_ptr[t + 1] - d.s_ptr[t];
       }
-      j += e1 - e0;
     }
+    mcnt[i] = ns <= INT32_MAX ? ns : 0;
+  }
+}
+
+// A mid vector keeps its records when all of them fit the workspace.
+__global__ void k_mid_rec_base(Plan P, int64_t cap, const int64_t *heavy_total, const int64_t *mcnt,
+                               const int64_t *mbase, int64_t *mid_rb, int32_t *mid_nrec) {
+  const int64_t nm = P.counters[kCtMid];
+  const int64_t h = *heavy_total;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r0 = h + mbase[i];
+    const bool ok = i < nm && mcnt[i] > 0 && r0 + mcnt[i] <= P.rec_cap;
+    mid_rb[i] = ok ? r0 : -1;
+    mid_nrec[i] = ok ? (int32_t)mcnt[i] : 0;
+  }
+}
+
+// One wavefront per mid vector with records (whole G vectors).
+template <int K>
+__global__ void k_mid_recs(Plan P) {
+  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t n = P.counters[kCtMid];
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const int64_t rb = uload(P.mid_rb + i);
+    if (rb < 0) continue;
+    vector_recs<K>(P, uload(P.mid_list + i), -1, -1, rb);
   }
 }
 

@@ -387,14 +387,22 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
 // slice inside the window and its S value) instead of the segment's
 // descriptors, the entry, its G vector and its window split points in turn.
 // Records name addresses, so a vector fed by several products (a SUMMA
-// share's stage products) walks them as one list.
+// share's stage products) walks them as one list. With at least as many
+// batches as wavefronts, the batches are dealt to the wavefronts round robin
+// and each takes all products of its own batches, so the chains of record
+// and gather loads run side by side instead of one batch after another;
+// with fewer, every wavefront walks every batch and takes its slice of the
+// batch's products.
 template <class SR, class Act>
 __device__ __forceinline__ void for_products_recs(const Plan &P, int64_t rb, int32_t nrec, int wid, int nw,
                                                   Act &act) {
   typedef typename SR::T T;
   static_assert(Act::kFlat, "records feed the flat walk");
   const int uw = uni(wid);
-  for (int64_t eb = 0; eb < nrec; eb += kWave) {
+  const int64_t nbatch = ((int64_t)nrec + kWave - 1) / kWave;
+  const bool many = nbatch >= nw;
+  const int sid = many ? 0 : uw, sn = many ? 1 : nw;
+  for (int64_t eb = (many ? uw : 0) * (int64_t)kWave; eb < nrec; eb += (many ? nw : 1) * (int64_t)kWave) {
     const int64_t x = rb + eb + lane();
     const bool ok = eb + lane() < nrec;
     const int len = ok ? gload(P.rec_len + x) : 0;
@@ -404,8 +412,8 @@ __device__ __forceinline__ void for_products_recs(const Plan &P, int64_t rb, int
     const int incl = wave_incl_scan(len);
     const int tot = read_lane(incl, kWave - 1);
     if (tot == 0) continue;
-    const int f0 = (int)((int64_t)tot * uw / nw);
-    const int f1 = (int)((int64_t)tot * (uw + 1) / nw);
+    const int f0 = (int)((int64_t)tot * sid / sn);
+    const int f1 = (int)((int64_t)tot * (sid + 1) / sn);
     const int st = incl - len;
     const int a = st > f0 ? st : f0;
     const int e = incl < f1 ? incl : f1;
@@ -801,7 +809,8 @@ __device__ __forceinline__ int64_t rank_window(const Plan &P, int64_t v, int64_t
       atomicOr(&words[WS * w], 1u << (r & 31));
       atomicOr(&top[w >> 5], 1u << (w & 31));
     });
-    for_products<SR>(P, v, b0, b1, wid, nw, mark);
+    if (RECS && rb >= 0) for_products_recs<SR>(P, rb, nrec, wid, nw, mark);
+    else for_products<SR>(P, v, b0, b1, wid, nw, mark);
     __syncthreads();
     int local = 0;
     for (int tw = tw0; tw < tw1; ++tw) {
@@ -1233,12 +1242,17 @@ __device__ __forceinline__ void heavy_item(const Plan &P, int64_t it, uint32_t *
   }
 }
 
-// Numeric pass of one mid-tier vector (either accumulator).
-template <int K>
-__device__ __forceinline__ void mid_item(const Plan &P, int64_t v, uint32_t *lds, int64_t *scratch) {
+// Numeric pass of mid-tier vector m (position in the mid list; either
+// accumulator). RECS: the plan may hold the vector's entry records, which
+// both passes of the rank accumulator then walk instead of the descriptors.
+template <int K, bool RECS>
+__device__ __forceinline__ void mid_item(const Plan &P, int64_t m, uint32_t *lds, int64_t *scratch) {
+  const int64_t v = uload(P.mid_list + m);
   if (P.mid_kind == 0) {
-    const int64_t n = rank_window<K, false, true>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1, -1,
-                                                  out_offset(P, v), lds, scratch);
+    const int64_t rb = RECS && P.mid_rb ? uload(P.mid_rb + m) : -1;
+    const int32_t nrec = rb >= 0 ? uload(P.mid_nrec + m) : 0;
+    const int64_t n = rank_window<K, false, true, RECS>(P, v, 0, uload(&P.groups[uload(P.ov_group + v)].minor), -1,
+                                                        -1, out_offset(P, v), lds, scratch, nullptr, rb, nrec);
     chk_count(P, threadIdx.x == 0 && n != gload(P.ov_cnt + v));
   } else {
     mid_hash_vector<K, false>(P, v, lds, scratch);
@@ -1277,7 +1291,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_mid(Plan P, int64_
     const int64_t i = uni(s_item);
     __syncthreads();
     if (i >= n) break;
-    mid_item<K>(P, uload(P.mid_list + i), lds, scratch);
+    mid_item<K, false>(P, i, lds, scratch);
     chk_lds_zero(P, lds);
   }
 }
@@ -1401,7 +1415,7 @@ __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, in
     if (i < n_items) {
       heavy_item<K, MODE, RECS>(P, i, lds, scratch);
     } else if (i < n_items + n_mid) {
-      mid_item<K>(P, uload(P.mid_list + (i - n_items)), lds, scratch);
+      mid_item<K, RECS>(P, i - n_items, lds, scratch);
     } else {
       const int64_t c0 = uni(((i - n_items - n_mid) * nw + threadIdx.x / kWave) * csz);
       if (c0 < n_tiny) tiny_pack<K, false>(P, c0, c0 + csz < n_tiny ? c0 + csz : n_tiny);
