@@ -402,13 +402,27 @@ __device__ __forceinline__ void for_products_recs(const Plan &P, int64_t rb, int
   const int64_t nbatch = ((int64_t)nrec + kWave - 1) / kWave;
   const bool many = nbatch >= nw;
   const int sid = many ? 0 : uw, sn = many ? 1 : nw;
-  for (int64_t eb = (many ? uw : 0) * (int64_t)kWave; eb < nrec; eb += (many ? nw : 1) * (int64_t)kWave) {
-    const int64_t x = rb + eb + lane();
-    const bool ok = eb + lane() < nrec;
-    const int len = ok ? gload(P.rec_len + x) : 0;
-    const int64_t gi = ok ? gload(P.rec_gi + x) : 0;
-    const int64_t gv = (SR::kVal && ok) ? gload(P.rec_gv + x) : 0;
-    const T sv = (SR::kVal && ok) ? gload((const T *)P.rec_sv + x) : T();
+  const int64_t step = (many ? nw : 1) * (int64_t)kWave;
+  // the next batch's records are requested before this batch's gathers, so
+  // the two load levels of consecutive batches overlap
+  int64_t eb = (many ? uw : 0) * (int64_t)kWave;
+  int len_n = 0;
+  int64_t gi_n = 0, gv_n = 0;
+  T sv_n = T();
+  auto fetch = [&](int64_t b) {
+    const int64_t x = rb + b + lane();
+    const bool ok = b + lane() < nrec;
+    len_n = ok ? gload(P.rec_len + x) : 0;
+    gi_n = ok ? gload(P.rec_gi + x) : 0;
+    gv_n = (SR::kVal && ok) ? gload(P.rec_gv + x) : 0;
+    sv_n = (SR::kVal && ok) ? gload((const T *)P.rec_sv + x) : T();
+  };
+  if (eb < nrec) fetch(eb);
+  for (; eb < nrec; eb += step) {
+    const int len = len_n;
+    const int64_t gi = gi_n, gv = gv_n;
+    const T sv = sv_n;
+    if (eb + step < nrec) fetch(eb + step);
     const int incl = wave_incl_scan(len);
     const int tot = read_lane(incl, kWave - 1);
     if (tot == 0) continue;
