@@ -316,8 +316,16 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
         _same(res["batched"], res["plain"], 1e-12, "SUMMA batched vs plain")
     except AssertionError as e:
         raise AssertionError(f"{e}; {_summa_diagnose(res, sg, dA, dB, sr)}")
-    # the replayed plan keeps per-window entry records (built once by its symbolic phase)
-    replay_tuning = {"entry_mb": 1024}
+    # the replayed plan's setting comes from the tuner, timing the persistent
+    # launch alone (the replayed form): joint presets (entry records, mid-tier
+    # capacity), then a coordinate descent over the record budget and the
+    # tier thresholds
+    from paper_1006_2183_amd import autotune as AT
+    tune = AT.autotune(sr, dA, dB, [0] * len(dA), 1, out_fmt="dcsc", form="numeric_reuse", reps=3,
+                       space=AT.REPLAY_SPACE, presets=AT.REPLAY_PRESETS)
+    replay_tuning = tune["tuning"]
+    log(f"[bench] SUMMA replay tuning {replay_tuning}: {tune['ms']:.3f} ms per launch "
+        f"(default {tune['default_ms']:.3f} ms, {tune['tried']} settings)")
     plan = BT.summa_share_plan(sr, dA, dB, tuning=sg.make_tuning(sr, **replay_tuning))
     flops = sum(i["flops"] for i in plan.infos)
     nnz_c = plan.infos[0]["nnz"]
@@ -340,6 +348,8 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
         "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batched, 3), "graph_replay_ms": round(ms_graph, 3),
         "plain_GFLOPs": round(flops / ms_plain / 1e6, 2), "batched_GFLOPs": round(flops / ms_batched / 1e6, 2),
         "graph_GFLOPs": round(flops / ms_graph / 1e6, 2), "graph_plan_tuning": replay_tuning,
+        "tuner": {"form": "numeric_reuse", "settings_tried": tune["tried"], "default_launch_ms": round(tune["default_ms"], 3),
+                  "tuned_launch_ms": round(tune["ms"], 3)},
         "batched_vs_plain": round(ms_plain / ms_batched, 2), "graph_vs_plain": round(ms_plain / ms_graph, 2),
         "persistent_kernel": {"launch_ms": round(kms, 4), "algorithmic_bytes": int(algo),
                               "achieved_GBs": round(algo / kms / 1e6, 1) if kms > 0 else None},

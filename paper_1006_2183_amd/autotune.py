@@ -129,10 +129,30 @@ class _Runner:
         return ts[len(ts) // 2] * 1e3
 
 
+# Joint settings for grouped plans that are replayed (a SUMMA share, a
+# batch of Galerkin products): knobs that only pay off together, tried as
+# whole candidates before the coordinate descent starts from the best one.
+REPLAY_PRESETS: List[Dict[str, int]] = [
+    {"entry_mb": 1024},
+    {"entry_mb": 1024, "mid_max_ub": 2048},
+    {"entry_mb": 1024, "mid_max_ub": 1024},
+    {"entry_mb": 256},
+    {"entry_mb": 1024, "heavy_lds_bytes": 159744, "heavy_threads": 1024, "lds_bytes": 159744, "block_threads": 1024},
+]
+REPLAY_SPACE: Dict[str, List[int]] = {
+    "entry_mb": [0, 256, 1024],
+    "mid_max_ub": [1024, 2048, 65535],
+    "tiny_max_flops": [32, 64],
+    "bitmap_mb": [0, 4096],
+}
+
+
 def autotune(semiring: str, As: Sequence, Bs: Sequence, group=None, ngroup=None, out_fmt: Optional[str] = None,
              form: str = "numeric", space: Optional[Dict[str, List[int]]] = None, reps: int = 3, sweeps: int = 1,
-             cache: Optional[TuneCache] = None, force: bool = False, log=None) -> dict:
-    """Search ``space`` by coordinate descent from the default setting.
+             cache: Optional[TuneCache] = None, force: bool = False, log=None,
+             presets: Optional[Sequence[Dict[str, int]]] = None) -> dict:
+    """Search ``space`` by coordinate descent from the default setting (or
+    from the fastest of ``presets``, whole settings tried first).
 
     form: "numeric" (symbolic + per-tier launches), "batched" (symbolic + one
     persistent launch) or "numeric_reuse" (the persistent launch alone, as a
@@ -153,6 +173,23 @@ def autotune(semiring: str, As: Sequence, Bs: Sequence, group=None, ngroup=None,
     best = {}
     best_ms = default_ms = run.time(None)
     tried = [({}, default_ms)]
+
+    def attempt(cand):
+        try:
+            ms = run.time(B.make_tuning(semiring, **cand))
+        except B.SgError as e:  # the library refused this setting for this shape
+            if log:
+                log(f"[autotune] {cand}: {e}")
+            return None
+        tried.append((cand, ms))
+        if log:
+            log(f"[autotune] {cand}: {ms:.3f} ms")
+        return ms
+
+    for cand in presets or []:
+        ms = attempt(dict(cand))
+        if ms is not None and ms < best_ms * 0.98:
+            best, best_ms = dict(cand), ms
     for _ in range(sweeps):
         improved = False
         for field, values in space.items():
@@ -160,15 +197,9 @@ def autotune(semiring: str, As: Sequence, Bs: Sequence, group=None, ngroup=None,
                 cand = dict(best, **{field: v})
                 if cand == best:
                     continue
-                try:
-                    ms = run.time(B.make_tuning(semiring, **cand))
-                except B.SgError as e:  # the library refused this setting for this shape
-                    if log:
-                        log(f"[autotune] {cand}: {e}")
+                ms = attempt(cand)
+                if ms is None:
                     continue
-                tried.append((cand, ms))
-                if log:
-                    log(f"[autotune] {cand}: {ms:.3f} ms")
                 if ms < best_ms * 0.98:
                     best, best_ms, improved = cand, ms, True
         if not improved:

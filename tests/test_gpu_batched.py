@@ -208,6 +208,34 @@ def test_autotune_keeps_results(sg, tmp_path):
     torch.cuda.synchronize()
 
 
+def test_autotune_replay_presets_keep_results(sg):
+    """The replayed-form search (presets first, then the record budget and tier
+    thresholds) on a small SUMMA share: the chosen setting computes the
+    oracle's result, and every preset and space value is a setting the
+    library accepts for this plan."""
+    from paper_1006_2183_amd import autotune as AT
+    from paper_1006_2183_amd import batched as BT
+    semiring = "plus_times_f64"
+    scale, grid = 11, 8
+    _say("case autotune replay presets")
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (1, 2), semiring=semiring, seed=5)
+    b = (1 << scale) // grid
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
+    R, _ = oracle.spgemm(semiring, SA, SB)
+    res = AT.autotune(semiring, dA, dB, [0] * grid, 1, out_fmt="dcsc", form="numeric_reuse", reps=1,
+                      space=AT.REPLAY_SPACE, presets=AT.REPLAY_PRESETS)
+    # the default, every preset (none refused) and at least one space value were timed
+    assert res["tried"] >= 2 + len(AT.REPLAY_PRESETS)
+    plan = BT.summa_share_plan(semiring, dA, dB, tuning=sg.make_tuning(semiring, **res["tuning"]))
+    G = BT.GraphedNumeric(plan)
+    G.replay()
+    G.replay()
+    assert_same(G.outputs[0].to_host(), R, semiring, 1e-12, f"tuned replay {res['tuning']}")
+    plan.destroy()
+
+
 @pytest.mark.parametrize("force", [-1, 1, 2])
 def test_summa_share_many_segments(sg, force):
     """16 stage products per output vector (more segments than wavefronts per workgroup), every tier."""
@@ -231,12 +259,14 @@ def test_summa_share_many_segments(sg, force):
 
 @pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
 @pytest.mark.parametrize("entry_mb", [1, 2048])
-def test_summa_share_entry_records(sg, semiring, entry_mb):
-    """Heavy windows of vectors fed by 16 stage products, walked from entry records (all, or
-    some within a 1 MiB budget), per tier launch and in the persistent launch."""
+@pytest.mark.parametrize("force", [2, -1])
+def test_summa_share_entry_records(sg, semiring, entry_mb, force):
+    """Heavy windows (and, unforced, mid-tier vectors) fed by 16 stage products, walked from
+    entry records (all, or some within a 1 MiB budget), per tier launch and in the
+    persistent launch."""
     from paper_1006_2183_amd import batched as BT
-    scale, grid = 12, 16
-    _say(f"case summa share entry records {semiring} entry_mb={entry_mb}")
+    scale, grid = 16, 16  # blocks of 4096 ids: wider than one dense window, so rank windows and records
+    _say(f"case summa share entry records {semiring} entry_mb={entry_mb} force {force}")
     a_blocks, b_blocks = W.summa_share(scale, 16, grid, (3, 5), semiring=semiring, seed=17)
     b = (1 << scale) // grid
     dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
@@ -244,8 +274,8 @@ def test_summa_share_entry_records(sg, semiring, entry_mb):
     SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
     R, _ = oracle.spgemm(semiring, SA, SB)
     for batched in (False, True):
-        t = sg.make_tuning(semiring, force_tier=2, lds_bytes=24576, block_threads=512, heavy_lds_bytes=24576,
+        t = sg.make_tuning(semiring, force_tier=force, lds_bytes=24576, block_threads=512, heavy_lds_bytes=24576,
                            heavy_threads=512, entry_mb=entry_mb)
         C = BT.summa_share(semiring, dA, dB, tuning=t, batched=batched).to_host()
         assert_canonical(C)
-        assert_same(C, R, semiring, 1e-12, f"entry_mb {entry_mb} batched {batched}")
+        assert_same(C, R, semiring, 1e-12, f"entry_mb {entry_mb} batched {batched} force {force}")
