@@ -123,7 +123,10 @@ typedef struct {
  *                    one a flag bit and a value slot per id)
  *   force_tier       -1 = bin by size; 0/1/2 = route every vector with
  *                    work to the tiny / mid / heavy tier where it is legal
- *                    (tiny needs flops <= 64, mid needs the bound to fit)
+ *                    (tiny needs flops <= 64, mid needs the bound to fit);
+ *                    3 = every vector with at most 512 multiplications to
+ *                    the mid tier's one-wavefront form (small_max_flops),
+ *                    the others by size
  *   blocks_per_cu    workgroups per compute unit of the persistent launches
  *   validate         non-zero: run sg_validate on every operand first
  *   xcd_ranges       heavy tier: the output id range is cut into 8 x this
@@ -154,7 +157,16 @@ typedef struct {
  *                    list. Windows beyond the budget walk the operands (0 =
  *                    off, the default: building them costs the symbolic phase
  *                    about what they save one numeric run, so they pay only
- *                    for a plan whose numeric phase is replayed)
+ *                    for a plan whose numeric phase is replayed). Mid-tier
+ *                    vectors of a plan with records get records too.
+ *   small_max_flops  mid tier: vectors with more than tiny_max_flops and at
+ *                    most this many multiplications (<= 512) run one per
+ *                    wavefront, with no LDS and no workgroup barrier: their
+ *                    products are gathered into registers (8 per lane),
+ *                    sorted by id with a register bitonic network, merged
+ *                    and written (0 = off: every mid vector takes a
+ *                    workgroup's LDS accumulator). They count as mid-tier
+ *                    vectors in the per-tier totals (n_small of sg_sym_info).
  */
 typedef struct {
     int32_t tiny_max_flops;
@@ -172,6 +184,7 @@ typedef struct {
     int32_t heavy_threads;
     int32_t heavy_lds_bytes;
     int32_t entry_mb;
+    int32_t small_max_flops;
 } sg_tuning;
 
 /* Host-side sizes of one output, valid when sg_spgemm_symbolic returns. */
@@ -187,9 +200,10 @@ typedef struct {
     int64_t n_heavy;
     int64_t n_heavy_items; /* (vector, window) work items of the heavy tier  */
     /* totals per tier (index 0 tiny, 1 mid, 2 heavy) over the whole call:  */
-    int64_t tier_flops[3]; /* multiplications                               */
+    int64_t tier_flops[3]; /* multiplications (mid: n_mid and n_small)      */
     int64_t tier_sent[3];  /* stored entries of the streamed operand read   */
     int64_t tier_nnz[3];   /* output entries written                        */
+    int64_t n_small;       /* mid-tier vectors run one per wavefront (not in n_mid) */
 } sg_sym_info;
 
 typedef struct sg_plan sg_plan;

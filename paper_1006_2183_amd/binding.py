@@ -70,7 +70,8 @@ class sg_tuning(ctypes.Structure):
                 ("bitmap_mb", ctypes.c_int32),
                 ("heavy_threads", ctypes.c_int32),
                 ("heavy_lds_bytes", ctypes.c_int32),
-                ("entry_mb", ctypes.c_int32)]
+                ("entry_mb", ctypes.c_int32),
+                ("small_max_flops", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -79,7 +80,8 @@ class sg_tuning(ctypes.Structure):
 class sg_sym_info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("flops", "nnz_ub", "nnz", "nvec", "max_vec_flops", "n_out_vec",
                                               "n_tiny", "n_mid", "n_heavy", "n_heavy_items")] + [
-        ("tier_flops", ctypes.c_int64 * 3), ("tier_sent", ctypes.c_int64 * 3), ("tier_nnz", ctypes.c_int64 * 3)]
+        ("tier_flops", ctypes.c_int64 * 3), ("tier_sent", ctypes.c_int64 * 3), ("tier_nnz", ctypes.c_int64 * 3),
+        ("n_small", ctypes.c_int64)]
 
     def as_dict(self):
         d = {}

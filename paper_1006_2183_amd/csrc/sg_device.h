@@ -150,6 +150,7 @@ enum Counter {
   kCtTierNnz = kCtTierSent + 3,    // 3 entries: output entries per tier
   kCtChkLds = kCtTierNnz + 3,      // invariant-check build: items that left LDS non-zero
   kCtChkCount,                     // invariant-check build: numeric counts that differ from the count pass
+  kCtSmall,                        // mid-tier vectors run one per wavefront (the small list)
   kCtNum
 };
 
@@ -169,6 +170,7 @@ struct Plan {
   const int64_t *counters;
   const int32_t *tiny_list;
   const int32_t *mid_list;
+  const int32_t *small_list;   // mid-tier vectors of at most kSmallMaxFlops products, one per wavefront
   const int32_t *heavy_list;
   const struct ItemDev *items;  // heavy (vector, window) items
   int32_t *bcnt;             // heavy vector q: entries per split bucket, at q * nbmax
@@ -184,7 +186,7 @@ struct Plan {
   int32_t *rec_len;          //   their count
   void *rec_sv;              //   the entry's S value
   int64_t rec_cap;           // records the workspace holds
-  const int64_t *mid_rb;     // mid-tier vector i (mid_list order): its first record, or -1 (plain walk)
+  const int64_t *mid_rb;     // mid-tier vector at position p (mid list, then small list): its first record, or -1
   const int32_t *mid_nrec;   //   its record count (its stored S entries)
   int64_t *chk;              // invariant-check counters (the plan's counters; written only by SG_CHECK builds)
   int32_t mid_cap;           // max entries of a mid-tier vector

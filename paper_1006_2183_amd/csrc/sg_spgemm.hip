@@ -233,7 +233,7 @@ struct Layout {
   int64_t *gstat;
   int32_t *ov_id, *ov_group, *seg_prod, *seg_svec;
   int64_t *ov_seg, *ov_flops, *ov_cnt, *ov_off, *nzflag, *nzpos;
-  int32_t *tiny, *mid, *heavy;
+  int32_t *tiny, *mid, *heavy, *small;
   int64_t *heavy_nwin, *ibase;
   ItemDev *items;
   int32_t *bcnt;
@@ -422,6 +422,7 @@ Layout carve(void *ws, int32_t nprod, const sg_mat *A, const sg_mat *B, int32_t 
   L.tiny = c.take<int32_t>(nov);
   L.mid = c.take<int32_t>(nov);
   L.heavy = c.take<int32_t>(nov);
+  L.small = c.take<int32_t>(nov);
   L.heavy_nwin = c.take<int64_t>(nov * sh.nrange + 1);
   L.ibase = c.take<int64_t>(nov * sh.nrange + 1);
   const int64_t items = nov * (int64_t)sh.nbmax;
@@ -538,13 +539,14 @@ void normalise(sg_tuning &t, int32_t kind) {
   if (t.block_threads < 64 || t.block_threads > kBlockMax || t.block_threads % 64) t.block_threads = d.block_threads;
   if (t.chunk_width < 0) t.chunk_width = 0;
   if (t.heavy_kind != 0 && t.heavy_kind != 1) t.heavy_kind = 0;
-  if (t.force_tier < -1 || t.force_tier > 2) t.force_tier = -1;
+  if (t.force_tier < -1 || t.force_tier > 3) t.force_tier = -1;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) t.blocks_per_cu = d.blocks_per_cu;
   if (t.xcd_ranges < 0 || t.xcd_ranges > 16) t.xcd_ranges = d.xcd_ranges;
   if (t.bitmap_mb < 0) t.bitmap_mb = d.bitmap_mb;
   if (t.heavy_threads == 0) t.heavy_threads = t.block_threads;
   if (t.heavy_threads < 64 || t.heavy_threads > kBlockMax || t.heavy_threads % 64) t.heavy_threads = d.heavy_threads;
   if (t.entry_mb < 0) t.entry_mb = d.entry_mb;
+  if (t.small_max_flops < 0 || t.small_max_flops > kSmallMaxFlops) t.small_max_flops = d.small_max_flops;
   if (t.heavy_lds_bytes == 0) t.heavy_lds_bytes = t.lds_bytes;
   if (t.heavy_lds_bytes < 4096 || t.heavy_lds_bytes > 160 * 1024 - 2048) t.heavy_lds_bytes = d.heavy_lds_bytes;
   t.heavy_lds_bytes &= ~7;
@@ -585,6 +587,10 @@ sg_status launch_counts(sg_plan *pl, hipStream_t st) {
   const int64_t tiny_blocks = std::min<int64_t>(std::max<int64_t>(1, (pl->nov_max + 3) / 4), persist * 8);
   hipLaunchKernelGGL((k_tiny<K, true>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, pl->P);
   SG_HIP(hipGetLastError());
+  if (pl->tune.small_max_flops > 0 || pl->tune.force_tier == 3) {
+    hipLaunchKernelGGL((k_small<K, true, false>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, pl->P);
+    SG_HIP(hipGetLastError());
+  }
   // the count kernels zero exactly the LDS they are launched with
   Plan Pm = pl->P;
   Pm.lds_words = pl->lds_mid_count / 4;
@@ -648,10 +654,14 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 1, true, st));
   }
-  if (I.n_tiny > 0) {
+  if (I.n_tiny > 0 || I.n_small > 0) {
     SG_TRY(mark(pl, 2, false, st));
-    hipLaunchKernelGGL((k_tiny<K, false>), dim3((unsigned)std::min<int64_t>((I.n_tiny + 3) / 4, persist * 8)), dim3(256), 0,
-                       st, P);
+    if (I.n_small > 0)
+      hipLaunchKernelGGL((k_small<K, false, true>), dim3((unsigned)std::min<int64_t>((I.n_small + 3) / 4, persist * 8)),
+                         dim3(256), 0, st, P);
+    if (I.n_tiny > 0)
+      hipLaunchKernelGGL((k_tiny<K, false>), dim3((unsigned)std::min<int64_t>((I.n_tiny + 3) / 4, persist * 8)), dim3(256),
+                         0, st, P);
     SG_HIP(hipGetLastError());
     SG_TRY(mark(pl, 2, true, st));
   }
@@ -667,7 +677,7 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   Plan P = pl->P;
   P.lds_words = lds / 4;
   const sg_sym_info &I = pl->info[0];
-  if (I.n_heavy_items == 0 && I.n_mid == 0) {
+  if (I.n_heavy_items == 0 && I.n_mid == 0 && I.n_small == 0) {
     // tiny vectors only (Galerkin triple products on grids): the tiny
     // kernel alone is the one launch, with no LDS to cap its occupancy
     SG_TRY(mark(pl, 0, false, st));
@@ -687,6 +697,15 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   const int64_t persist = std::max<int64_t>(1, std::min(resident_blocks(pl->ncu, nt, lds, kWavesPerSimd), work));
   SG_TRY(fill64(pl->counters + kCtQueue, 1, 0, st));
   SG_TRY(mark(pl, 0, false, st));
+  // the small list first, on the same stream: beside the persistent launch
+  // (on a second stream) its wavefronts would hold compute units the
+  // persistent workgroups are sized for, which measured slower
+  if (I.n_small > 0) {
+    const int64_t sp = (int64_t)pl->ncu * pl->tune.blocks_per_cu * 8;
+    hipLaunchKernelGGL((k_small<K, false, true>), dim3((unsigned)std::min<int64_t>((I.n_small + 3) / 4, sp)), dim3(256), 0,
+                       st, pl->P);
+    SG_HIP(hipGetLastError());
+  }
   const int mode = pl->has_mode[0] && pl->has_mode[1] ? 2 : (pl->has_mode[1] ? 1 : 0);
   const bool recs = P.rec_cap > 0 && mode != 0;  // only rank windows (mode 1) carry records
   const int64_t ni = I.n_heavy_items, nm = I.n_mid, ntn = I.n_tiny;
@@ -875,6 +894,7 @@ void sg_tuning_default(int32_t kind, sg_tuning *t) {
   // entry records cost the symbolic phase more than they save one numeric
   // run; they pay when a plan's numeric phase is replayed many times
   t->entry_mb = 0;
+  t->small_max_flops = kSmallMaxFlops;
 }
 
 const char *sg_last_error(void) { return g_last_error; }
@@ -1131,6 +1151,7 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
   P.tiny_list = L.tiny;
   P.mid_list = L.mid;
   P.heavy_list = L.heavy;
+  P.small_list = L.small;
   P.items = L.items;
   P.bcnt = L.bcnt;
   P.nbmax = sh.nbmax;
@@ -1160,9 +1181,9 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
   // flops per output vector, then the tiers
   if (sh.nov_max > 0) {
     const int64_t waves = std::min<int64_t>(sh.nov_max, (int64_t)pl->ncu * 64);
-    BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier};
+    BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier, t.small_max_flops};
     hipLaunchKernelGGL(k_flops_bin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, bp, L.gstat, L.counters,
-                       L.tiny, L.mid, L.heavy);
+                       L.tiny, L.mid, L.heavy, L.small);
     SG_HIP(hipGetLastError());
   }
   for (int32_t q = 0; q < nprod; ++q) {
@@ -1237,6 +1258,7 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
     I.n_tiny = cnt[kCtTiny];
     I.n_mid = cnt[kCtMid];
     I.n_heavy = cnt[kCtHeavy];
+    I.n_small = cnt[kCtSmall];
     I.n_heavy_items = cnt[kCtItems];
     for (int x = 0; x < 3; ++x) {
       I.tier_flops[x] = cnt[kCtTierFlops + x];
@@ -1294,6 +1316,7 @@ sg_status sg_plan_destroy(sg_plan *pl) {
   if (!pl) return SG_ERR_INVALID_ARG;
   if (pl->events_made)
     for (int i = 0; i < 8; ++i) (void)hipEventDestroy(pl->ev[i]);
+
   delete pl;
   return SG_OK;
 }

@@ -260,7 +260,12 @@ struct BinParams {
   int32_t tiny_max;
   int32_t mid_cap;
   int32_t force;
+  int32_t small_max;  // mid-tier vectors up to this many products go to the small list (0: none)
 };
+
+// Products of a small-list vector at most (eight per lane of a wavefront).
+constexpr int kSmallPerLane = 8;
+constexpr int kSmallMaxFlops = kSmallPerLane * kWave;
 
 // G vector of stored S entry e (-1: absent); a doubly compressed G is
 // resolved through AUX and the result kept in d.gres for the numeric kernels.
@@ -312,7 +317,7 @@ __device__ __forceinline__ int64_t entries_flops(const ProdDev &d, int64_t e0, i
 // accumulator and the id range spans several split buckets (with one bucket
 // the heavy tier's single dense window is the better accumulator); else heavy.
 __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *counters, int32_t *tiny, int32_t *mid,
-                            int32_t *heavy) {
+                            int32_t *heavy, int32_t *small) {
   constexpr int kSerial = 32;
   constexpr int kLaneSegs = 8;  // segments from which a vector's segments go one per lane
   constexpr int kBatch = 8;     // chunks whose list appends share one atomic per tier
@@ -442,14 +447,16 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
         if (f == 0) tier = -1;
         else if (bp.force == 2) tier = 2;
         else if (bp.force == 1) tier = mid_fit ? 1 : 2;
+        else if (bp.force == 3 && f <= kSmallMaxFlops) tier = 3;
         else if (f <= bp.tiny_max) tier = 0;
+        else if (f <= bp.small_max) tier = 3;
         else if (mid_fit && nsplit > 1) tier = 1;
         else tier = 2;
       }
       tier_of[i] = (int8_t)tier;
-      if (tier >= 0) {
-        tf[tier] += f;
-        ts[tier] += sent;
+      if (tier >= 0) {  // the small list counts as the mid tier in the totals
+        tf[tier == 3 ? 1 : tier] += f;
+        ts[tier == 3 ? 1 : tier] += sent;
       }
       // group totals: registers while the chunk stays in the current group
       const int64_t ub = f < minor ? f : minor;
@@ -469,9 +476,9 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
         }
       }
     }
-    // list appends of the kBatch chunks: one atomic per tier
-    for (int x = 0; x < 3; ++x) {
-      int32_t *list = x == 0 ? tiny : (x == 1 ? mid : heavy);
+    // list appends of the kBatch chunks: one atomic per list
+    for (int x = 0; x < 4; ++x) {
+      int32_t *list = x == 0 ? tiny : (x == 1 ? mid : (x == 2 ? heavy : small));
       uint64_t m[kBatch];
       int total = 0;
 #pragma unroll
@@ -481,7 +488,9 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
       }
       if (total == 0) continue;
       int64_t base = 0;
-      if (l == 0) base = (int64_t)atomicAdd((unsigned long long *)&counters[kCtTiny + x], (unsigned long long)total);
+      if (l == 0)
+        base = (int64_t)atomicAdd((unsigned long long *)&counters[x == 3 ? kCtSmall : kCtTiny + x],
+                                  (unsigned long long)total);
       base = __shfl(base, 0, kWave);
       const uint64_t below = (1ull << l) - 1ull;
 #pragma unroll
@@ -502,16 +511,17 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
   }
 }
 
-// Output entries per tier.
+// Output entries per tier (the small list counts as the mid tier).
 __global__ void k_tier_nnz(Plan P, int64_t *counters) {
-  const int64_t n[3] = {counters[kCtTiny], counters[kCtMid], counters[kCtHeavy]};
-  const int32_t *lists[3] = {P.tiny_list, P.mid_list, P.heavy_list};
-  for (int x = 0; x < 3; ++x) {
+  const int64_t n[4] = {counters[kCtTiny], counters[kCtMid], counters[kCtHeavy], counters[kCtSmall]};
+  const int32_t *lists[4] = {P.tiny_list, P.mid_list, P.heavy_list, P.small_list};
+  for (int x = 0; x < 4; ++x) {
     int64_t acc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n[x]; i += (int64_t)gridDim.x * blockDim.x)
       acc += P.ov_cnt[lists[x][i]];
     acc = wave_sum64(acc);
-    if (lane() == 0 && acc) atomicAdd((unsigned long long *)&counters[kCtTierNnz + x], (unsigned long long)acc);
+    const int t = x == 3 ? 1 : x;
+    if (lane() == 0 && acc) atomicAdd((unsigned long long *)&counters[kCtTierNnz + t], (unsigned long long)acc);
   }
 }
 
@@ -720,15 +730,21 @@ __global__ void k_item_recs(Plan P) {
   }
 }
 
-// Records of the mid-tier vectors: per mid vector i its stored S entries
-// (mcnt, scanned into mbase), placed after the heavy items' records (whose
-// total is *heavy_total).
+// The mid-tier vector at record position p: the mid list, then the small list.
+__device__ __forceinline__ int32_t mid_pos_vector(const Plan &P, int64_t nm, int64_t p) {
+  return p < nm ? P.mid_list[p] : P.small_list[p - nm];
+}
+
+// Records of the mid-tier vectors: per position i (mid list, then small
+// list) the vector's stored S entries (mcnt, scanned into mbase), placed
+// after the heavy items' records (whose total is *heavy_total).
 __global__ void k_mid_rec_count(Plan P, int64_t cap, int64_t *mcnt) {
   const int64_t nm = P.counters[kCtMid];
+  const int64_t np = nm + P.counters[kCtSmall];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
     int64_t ns = 0;
-    if (i < nm) {
-      const int32_t v = P.mid_list[i];
+    if (i < np) {
+      const int32_t v = mid_pos_vector(P, nm, i);
       for (int64_t s = P.ov_seg[v]; s < P.ov_seg[v + 1]; ++s) {
         const ProdDev &d = P.prods[P.seg_prod[s]];
         const int32_t t = P.seg_svec[s];
@@ -742,26 +758,27 @@ __global__ void k_mid_rec_count(Plan P, int64_t cap, int64_t *mcnt) {
 // A mid vector keeps its records when all of them fit the workspace.
 __global__ void k_mid_rec_base(Plan P, int64_t cap, const int64_t *heavy_total, const int64_t *mcnt,
                                const int64_t *mbase, int64_t *mid_rb, int32_t *mid_nrec) {
-  const int64_t nm = P.counters[kCtMid];
+  const int64_t np = P.counters[kCtMid] + P.counters[kCtSmall];
   const int64_t h = *heavy_total;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r0 = h + mbase[i];
-    const bool ok = i < nm && mcnt[i] > 0 && r0 + mcnt[i] <= P.rec_cap;
+    const bool ok = i < np && mcnt[i] > 0 && r0 + mcnt[i] <= P.rec_cap;
     mid_rb[i] = ok ? r0 : -1;
     mid_nrec[i] = ok ? (int32_t)mcnt[i] : 0;
   }
 }
 
-// One wavefront per mid vector with records (whole G vectors).
+// One wavefront per mid-tier vector with records (whole G vectors).
 template <int K>
 __global__ void k_mid_recs(Plan P) {
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const int64_t n = P.counters[kCtMid];
+  const int64_t nm = P.counters[kCtMid];
+  const int64_t n = nm + P.counters[kCtSmall];
   for (int64_t i = wave; i < n; i += nwaves) {
     const int64_t rb = uload(P.mid_rb + i);
     if (rb < 0) continue;
-    vector_recs<K>(P, uload(P.mid_list + i), -1, -1, rb);
+    vector_recs<K>(P, i < nm ? uload(P.mid_list + i) : uload(P.small_list + (i - nm)), -1, -1, rb);
   }
 }
 

@@ -1274,6 +1274,252 @@ __device__ __forceinline__ void mid_item(const Plan &P, int64_t m, uint32_t *lds
 }
 
 // ---------------------------------------------------------------------------
+// Small list: a mid-tier vector of at most kSmallMaxFlops products on one
+// wavefront, with no LDS and no workgroup barrier. Its products are
+// gathered into registers, kSmallPerLane per lane (product s of the vector
+// goes to lane s mod 64, register s / 64), with every gather load in flight
+// before the first is used; a bitonic network then sorts the 64 x 8
+// (id, value) pairs into lane-major order (element e = 8 lane + register),
+// exchanging registers inside a lane for distances below 8 and lanes on the
+// VALU (xor_lane) for the others; equal ids are merged by a running (+)
+// inside each lane and a segmented prefix across lanes; each lane writes its
+// run ends at their ranks. Padding slots hold id INT32_MAX and sort last.
+// A vector of at most 64 ep products (ep = 1, 2, 4 or 8, the smallest that
+// holds it) sorts only registers 0 .. ep - 1 (element e = ep lane + j): the
+// network's work grows with ep, so a vector of 100 products costs a sort of
+// 128 elements, not 512. The network is a loop over its stages, one code
+// block per exchange distance, not unrolled: a fully unrolled network is about twelve thousand
+// instructions, which every wavefront would stream through the instruction
+// cache for each vector.
+// One stage across lanes: element e and e xor (LM * E) compare-exchange,
+// ascending where e & k is 0.
+template <class SR, int E, int LM>
+__device__ __forceinline__ void small_xstage(int32_t (&key)[E], typename SR::T (&val)[E], int k, int ep) {
+  typedef typename SR::T T;
+  const int l = lane();
+  const bool low = (l & LM) == 0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (j >= ep) break;  // uniform: registers past the vector's ep hold padding only
+    const int32_t pk = xor_lane(key[j], LM);
+    const T pv = SR::kVal ? xor_lane(val[j], LM) : T();
+    const bool up = ((l * ep + j) & k) == 0;
+    const bool take = low ? (up ? pk < key[j] : pk > key[j]) : (up ? pk > key[j] : pk < key[j]);
+    if (take) {
+      key[j] = pk;
+      if (SR::kVal) val[j] = pv;
+    }
+  }
+}
+// One stage inside a lane: registers j and j + M.
+template <class SR, int E, int M>
+__device__ __forceinline__ void small_istage(int32_t (&key)[E], typename SR::T (&val)[E], int k, int ep) {
+  typedef typename SR::T T;
+  const int l = lane();
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (j & M) continue;
+    if (j >= ep) break;
+    const int jp = j | M;
+    const bool up = ((l * ep + j) & k) == 0;
+    const bool sw = up ? key[j] > key[jp] : key[j] < key[jp];
+    if (sw) {
+      const int32_t tk = key[j];
+      key[j] = key[jp];
+      key[jp] = tk;
+      if (SR::kVal) {
+        const T tv = val[j];
+        val[j] = val[jp];
+        val[jp] = tv;
+      }
+    }
+  }
+}
+
+template <int K, bool COUNT, bool RECS>
+__device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  constexpr int E = kSmallPerLane;
+  static_assert(E == 8, "the stage blocks below cover in-lane distances 4, 2, 1");
+  const int l = lane();
+  int32_t key[E];
+  T val[E];  // gathered G values, then products
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    key[j] = INT32_MAX;
+    val[j] = T();
+  }
+  int filled = 0;
+  // one batch of up to 64 entries, one per lane: `len` products whose ids
+  // start at address ia and values at va (S value sv); products f of the
+  // batch go to slots filled + f. Every gather of the batch is issued before
+  // the first product is formed; the owner lane of each register's product
+  // is kept packed (8 bits per register) to fetch its S value afterwards.
+  auto place = [&](int len, int64_t ia, int64_t va, T sv) {
+    const int incl = wave_incl_scan(len);
+    const int tot = read_lane(incl, kWave - 1);
+    if (tot == 0) return;
+    const int st = incl - len;  // the entry's first product in the batch
+    const int64_t ia0 = ia - (int64_t)st * (int64_t)sizeof(int32_t);  // id address of product 0 of the entry
+    const int64_t va0 = va - (int64_t)st * (int64_t)sizeof(T);
+    uint32_t own[2] = {0u, 0u};
+    uint32_t got = 0;  // registers this lane gathered into in this batch
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int f0 = j * kWave - filled;  // the batch product in this register of lane 0
+      if (f0 >= tot || f0 + kWave <= 0) continue;  // uniform: no lane has a product in this register
+      const int f = f0 + l;
+      const bool mine = f >= 0 && f < tot;
+      // the entry of each lane's product: the entry of the register's first
+      // product, unless an entry starts later in the register (a few such
+      // starts are taken in order; many, by a binary search)
+      const int r0 = f0 > 0 ? f0 : 0;
+      int o = (int)__popcll(__ballot(incl <= r0));
+      const uint64_t starts = __ballot(len > 0 && st > r0 && st < f0 + kWave);
+      if (starts) {
+        if (__popcll(starts) <= 4) {
+          uint64_t m = starts;
+          while (m) {
+            const int x = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            if (f >= read_lane(st, x)) o = x;
+          }
+        } else {
+          o = owner_of(incl, mine ? f : 0);
+        }
+      }
+      const int64_t a = __shfl(ia0, o, kWave) + (int64_t)f * (int64_t)sizeof(int32_t);
+      const int64_t b = SR::kVal ? __shfl(va0, o, kWave) + (int64_t)f * (int64_t)sizeof(T) : 0;
+      own[j >> 2] |= (uint32_t)o << (8 * (j & 3));
+      if (mine) {
+        key[j] = gload((const int32_t *)a);
+        if (SR::kVal) val[j] = gload((const T *)b);
+        got |= 1u << j;
+      }
+    }
+    if (SR::kVal) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int f0 = j * kWave - filled;
+        if (f0 + kWave <= 0 || f0 >= tot) continue;  // uniform: no lane gathered into register j
+        const T sj = __shfl(sv, (int)((own[j >> 2] >> (8 * (j & 3))) & 63u), kWave);
+        if ((got >> j) & 1u) val[j] = SR::mul(sj, val[j]);
+      }
+    }
+    filled += tot;
+  };
+  const int64_t rb = RECS && P.mid_rb ? uload(P.mid_rb + p) : -1;
+  if (RECS && rb >= 0) {
+    const int32_t nrec = uload(P.mid_nrec + p);
+    for (int64_t eb = 0; eb < nrec; eb += kWave) {
+      const int64_t x = rb + eb + l;
+      const bool ok = eb + l < nrec;
+      const int len = ok ? gload(P.rec_len + x) : 0;
+      const int64_t gi = ok ? gload(P.rec_gi + x) : 0;
+      const int64_t gv = (SR::kVal && ok) ? gload(P.rec_gv + x) : 0;
+      const T sv = (SR::kVal && ok) ? gload((const T *)P.rec_sv + x) : T();
+      place(len, gi, gv, sv);
+    }
+  } else {
+    const int64_t s0 = uload(P.ov_seg + v), s1 = uload(P.ov_seg + v + 1);
+    for (int64_t s = s0; s < s1; ++s) {
+      const ProdDev d = uload(P.prods + uload(P.seg_prod + s));
+      const int32_t t = uload(P.seg_svec + s);
+      const int64_t e1 = uload(d.s_ptr + t + 1);
+      for (int64_t eb = uload(d.s_ptr + t); eb < e1; eb += kWave) {
+        int len;
+        int64_t gb;
+        T sv;
+        load_entry<SR>(d, eb + l, e1, -1, -1, len, gb, sv);
+        place(len, (int64_t)(d.g_idx + gb), SR::kVal ? (int64_t)((const T *)d.g_val + gb) : 0, sv);
+      }
+    }
+  }
+  // registers in use: the vector's products fill ceil(filled / 64) of them
+  const int ep = filled <= kWave ? 1 : (filled <= 2 * kWave ? 2 : (filled <= 4 * kWave ? 4 : 8));
+  // bitonic sort of the ep x 64 elements, element e = ep lane + j, ascending id
+  for (int k = 2; k <= ep * kWave; k <<= 1) {
+    for (int m = k >> 1; m >= ep; m >>= 1) {
+      switch (uni(m / ep)) {  // the lane distance, uniform: one code block per distance
+        case 1: small_xstage<SR, E, 1>(key, val, k, ep); break;
+        case 2: small_xstage<SR, E, 2>(key, val, k, ep); break;
+        case 4: small_xstage<SR, E, 4>(key, val, k, ep); break;
+        case 8: small_xstage<SR, E, 8>(key, val, k, ep); break;
+        case 16: small_xstage<SR, E, 16>(key, val, k, ep); break;
+        default: small_xstage<SR, E, 32>(key, val, k, ep); break;
+      }
+    }
+    if (k >= 8 && ep > 4) small_istage<SR, E, 4>(key, val, k, ep);
+    if (k >= 4 && ep > 2) small_istage<SR, E, 2>(key, val, k, ep);
+    if (ep > 1) small_istage<SR, E, 1>(key, val, k, ep);
+  }
+  // the last register in use, its id and value (a select chain: ep is uniform)
+  int32_t klast32 = key[0];
+  T vlast = val[0];
+#pragma unroll
+  for (int j = 1; j < E; ++j) {
+    if (j == ep - 1) {
+      klast32 = key[j];
+      vlast = val[j];
+    }
+  }
+  // merge equal ids: a running (+) inside the lane, then the run that
+  // reaches this lane's first element from earlier lanes is carried in
+#pragma unroll
+  for (int j = 1; j < E; ++j) {
+    if (j >= ep) break;
+    if (SR::kVal && key[j] == key[j - 1]) val[j] = SR::add(val[j - 1], val[j]);
+    if (j == ep - 1) vlast = val[j];
+  }
+  if (SR::kVal) {
+    const T run = seg_prefix<SR>((uint64_t)(uint32_t)klast32, vlast);  // consecutive lanes ending in the same id
+    const int32_t pk = __shfl_up(klast32, 1, kWave);
+    const T pr = __shfl_up(run, 1, kWave);
+    if (l > 0 && pk == key[0]) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        if (j >= ep) break;
+        if (key[j] == key[0]) val[j] = SR::add(pr, val[j]);
+      }
+    }
+  }
+  // run ends: the next element (the next lane's first for the last register) has another id
+  const int32_t nk = __shfl_down(key[0], 1, kWave);
+  const MaskRef mk = mask_of(P, v);
+  uint32_t tails = 0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (j >= ep) break;
+    const bool lastreg = j == ep - 1;
+    const int32_t next = !lastreg ? key[j + 1 < E ? j + 1 : j] : (l + 1 < kWave ? nk : INT32_MAX);
+    bool t = key[j] != INT32_MAX && (next != key[j] || (lastreg && l + 1 == kWave));
+    if (mk.on() && t) t = mk.keeps(key[j]);
+    tails |= (uint32_t)t << j;
+  }
+  const int cnt = __popc(tails);
+  const int incl = wave_incl_scan(cnt);
+  const int total = read_lane(incl, kWave - 1);
+  if (COUNT) {
+    if (l == 0) P.ov_cnt[v] = total;
+    return;
+  }
+  chk_count(P, l == 0 && (int64_t)total != gload(P.ov_cnt + v));
+  if (tails) {
+    const OutDev O = uload(P.outs + uload(P.ov_group + v));
+    int64_t pos = out_offset(P, v) + (incl - cnt);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((tails >> j) & 1u) {
+        gstore(O.idx + pos, key[j]);
+        if (SR::kVal) gstore((T *)O.val + pos, val[j]);
+        ++pos;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kernels. Mid and heavy kernels pull work from a device queue counter;
 // every workgroup exits once the counter passes the item count, which is
 // fixed before the launch, so every wave reaches the exit.
@@ -1290,6 +1536,17 @@ __global__ void __launch_bounds__(1024) k_tiny(Plan P) {
   // chunks as large as needed to give every wavefront work, at most 64
   const int64_t csz = tiny_chunk(n, nwaves);
   for (int64_t c0 = wave * csz; c0 < n; c0 += nwaves * csz) tiny_pack<K, COUNT>(P, c0, c0 + csz < n ? c0 + csz : n);
+}
+
+// Small-list vectors, one per wavefront at a time (count pass: COUNT; the
+// numeric pass walks entry records where the plan has them).
+template <int K, bool COUNT, bool RECS>
+__global__ void __launch_bounds__(1024) k_small(Plan P) {
+  const int64_t nm = P.counters[kCtMid];
+  const int64_t n = P.counters[kCtSmall];
+  const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t i = wave; i < n; i += nwaves) small_vector<K, COUNT, RECS>(P, uload(P.small_list + i), nm + i);
 }
 
 template <int K>
@@ -1406,9 +1663,11 @@ __global__ void __launch_bounds__(kBlockMax, heavy_count_waves<MODE>()) k_heavy_
   }
 }
 
-// One persistent launch for every tier: queue items are heavy windows
-// first, then mid vectors, then chunks of 64 tiny-list positions (one chunk
-// per wavefront, packed as in tiny_pack).
+// One persistent launch for the workgroup tiers: queue items are heavy
+// windows first, then mid vectors, then chunks of 64 tiny-list positions
+// (one chunk per wavefront, packed as in tiny_pack). The small list runs in
+// its own launch (k_small): its registers would otherwise count against
+// every path of this kernel.
 template <int K, int MODE, bool RECS>
 __global__ void __launch_bounds__(kBlockMax, kWavesPerSimd) k_batched(Plan P, int64_t *queue, int64_t n_items, int64_t n_mid,
                                                   int64_t n_tiny) {

@@ -72,7 +72,7 @@ def test_summa_share_forced_tiers_and_order(sg):
     dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
     SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
     R, _ = oracle.spgemm(semiring, SA, SB)
-    for force in (-1, 1, 2):
+    for force in (-1, 1, 2, 3):
         t = sg.make_tuning(semiring, force_tier=force, lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384,
                            heavy_threads=256)
         C = BT.summa_share(semiring, dA, dB, tuning=t).to_host()
@@ -236,7 +236,7 @@ def test_autotune_replay_presets_keep_results(sg):
     plan.destroy()
 
 
-@pytest.mark.parametrize("force", [-1, 1, 2])
+@pytest.mark.parametrize("force", [-1, 1, 2, 3])
 def test_summa_share_many_segments(sg, force):
     """16 stage products per output vector (more segments than wavefronts per workgroup), every tier."""
     from paper_1006_2183_amd import batched as BT
@@ -259,7 +259,7 @@ def test_summa_share_many_segments(sg, force):
 
 @pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
 @pytest.mark.parametrize("entry_mb", [1, 2048])
-@pytest.mark.parametrize("force", [2, -1])
+@pytest.mark.parametrize("force", [2, -1, 3])
 def test_summa_share_entry_records(sg, semiring, entry_mb, force):
     """Heavy windows (and, unforced, mid-tier vectors) fed by 16 stage products, walked from
     entry records (all, or some within a 1 MiB budget), per tier launch and in the

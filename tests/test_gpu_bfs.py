@@ -48,6 +48,7 @@ def _masked_ref(semiring, A, B, bits, stride, complement):
 @pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32", "or_and_bool"])
 @pytest.mark.parametrize("complement", [True, False])
 @pytest.mark.parametrize("tune", [dict(), dict(force_tier=0), dict(force_tier=1), dict(force_tier=1, mid_kind=1),
+                                  dict(force_tier=3), dict(small_max_flops=0),
                                   dict(force_tier=2, lds_bytes=16384, heavy_lds_bytes=16384, block_threads=256,
                                        heavy_threads=256),
                                   dict(force_tier=2, lds_bytes=16384, heavy_lds_bytes=16384, block_threads=256,

@@ -81,6 +81,8 @@ def _oracle_check(semiring, C, A, B, what):
     dict(lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384, heavy_threads=256, mid_kind=1),
     dict(lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384, heavy_threads=256, heavy_kind=1),
     dict(lds_bytes=8192, block_threads=128, heavy_lds_bytes=12288, heavy_threads=192, entry_mb=1),
+    dict(lds_bytes=16384, block_threads=256, heavy_lds_bytes=16384, heavy_threads=256, force_tier=3, entry_mb=64),
+    dict(small_max_flops=0),
 ])
 def test_rmat_tiers_invariants(sg, semiring, batched, cfg):
     """All tiers in one launch (batched) or per tier, with small LDS budgets so that
@@ -100,7 +102,8 @@ def test_summa_share_invariants(sg, batched):
     _say(f"case invariants SUMMA share s{scale} grid {grid} batched={batched}")
     a_blocks, b_blocks = W.summa_share(scale, 16, grid, (1, 2), semiring=sr, seed=7, fmt="dcsc")
     b = (1 << scale) // grid
-    for tune in (dict(), dict(entry_mb=256), dict(lds_bytes=24576, heavy_lds_bytes=24576, heavy_threads=256)):
+    for tune in (dict(), dict(entry_mb=256), dict(lds_bytes=24576, heavy_lds_bytes=24576, heavy_threads=256),
+                 dict(entry_mb=256, force_tier=3)):
         (C,) = _run(sg, sr, a_blocks, b_blocks, [0] * grid, 1, out_fmt="dcsc", batched=batched, reps=2, **tune)
         # oracle: the strips A(I, :) A(:, J)
         ra, ca, va, rb, cb, vb = [], [], [], [], [], []

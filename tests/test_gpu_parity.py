@@ -89,7 +89,8 @@ def test_rmat_s10_default_tiers(sg, semiring, batched):
 @pytest.mark.parametrize("semiring", SEMIRINGS)
 @pytest.mark.parametrize("force,mid_kind,heavy_kind,bitmap_mb", [(0, 0, 0, 4096), (1, 0, 0, 4096), (1, 1, 0, 4096),
                                                                  (2, 0, 0, 4096), (2, 0, 0, 0), (2, 0, 0, 1),
-                                                                 (2, 0, 1, 4096), (-1, 0, 0, 4096), (-1, 1, 1, 0)])
+                                                                 (2, 0, 1, 4096), (-1, 0, 0, 4096), (-1, 1, 1, 0),
+                                                                 (3, 0, 0, 4096)])
 def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind, bitmap_mb):
     """Every tier on every vector it can take. 16 KB of LDS: a rank window's words and values
     share 2048 (f64) or 4096 (4-byte values) value slots over 1K/2K-id buckets, so heavy rows
@@ -106,6 +107,8 @@ def test_forced_tiers_several_windows(sg, semiring, force, mid_kind, heavy_kind,
         assert info["n_mid"] == 0 and info["n_tiny"] == 0
     if force == 1:
         assert info["n_mid"] > 0
+    if force == 3:
+        assert info["n_small"] > 0
 
 
 @pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32", "or_and_bool"])
