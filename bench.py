@@ -342,7 +342,7 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
     kms = plan.kernel_times()["heavy"]
     algo = _tier_bytes(plan.infos, 8)
     out = {
-        "workload": f"rmat_s{scale}_ef16_summa{grid}x{grid}_share_p00_f64",
+        "workload": SUMMA_WORKLOAD,
         "stages": len(dA), "nnz_blocks_min": int(min(nnz_blocks)), "nnz_blocks_max": int(max(nnz_blocks)),
         "flops": int(flops), "nnz_C": int(nnz_c),
         "plain_ms": round(ms_plain, 3), "batched_ms": round(ms_batched, 3), "graph_replay_ms": round(ms_graph, 3),
@@ -352,7 +352,11 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
                   "tuned_launch_ms": round(tune["ms"], 3)},
         "batched_vs_plain": round(ms_plain / ms_batched, 2), "graph_vs_plain": round(ms_plain / ms_graph, 2),
         "persistent_kernel": {"launch_ms": round(kms, 4), "algorithmic_bytes": int(algo),
-                              "achieved_GBs": round(algo / kms / 1e6, 1) if kms > 0 else None},
+                              "achieved_GBs": round(algo / kms / 1e6, 1) if kms > 0 else None,
+                              "kernels": "k_small (small list) then k_batched (all other tiers), one replay",
+                              # counters are taken on the replay-only run at SUMMA_PROFILE_TUNING
+                              "traffic": load_traffic("replay", SUMMA_WORKLOAD, sr)
+                              if replay_tuning == SUMMA_PROFILE_TUNING else None},
         "plain": "64 x (symbolic + sync + alloc + per-tier numeric) into DCSC partials, then a 64-way merge",
         "exact": "batched == plain == graph replay (patterns exact, values within 1e-12 relative)",
         "cpu_baseline": cpu,
@@ -360,6 +364,34 @@ def suite_summa(sg, torch, W, reps, scale=24, grid=64, seed=24):
     plan.destroy()
     del G, res, dA, dB
     torch.cuda.empty_cache()
+    return out
+
+
+SUMMA_WORKLOAD = "rmat_s24_ef16_summa64x64_share_p00_f64"
+SUMMA_PROFILE_TUNING = {"entry_mb": 1024}  # the replay-only run's setting (kernel traces, counters)
+
+
+def suite_summa_replay(sg, torch, W, reps, tuning, scale=24, grid=64, seed=24):
+    """Graph replays of the SUMMA share's plan alone (no plain path, no tuner), so that
+    a kernel trace or a counter pass sees only the replayed launches: the small-list
+    kernel and the persistent kernel, once per replay."""
+    from paper_1006_2183_amd import batched as BT
+    sr = "plus_times_f64"
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=sr, seed=seed, device="cuda", fmt="dcsc")
+    dA = [sg.DevMat.from_host(x, "cuda", sr) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", sr) for x in b_blocks]
+    del a_blocks, b_blocks
+    plan = BT.summa_share_plan(sr, dA, dB, tuning=sg.make_tuning(sr, **tuning))
+    G = BT.GraphedNumeric(plan)
+    ms = _median_ms(torch, G.replay, reps)
+    plan.profile(True)
+    sg.spgemm_batched(plan, G.outputs)
+    kms = plan.kernel_times()["heavy"]
+    algo = _tier_bytes(plan.infos, 8)
+    out = {"workload": SUMMA_WORKLOAD, "tuning": tuning, "replays": reps, "graph_replay_ms": round(ms, 3),
+           "launch_ms": round(kms, 4), "algorithmic_bytes": int(algo),
+           "n_small": plan.infos[0]["n_small"], "n_mid": plan.infos[0]["n_mid"]}
+    plan.destroy()
     return out
 
 
@@ -691,6 +723,25 @@ def ingest_counters(root, copy_mib, workload, semiring):
         with open(path) as f:
             d = json.load(f)
     d[f"{workload}/{semiring}/k_heavy"] = entry
+    # the SUMMA share's replayed launch (k_small and the persistent kernel, counted
+    # together per replay) when its passes were taken too
+    if os.path.isdir(os.path.join(root, "summa_fetch")):
+        sp = {}
+        pats = (re.compile(r"k_batched<\d+, \d+, true>"), re.compile(r"k_small<\d+, false, true>"))
+        for ctr, sub in (("FETCH_SIZE", "summa_fetch"), ("WRITE_SIZE", "summa_write")):
+            rows = [(k, v) for k, c, v, _ in _counter_rows(os.path.join(root, sub)) if c == ctr]
+            tot = 0.0
+            for pt in pats:
+                vals = [v for k, v in rows if pt.search(k)]
+                tot += float(np.mean(vals)) if vals else 0.0
+            if not any(pats[0].search(k) for k, _ in rows):
+                raise SystemExit(f"no persistent-kernel dispatch in {sub}")
+            sp[ctr] = tot * 1024.0 * factors[ctr]
+        se = {"kernel_hash": kernel_source_hash(), "bytes_per_launch": int(sp["FETCH_SIZE"] + sp["WRITE_SIZE"]),
+              "fetch_bytes": int(sp["FETCH_SIZE"]), "write_bytes": int(sp["WRITE_SIZE"]),
+              "copy_scale": {k: round(v, 4) for k, v in factors.items()}, "copy_mib": copy_mib}
+        d[f"{SUMMA_WORKLOAD}/plus_times_f64/replay"] = se
+        print(json.dumps(se))
     with open(path, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
     print(json.dumps(entry))
@@ -712,7 +763,7 @@ def main():
     ap.add_argument("--no-suite", action="store_true",
                     help="skip the batched (SUMMA share, Galerkin) and served measurements")
     ap.add_argument("--suite-reps", type=int, default=3)
-    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving", "bfs"], default=None,
+    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving", "bfs", "summa_replay"], default=None,
                     help="run one of the batched/served measurements alone and print its JSON object")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-qps", default="500,2000,8000")
@@ -762,7 +813,9 @@ def main():
               "serving": ("serving", lambda: suite_serve(sg, torch, W, args.serve_requests,
                                                          [float(q) for q in args.serve_qps.split(",")])),
               "bfs": ("served_bfs", lambda: suite_bfs(sg, torch, W, args.bfs_requests,
-                                                      [float(q) for q in args.bfs_qps.split(",")]))}
+                                                      [float(q) for q in args.bfs_qps.split(",")])),
+              "summa_replay": ("summa_replay", lambda: suite_summa_replay(
+                  sg, torch, W, args.suite_reps, json.loads(args.tuning) if args.tuning else SUMMA_PROFILE_TUNING))}
     if args.only:
         print(json.dumps({suites[args.only][0]: suites[args.only][1]()}), flush=True)
         return
