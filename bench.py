@@ -907,7 +907,9 @@ def main():
         log("[bench] timing the CPU oracle on a row sample")
         out["cpu_baseline"] = cpu_baseline(args.semiring, A_main, info["flops"], args.cpu_seconds)
     if not args.no_suite:
-        for name, fn in suites.values():
+        for key, (name, fn) in suites.items():
+            if key == "summa_replay":  # a profiling run of its own (--only), not part of the line
+                continue
             t = time.perf_counter()
             try:
                 out[name] = fn()
