@@ -395,6 +395,45 @@ def suite_summa_replay(sg, torch, W, reps, tuning, scale=24, grid=64, seed=24):
     return out
 
 
+GALERKIN_WORKLOAD = "galerkin_rap_7pt_16_instances_n_in_32_48_64_96_128_f64"
+
+
+def galerkin_operands(sg, W, count=16, seed=4):
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.choice([32, 48, 64, 96, 128], size=count)]
+    host = {}
+    for n in sorted(set(sizes)):
+        L = W.laplacian_7pt(n, "csr")
+        P = W.aggregation_p(n, "csr")
+        host[n] = (L, P, W.transpose(P, "csr"))
+    dev = lambda M: sg.DevMat.from_host(M, "cuda")
+    return sizes, host, [dev(host[n][0]) for n in sizes], [dev(host[n][1]) for n in sizes], \
+        [dev(host[n][2]) for n in sizes]
+
+
+def suite_galerkin_replay(sg, torch, W, reps):
+    """Graph replays alone of the Galerkin batch's two-launch chain (A P, then R (A P),
+    default settings) and of the fused chain, so that a counter pass sees only their
+    numeric launches: `reps` replays of each after the one eager launch each graph's
+    set-up runs."""
+    from paper_1006_2183_amd import batched as BT
+    sr = "plus_times_f64"
+    sizes, host, Ls, Ps, Rs = galerkin_operands(sg, W)
+    plan_ap, AP, plan_rap = BT.galerkin_plans(sr, Rs, Ls, Ps)
+    G = BT.GraphedNumeric([plan_ap, plan_rap], [AP, None])
+    for _ in range(reps):
+        G.replay()
+    torch.cuda.synchronize()
+    plan_f = BT.galerkin_chain_plan(sr, Rs, Ls, Ps)
+    GF = BT.GraphedNumeric(plan_f)
+    for _ in range(reps):
+        GF.replay()
+    torch.cuda.synchronize()
+    out = {"workload": GALERKIN_WORKLOAD, "replays": reps, "launches_each": reps + 1}
+    plan_f.destroy()
+    return out
+
+
 def summa_cpu_baseline(sr, a_blocks, b_blocks, grid, b):
     """The oracle on the whole share: the strip product A(I, :) A(:, J)."""
     import oracle
@@ -417,18 +456,8 @@ def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
     from paper_1006_2183_amd import batched as BT
     from paper_1006_2183_amd import autotune as AT
     sr = "plus_times_f64"
-    rng = np.random.default_rng(seed)
-    sizes = [int(x) for x in rng.choice([32, 48, 64, 96, 128], size=count)]
+    sizes, host, Ls, Ps, Rs = galerkin_operands(sg, W, count, seed)
     log(f"[bench] Galerkin R A P: {count} instances, grid sizes {sizes}")
-    host = {}
-    for n in sorted(set(sizes)):
-        L = W.laplacian_7pt(n, "csr")
-        P = W.aggregation_p(n, "csr")
-        host[n] = (L, P, W.transpose(P, "csr"))
-    dev = lambda M: sg.DevMat.from_host(M, "cuda")
-    Ls = [dev(host[n][0]) for n in sizes]
-    Ps = [dev(host[n][1]) for n in sizes]
-    Rs = [dev(host[n][2]) for n in sizes]
     res = {}
 
     def plain():
@@ -506,10 +535,12 @@ def suite_galerkin(sg, torch, W, reps, count=16, seed=4):
                  "launch_ms": round(launch_f, 4),
                  "algorithmic_bytes": int(algo_f),
                  "achieved_GBs": round(algo_f / launch_f / 1e6, 1) if launch_f > 0 else None,
+                 "traffic": load_traffic("fused_replay", GALERKIN_WORKLOAD, sr),
                  "exact": "fused == plain bitwise (R A P == 4 L_(n/2) on every instance)"}
     plan_f.destroy()
     out = {
-        "workload": f"galerkin_rap_7pt_{count}_instances_n_in_32_48_64_96_128_f64",
+        "workload": GALERKIN_WORKLOAD,
+        "graph_replay_traffic": load_traffic("two_launch_replay", GALERKIN_WORKLOAD, sr),
         "fused_chain": out_fused,
         "sizes": sizes, "flops": int(flops),
         "nnz_RAP": int(sum(i["nnz"] for i in plan_rap.infos)),
@@ -742,6 +773,35 @@ def ingest_counters(root, copy_mib, workload, semiring):
               "copy_scale": {k: round(v, 4) for k, v in factors.items()}, "copy_mib": copy_mib}
         d[f"{SUMMA_WORKLOAD}/plus_times_f64/replay"] = se
         print(json.dumps(se))
+    # the Galerkin batch's replays: the fused chain (k_chain_tiny / k_chain_mid per
+    # launch) and the two-launch chain (two k_tiny launches per replay)
+    if os.path.isdir(os.path.join(root, "galerkin_fetch")):
+        def two_sizes(vals):
+            # the two launches of a replay (A P, then R (A P)) differ in size: the
+            # median of each of the two clusters of dispatch values, added
+            lo, hi = min(vals), max(vals)
+            cut = (lo + hi) / 2.0
+            big = [v for v in vals if v > cut] or [hi]
+            small = [v for v in vals if v <= cut] or [lo]
+            return float(np.median(big)) + float(np.median(small))
+
+        for key, pats, two in (("fused_replay", (re.compile(r"k_chain_tiny<\d+, false>"),
+                                                 re.compile(r"k_chain_mid<\d+, false>")), False),
+                               ("two_launch_replay", (re.compile(r"k_tiny<\d+, false>"),), True)):
+            gp = {}
+            for ctr, sub in (("FETCH_SIZE", "galerkin_fetch"), ("WRITE_SIZE", "galerkin_write")):
+                rows = [(k, v) for k, c, v, _ in _counter_rows(os.path.join(root, sub)) if c == ctr]
+                tot = 0.0
+                for pt in pats:
+                    vals = [v for k, v in rows if pt.search(k)]
+                    if vals:
+                        tot += two_sizes(vals) if two else float(np.median(vals))
+                gp[ctr] = tot * 1024.0 * factors[ctr]
+            ge = {"kernel_hash": kernel_source_hash(), "bytes_per_launch": int(gp["FETCH_SIZE"] + gp["WRITE_SIZE"]),
+                  "fetch_bytes": int(gp["FETCH_SIZE"]), "write_bytes": int(gp["WRITE_SIZE"]),
+                  "copy_scale": {k: round(v, 4) for k, v in factors.items()}, "copy_mib": copy_mib}
+            d[f"{GALERKIN_WORKLOAD}/plus_times_f64/{key}"] = ge
+            print(key, json.dumps(ge))
     with open(path, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
     print(json.dumps(entry))
@@ -763,7 +823,8 @@ def main():
     ap.add_argument("--no-suite", action="store_true",
                     help="skip the batched (SUMMA share, Galerkin) and served measurements")
     ap.add_argument("--suite-reps", type=int, default=3)
-    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving", "bfs", "summa_replay"], default=None,
+    ap.add_argument("--only", choices=["small", "summa", "galerkin", "serving", "bfs", "summa_replay", "galerkin_replay"],
+                    default=None,
                     help="run one of the batched/served measurements alone and print its JSON object")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-qps", default="500,2000,8000")
@@ -814,6 +875,7 @@ def main():
                                                          [float(q) for q in args.serve_qps.split(",")])),
               "bfs": ("served_bfs", lambda: suite_bfs(sg, torch, W, args.bfs_requests,
                                                       [float(q) for q in args.bfs_qps.split(",")])),
+              "galerkin_replay": ("galerkin_replay", lambda: suite_galerkin_replay(sg, torch, W, args.suite_reps)),
               "summa_replay": ("summa_replay", lambda: suite_summa_replay(
                   sg, torch, W, args.suite_reps, json.loads(args.tuning) if args.tuning else SUMMA_PROFILE_TUNING))}
     if args.only:
@@ -908,7 +970,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.semiring, A_main, info["flops"], args.cpu_seconds)
     if not args.no_suite:
         for key, (name, fn) in suites.items():
-            if key == "summa_replay":  # a profiling run of its own (--only), not part of the line
+            if key.endswith("_replay"):  # profiling runs of their own (--only), not part of the line
                 continue
             t = time.perf_counter()
             try:

@@ -167,6 +167,9 @@ typedef struct {
  *                    and written (0 = off: every mid vector takes a
  *                    workgroup's LDS accumulator). They count as mid-tier
  *                    vectors in the per-tier totals (n_small of sg_sym_info).
+ *                    Only plans with at least 8192 output vectors (bound
+ *                    from the streamed operand) use it: fewer could not give
+ *                    the chip's wavefronts one vector each.
  */
 typedef struct {
     int32_t tiny_max_flops;

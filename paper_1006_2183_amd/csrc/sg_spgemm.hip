@@ -220,6 +220,11 @@ struct sg_plan {
   const ChainDev *chains = nullptr;
   int chain_ts = 0;   // hash slots per stage of the chain mid tier
   int lds_chain = 0;  // its dynamic LDS bytes
+  // small-list bound in effect: the tuning's, for plans with enough output
+  // vectors to give every wavefront of the chip one (kSmallMinVectors);
+  // otherwise 0, since one wavefront per vector leaves a plan of few
+  // vectors waiting on the longest vector's gather and sort
+  int32_t small_max = 0;
 };
 
 namespace {
@@ -587,7 +592,7 @@ sg_status launch_counts(sg_plan *pl, hipStream_t st) {
   const int64_t tiny_blocks = std::min<int64_t>(std::max<int64_t>(1, (pl->nov_max + 3) / 4), persist * 8);
   hipLaunchKernelGGL((k_tiny<K, true>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, pl->P);
   SG_HIP(hipGetLastError());
-  if (pl->tune.small_max_flops > 0 || pl->tune.force_tier == 3) {
+  if (pl->small_max > 0 || pl->tune.force_tier == 3) {
     hipLaunchKernelGGL((k_small<K, true, false>), dim3((unsigned)tiny_blocks), dim3(256), 0, st, pl->P);
     SG_HIP(hipGetLastError());
   }
@@ -983,6 +988,7 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
   pl->ncu = device_cus();
   pl->dense_path = sh.dense_path;
   pl->nov_max = sh.nov_max;
+  pl->small_max = sh.nov_max >= kSmallMinVectors ? t.small_max_flops : 0;
   pl->ndense_ptr = sh.ndense_ptr;
   pl->out_minor = sh.minor;
   pl->out_major = sh.major;
@@ -1181,7 +1187,7 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
   // flops per output vector, then the tiers
   if (sh.nov_max > 0) {
     const int64_t waves = std::min<int64_t>(sh.nov_max, (int64_t)pl->ncu * 64);
-    BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier, t.small_max_flops};
+    BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier, pl->small_max};
     hipLaunchKernelGGL(k_flops_bin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, bp, L.gstat, L.counters,
                        L.tiny, L.mid, L.heavy, L.small);
     SG_HIP(hipGetLastError());

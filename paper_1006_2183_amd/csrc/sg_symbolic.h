@@ -266,6 +266,8 @@ struct BinParams {
 // Products of a small-list vector at most (eight per lane of a wavefront).
 constexpr int kSmallPerLane = 8;
 constexpr int kSmallMaxFlops = kSmallPerLane * kWave;
+// Output vectors (upper bound) from which a plan uses the small list.
+constexpr int64_t kSmallMinVectors = 8192;
 
 // G vector of stored S entry e (-1: absent); a doubly compressed G is
 // resolved through AUX and the result kept in d.gres for the numeric kernels.
