@@ -124,9 +124,10 @@ typedef struct {
  *   force_tier       -1 = bin by size; 0/1/2 = route every vector with
  *                    work to the tiny / mid / heavy tier where it is legal
  *                    (tiny needs flops <= 64, mid needs the bound to fit);
- *                    3 = every vector with at most 512 multiplications to
- *                    the mid tier's one-wavefront form (small_max_flops),
- *                    the others by size
+ *                    3 = every vector with at most 1024 multiplications
+ *                    (and an id range below 2^22 - 1) to the mid tier's
+ *                    one-wavefront form (small_max_flops), the others by
+ *                    size
  *   blocks_per_cu    workgroups per compute unit of the persistent launches
  *   validate         non-zero: run sg_validate on every operand first
  *   xcd_ranges       heavy tier: the output id range is cut into 8 x this
@@ -160,11 +161,13 @@ typedef struct {
  *                    for a plan whose numeric phase is replayed). Mid-tier
  *                    vectors of a plan with records get records too.
  *   small_max_flops  mid tier: vectors with more than tiny_max_flops and at
- *                    most this many multiplications (<= 512) run one per
- *                    wavefront, with no LDS and no workgroup barrier: their
- *                    products are gathered into registers (8 per lane),
- *                    sorted by id with a register bitonic network, merged
- *                    and written (0 = off: every mid vector takes a
+ *                    most this many multiplications (<= 1024), whose id
+ *                    range is below 2^22 - 1, run one per wavefront with no
+ *                    workgroup barrier: their ids are gathered into
+ *                    registers (16 per lane) and their products into the
+ *                    wavefront's LDS, (id, slot) keys are sorted with a
+ *                    register bitonic network, and runs of equal ids are
+ *                    summed and written (0 = off: every mid vector takes a
  *                    workgroup's LDS accumulator). They count as mid-tier
  *                    vectors in the per-tier totals (n_small of sg_sym_info).
  *                    Only plans with at least 8192 output vectors (bound

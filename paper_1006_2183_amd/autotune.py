@@ -36,6 +36,7 @@ SPACE: Dict[str, List[int]] = {
     "mid_max_ub": [4096, 16384, 65535],
     "tiny_max_flops": [16, 32, 64],
     "entry_mb": [0, 1024],
+    "small_max_flops": [0, 512, 1024],
 }
 
 
@@ -141,6 +142,7 @@ REPLAY_PRESETS: List[Dict[str, int]] = [
 ]
 REPLAY_SPACE: Dict[str, List[int]] = {
     "entry_mb": [0, 256, 1024],
+    "small_max_flops": [0, 512, 1024],
     "mid_max_ub": [1024, 2048, 65535],
     "tiny_max_flops": [32, 64],
     "bitmap_mb": [0, 4096],

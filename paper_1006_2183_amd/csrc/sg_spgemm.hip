@@ -65,6 +65,10 @@ int slot_bytes(int32_t kind) {
   }
 }
 
+// Dynamic LDS of a numeric small-list launch (256 threads): each wavefront's
+// kSmallMaxFlops values.
+int small_lds(int32_t kind) { return (256 / kWave) * kSmallMaxFlops * slot_bytes(kind); }
+
 int64_t major_of(const sg_mat &M) { return row_major(M.fmt) ? M.nrows : M.ncols; }
 int64_t minor_of(const sg_mat &M) { return row_major(M.fmt) ? M.ncols : M.nrows; }
 
@@ -663,7 +667,7 @@ sg_status launch_numeric(sg_plan *pl, hipStream_t st) {
     SG_TRY(mark(pl, 2, false, st));
     if (I.n_small > 0)
       hipLaunchKernelGGL((k_small<K, false, true>), dim3((unsigned)std::min<int64_t>((I.n_small + 3) / 4, persist * 8)),
-                         dim3(256), 0, st, P);
+                         dim3(256), small_lds(pl->kind), st, P);
     if (I.n_tiny > 0)
       hipLaunchKernelGGL((k_tiny<K, false>), dim3((unsigned)std::min<int64_t>((I.n_tiny + 3) / 4, persist * 8)), dim3(256),
                          0, st, P);
@@ -707,8 +711,8 @@ sg_status launch_batched(sg_plan *pl, hipStream_t st) {
   // persistent workgroups are sized for, which measured slower
   if (I.n_small > 0) {
     const int64_t sp = (int64_t)pl->ncu * pl->tune.blocks_per_cu * 8;
-    hipLaunchKernelGGL((k_small<K, false, true>), dim3((unsigned)std::min<int64_t>((I.n_small + 3) / 4, sp)), dim3(256), 0,
-                       st, pl->P);
+    hipLaunchKernelGGL((k_small<K, false, true>), dim3((unsigned)std::min<int64_t>((I.n_small + 3) / 4, sp)), dim3(256),
+                       small_lds(pl->kind), st, pl->P);
     SG_HIP(hipGetLastError());
   }
   const int mode = pl->has_mode[0] && pl->has_mode[1] ? 2 : (pl->has_mode[1] ? 1 : 0);

@@ -263,9 +263,12 @@ struct BinParams {
   int32_t small_max;  // mid-tier vectors up to this many products go to the small list (0: none)
 };
 
-// Products of a small-list vector at most (eight per lane of a wavefront).
-constexpr int kSmallPerLane = 8;
+// Products of a small-list vector at most (sixteen per lane of a wavefront),
+// and the largest id range it may have (its ids are packed with a 10-bit slot
+// into 32-bit sort keys, and the all-ones key is the padding).
+constexpr int kSmallPerLane = 16;
 constexpr int kSmallMaxFlops = kSmallPerLane * kWave;
+constexpr int64_t kSmallMaxMinor = ((int64_t)1 << 22) - 1;
 // Output vectors (upper bound) from which a plan uses the small list.
 constexpr int64_t kSmallMinVectors = 8192;
 
@@ -449,9 +452,9 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
         if (f == 0) tier = -1;
         else if (bp.force == 2) tier = 2;
         else if (bp.force == 1) tier = mid_fit ? 1 : 2;
-        else if (bp.force == 3 && f <= kSmallMaxFlops) tier = 3;
+        else if (bp.force == 3 && f <= kSmallMaxFlops && minor <= kSmallMaxMinor) tier = 3;
         else if (f <= bp.tiny_max) tier = 0;
-        else if (f <= bp.small_max) tier = 3;
+        else if (f <= bp.small_max && minor <= kSmallMaxMinor) tier = 3;
         else if (mid_fit && nsplit > 1) tier = 1;
         else tier = 2;
       }

@@ -1275,46 +1275,45 @@ __device__ __forceinline__ void mid_item(const Plan &P, int64_t m, uint32_t *lds
 
 // ---------------------------------------------------------------------------
 // Small list: a mid-tier vector of at most kSmallMaxFlops products on one
-// wavefront, with no LDS and no workgroup barrier. Its products are
-// gathered into registers, kSmallPerLane per lane (product s of the vector
-// goes to lane s mod 64, register s / 64), with every gather load in flight
-// before the first is used; a bitonic network then sorts the 64 x 8
-// (id, value) pairs into lane-major order (element e = 8 lane + register),
-// exchanging registers inside a lane for distances below 8 and lanes on the
-// VALU (xor_lane) for the others; equal ids are merged by a running (+)
-// inside each lane and a segmented prefix across lanes; each lane writes its
-// run ends at their ranks. Padding slots hold id INT32_MAX and sort last.
-// A vector of at most 64 ep products (ep = 1, 2, 4 or 8, the smallest that
-// holds it) sorts only registers 0 .. ep - 1 (element e = ep lane + j): the
-// network's work grows with ep, so a vector of 100 products costs a sort of
-// 128 elements, not 512. The network is a loop over its stages, one code
-// block per exchange distance, not unrolled: a fully unrolled network is about twelve thousand
-// instructions, which every wavefront would stream through the instruction
-// cache for each vector.
-// One stage across lanes: element e and e xor (LM * E) compare-exchange,
+// wavefront, with no workgroup barrier. Product s of the vector (its slot)
+// goes to lane s mod 64, register s / 64: its id into a register, its
+// value (the S value times the G value) into the wavefront's own LDS array
+// at index s. Every gather load of a half of the registers is in flight
+// before the first is used. The registers then hold packed keys
+// (id << 10 | slot), which a bitonic network sorts into lane-major order
+// (element e = ep lane + j for the ep registers in use, ep = 1, 2, 4, 8 or
+// 16, the fewest that hold the vector): a key names its value's slot, so
+// only the 32-bit keys move through the network. Equal ids end up adjacent
+// in slot order; their values are read back from LDS and summed in that
+// order (a lane's trailing run and the segmented prefix of those across
+// lanes give each lane the part of its first run held by earlier lanes),
+// and each lane writes its run ends at their ranks. Padding slots hold the
+// key 0xFFFFFFFF and sort last; ids stay below 2^22 - 1 (kSmallMaxMinor)
+// so that no packed key reaches it. The network is a loop over its stages,
+// one code block per exchange distance, not unrolled: a fully unrolled
+// network is thousands of instructions, which every wavefront would stream
+// through the instruction cache for each vector.
+constexpr uint32_t kSmallPad = 0xFFFFFFFFu;
+constexpr int kSmallSlotBits = 10;  // slots < kSmallMaxFlops
+
+// One stage across lanes: element e and e xor (LM * ep) compare-exchange,
 // ascending where e & k is 0.
-template <class SR, int E, int LM>
-__device__ __forceinline__ void small_xstage(int32_t (&key)[E], typename SR::T (&val)[E], int k, int ep) {
-  typedef typename SR::T T;
+template <int E, int LM>
+__device__ __forceinline__ void small_xstage(uint32_t (&key)[E], int k, int ep) {
   const int l = lane();
   const bool low = (l & LM) == 0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    if (j >= ep) break;  // uniform: registers past the vector's ep hold padding only
-    const int32_t pk = xor_lane(key[j], LM);
-    const T pv = SR::kVal ? xor_lane(val[j], LM) : T();
+    if (j >= ep) break;  // uniform: registers past ep hold padding only
+    const uint32_t pk = xor_lane(key[j], LM);
     const bool up = ((l * ep + j) & k) == 0;
-    const bool take = low ? (up ? pk < key[j] : pk > key[j]) : (up ? pk > key[j] : pk < key[j]);
-    if (take) {
-      key[j] = pk;
-      if (SR::kVal) val[j] = pv;
-    }
+    const bool take = low == up ? pk < key[j] : pk > key[j];
+    key[j] = take ? pk : key[j];
   }
 }
 // One stage inside a lane: registers j and j + M.
-template <class SR, int E, int M>
-__device__ __forceinline__ void small_istage(int32_t (&key)[E], typename SR::T (&val)[E], int k, int ep) {
-  typedef typename SR::T T;
+template <int E, int M>
+__device__ __forceinline__ void small_istage(uint32_t (&key)[E], int k, int ep) {
   const int l = lane();
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -1322,40 +1321,31 @@ __device__ __forceinline__ void small_istage(int32_t (&key)[E], typename SR::T (
     if (j >= ep) break;
     const int jp = j | M;
     const bool up = ((l * ep + j) & k) == 0;
-    const bool sw = up ? key[j] > key[jp] : key[j] < key[jp];
-    if (sw) {
-      const int32_t tk = key[j];
-      key[j] = key[jp];
-      key[jp] = tk;
-      if (SR::kVal) {
-        const T tv = val[j];
-        val[j] = val[jp];
-        val[jp] = tv;
-      }
-    }
+    const uint32_t a = key[j], b = key[jp];
+    const bool sw = up ? a > b : a < b;
+    key[j] = sw ? b : a;
+    key[jp] = sw ? a : b;
   }
 }
 
+// wvals: this wavefront's LDS array of kSmallMaxFlops values (unused when
+// counting or without values).
 template <int K, bool COUNT, bool RECS>
-__device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p) {
+__device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p, typename Sr<K>::T *wvals) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   constexpr int E = kSmallPerLane;
-  static_assert(E == 8, "the stage blocks below cover in-lane distances 4, 2, 1");
+  constexpr int H = E / 2;  // registers per gather half
+  constexpr bool kVals = SR::kVal && !COUNT;
+  static_assert(E == 16 && kSmallMaxFlops == (1 << kSmallSlotBits), "stage blocks and slot bits below");
   const int l = lane();
-  int32_t key[E];
-  T val[E];  // gathered G values, then products
+  uint32_t key[E];  // gathered ids, then packed keys
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    key[j] = INT32_MAX;
-    val[j] = T();
-  }
+  for (int j = 0; j < E; ++j) key[j] = kSmallPad;
   int filled = 0;
   // one batch of up to 64 entries, one per lane: `len` products whose ids
   // start at address ia and values at va (S value sv); products f of the
-  // batch go to slots filled + f. Every gather of the batch is issued before
-  // the first product is formed; the owner lane of each register's product
-  // is kept packed (8 bits per register) to fetch its S value afterwards.
+  // batch go to slots filled + f
   auto place = [&](int len, int64_t ia, int64_t va, T sv) {
     const int incl = wave_incl_scan(len);
     const int tot = read_lane(incl, kWave - 1);
@@ -1363,48 +1353,55 @@ __device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p
     const int st = incl - len;  // the entry's first product in the batch
     const int64_t ia0 = ia - (int64_t)st * (int64_t)sizeof(int32_t);  // id address of product 0 of the entry
     const int64_t va0 = va - (int64_t)st * (int64_t)sizeof(T);
-    uint32_t own[2] = {0u, 0u};
-    uint32_t got = 0;  // registers this lane gathered into in this batch
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int f0 = j * kWave - filled;  // the batch product in this register of lane 0
-      if (f0 >= tot || f0 + kWave <= 0) continue;  // uniform: no lane has a product in this register
-      const int f = f0 + l;
-      const bool mine = f >= 0 && f < tot;
-      // the entry of each lane's product: the entry of the register's first
-      // product, unless an entry starts later in the register (a few such
-      // starts are taken in order; many, by a binary search)
-      const int r0 = f0 > 0 ? f0 : 0;
-      int o = (int)__popcll(__ballot(incl <= r0));
-      const uint64_t starts = __ballot(len > 0 && st > r0 && st < f0 + kWave);
-      if (starts) {
-        if (__popcll(starts) <= 4) {
-          uint64_t m = starts;
-          while (m) {
-            const int x = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            if (f >= read_lane(st, x)) o = x;
+    for (int h = 0; h < 2; ++h) {
+      T gv[H];
+      uint32_t own[2] = {0u, 0u};  // owner lane of each register's product, 8 bits each
+      uint32_t got = 0;
+#pragma unroll
+      for (int jj = 0; jj < H; ++jj) {
+        const int j = h * H + jj;
+        gv[jj] = T();
+        const int f0 = j * kWave - filled;  // the batch product in this register of lane 0
+        if (f0 >= tot || f0 + kWave <= 0) continue;  // uniform: no lane has a product in this register
+        const int f = f0 + l;
+        const bool mine = f >= 0 && f < tot;
+        // the entry of each lane's product: the entry of the register's
+        // first product, unless entries start later in the register (a few
+        // are taken in order; many, by a binary search)
+        const int r0 = f0 > 0 ? f0 : 0;
+        int o = (int)__popcll(__ballot(incl <= r0));
+        const uint64_t starts = __ballot(len > 0 && st > r0 && st < f0 + kWave);
+        if (starts) {
+          if (__popcll(starts) <= 4) {
+            uint64_t m = starts;
+            while (m) {
+              const int x = __ffsll((unsigned long long)m) - 1;
+              m &= m - 1;
+              if (f >= read_lane(st, x)) o = x;
+            }
+          } else {
+            o = owner_of(incl, mine ? f : 0);
           }
-        } else {
-          o = owner_of(incl, mine ? f : 0);
+        }
+        const int64_t a = __shfl(ia0, o, kWave) + (int64_t)f * (int64_t)sizeof(int32_t);
+        const int64_t b = kVals ? __shfl(va0, o, kWave) + (int64_t)f * (int64_t)sizeof(T) : 0;
+        own[jj >> 2] |= (uint32_t)o << (8 * (jj & 3));
+        if (mine) {
+          key[j] = (uint32_t)gload((const int32_t *)a);
+          if (kVals) gv[jj] = gload((const T *)b);
+          got |= 1u << jj;
         }
       }
-      const int64_t a = __shfl(ia0, o, kWave) + (int64_t)f * (int64_t)sizeof(int32_t);
-      const int64_t b = SR::kVal ? __shfl(va0, o, kWave) + (int64_t)f * (int64_t)sizeof(T) : 0;
-      own[j >> 2] |= (uint32_t)o << (8 * (j & 3));
-      if (mine) {
-        key[j] = gload((const int32_t *)a);
-        if (SR::kVal) val[j] = gload((const T *)b);
-        got |= 1u << j;
-      }
-    }
-    if (SR::kVal) {
+      if (kVals) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int f0 = j * kWave - filled;
-        if (f0 + kWave <= 0 || f0 >= tot) continue;  // uniform: no lane gathered into register j
-        const T sj = __shfl(sv, (int)((own[j >> 2] >> (8 * (j & 3))) & 63u), kWave);
-        if ((got >> j) & 1u) val[j] = SR::mul(sj, val[j]);
+        for (int jj = 0; jj < H; ++jj) {
+          const int j = h * H + jj;
+          const int f0 = j * kWave - filled;
+          if (f0 + kWave <= 0 || f0 >= tot) continue;  // uniform: no lane gathered into register j
+          const T sj = __shfl(sv, (int)((own[jj >> 2] >> (8 * (jj & 3))) & 63u), kWave);
+          if ((got >> jj) & 1u) wvals[j * kWave + l] = SR::mul(sj, gv[jj]);
+        }
       }
     }
     filled += tot;
@@ -1436,65 +1433,48 @@ __device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p
       }
     }
   }
-  // registers in use: the vector's products fill ceil(filled / 64) of them
-  const int ep = filled <= kWave ? 1 : (filled <= 2 * kWave ? 2 : (filled <= 4 * kWave ? 4 : 8));
-  // bitonic sort of the ep x 64 elements, element e = ep lane + j, ascending id
+  // packed keys; registers in use: the vector's products fill ceil(filled / 64) of them
+#pragma unroll
+  for (int j = 0; j < E; ++j)
+    if (key[j] != kSmallPad) key[j] = (key[j] << kSmallSlotBits) | (uint32_t)(j * kWave + l);
+  const int ep = filled <= kWave ? 1 : (filled <= 2 * kWave ? 2 : (filled <= 4 * kWave ? 4 : (filled <= 8 * kWave ? 8 : 16)));
+  // bitonic sort of the ep x 64 keys, element e = ep lane + j, ascending
   for (int k = 2; k <= ep * kWave; k <<= 1) {
     for (int m = k >> 1; m >= ep; m >>= 1) {
       switch (uni(m / ep)) {  // the lane distance, uniform: one code block per distance
-        case 1: small_xstage<SR, E, 1>(key, val, k, ep); break;
-        case 2: small_xstage<SR, E, 2>(key, val, k, ep); break;
-        case 4: small_xstage<SR, E, 4>(key, val, k, ep); break;
-        case 8: small_xstage<SR, E, 8>(key, val, k, ep); break;
-        case 16: small_xstage<SR, E, 16>(key, val, k, ep); break;
-        default: small_xstage<SR, E, 32>(key, val, k, ep); break;
+        case 1: small_xstage<E, 1>(key, k, ep); break;
+        case 2: small_xstage<E, 2>(key, k, ep); break;
+        case 4: small_xstage<E, 4>(key, k, ep); break;
+        case 8: small_xstage<E, 8>(key, k, ep); break;
+        case 16: small_xstage<E, 16>(key, k, ep); break;
+        default: small_xstage<E, 32>(key, k, ep); break;
       }
     }
-    if (k >= 8 && ep > 4) small_istage<SR, E, 4>(key, val, k, ep);
-    if (k >= 4 && ep > 2) small_istage<SR, E, 2>(key, val, k, ep);
-    if (ep > 1) small_istage<SR, E, 1>(key, val, k, ep);
+    if (k >= 16 && ep > 8) small_istage<E, 8>(key, k, ep);
+    if (k >= 8 && ep > 4) small_istage<E, 4>(key, k, ep);
+    if (k >= 4 && ep > 2) small_istage<E, 2>(key, k, ep);
+    if (ep > 1) small_istage<E, 1>(key, k, ep);
   }
-  // the last register in use, its id and value (a select chain: ep is uniform)
-  int32_t klast32 = key[0];
-  T vlast = val[0];
+  // run ends: the next element (the next lane's first for the last register
+  // in use) has another id
+  const uint32_t first = key[0] >> kSmallSlotBits;
+  uint32_t klast = key[0];
 #pragma unroll
-  for (int j = 1; j < E; ++j) {
-    if (j == ep - 1) {
-      klast32 = key[j];
-      vlast = val[j];
-    }
-  }
-  // merge equal ids: a running (+) inside the lane, then the run that
-  // reaches this lane's first element from earlier lanes is carried in
-#pragma unroll
-  for (int j = 1; j < E; ++j) {
-    if (j >= ep) break;
-    if (SR::kVal && key[j] == key[j - 1]) val[j] = SR::add(val[j - 1], val[j]);
-    if (j == ep - 1) vlast = val[j];
-  }
-  if (SR::kVal) {
-    const T run = seg_prefix<SR>((uint64_t)(uint32_t)klast32, vlast);  // consecutive lanes ending in the same id
-    const int32_t pk = __shfl_up(klast32, 1, kWave);
-    const T pr = __shfl_up(run, 1, kWave);
-    if (l > 0 && pk == key[0]) {
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        if (j >= ep) break;
-        if (key[j] == key[0]) val[j] = SR::add(pr, val[j]);
-      }
-    }
-  }
-  // run ends: the next element (the next lane's first for the last register) has another id
-  const int32_t nk = __shfl_down(key[0], 1, kWave);
+  for (int j = 1; j < E; ++j)
+    if (j == ep - 1) klast = key[j];
+  const uint32_t idlast = klast >> kSmallSlotBits;
+  const uint32_t nfirst = (uint32_t)__shfl_down((int)first, 1, kWave);
   const MaskRef mk = mask_of(P, v);
   uint32_t tails = 0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     if (j >= ep) break;
+    const uint32_t id = key[j] >> kSmallSlotBits;
     const bool lastreg = j == ep - 1;
-    const int32_t next = !lastreg ? key[j + 1 < E ? j + 1 : j] : (l + 1 < kWave ? nk : INT32_MAX);
-    bool t = key[j] != INT32_MAX && (next != key[j] || (lastreg && l + 1 == kWave));
-    if (mk.on() && t) t = mk.keeps(key[j]);
+    const uint32_t next = !lastreg ? key[j + 1 < E ? j + 1 : j] >> kSmallSlotBits
+                                   : (l + 1 < kWave ? nfirst : (kSmallPad >> kSmallSlotBits));
+    bool t = key[j] != kSmallPad && (next != id || (lastreg && l + 1 == kWave));
+    if (mk.on() && t) t = mk.keeps((int64_t)id);
     tails |= (uint32_t)t << j;
   }
   const int cnt = __popc(tails);
@@ -1505,16 +1485,46 @@ __device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p
     return;
   }
   chk_count(P, l == 0 && (int64_t)total != gload(P.ov_cnt + v));
-  if (tails) {
-    const OutDev O = uload(P.outs + uload(P.ov_group + v));
-    int64_t pos = out_offset(P, v) + (incl - cnt);
+  const OutDev O = uload(P.outs + uload(P.ov_group + v));
+  int64_t pos = out_offset(P, v) + (incl - cnt);
+  if (!SR::kVal) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      if ((tails >> j) & 1u) {
-        gstore(O.idx + pos, key[j]);
-        if (SR::kVal) gstore((T *)O.val + pos, val[j]);
-        ++pos;
-      }
+      if (j >= ep) break;
+      if ((tails >> j) & 1u) gstore(O.idx + pos++, (int32_t)(key[j] >> kSmallSlotBits));
+    }
+    return;
+  }
+  __builtin_amdgcn_wave_barrier();  // the values were written by other lanes of this wavefront
+  // the lane's trailing run (slot order), then the same across lanes
+  T tail_sum = T();
+  bool have = false;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (j >= ep) break;
+    if (key[j] != kSmallPad && (key[j] >> kSmallSlotBits) == idlast) {
+      const T x = wvals[key[j] & (kSmallMaxFlops - 1)];
+      tail_sum = have ? SR::add(tail_sum, x) : x;
+      have = true;
+    }
+  }
+  const T run_lanes = seg_prefix<SR>((uint64_t)idlast, tail_sum);
+  const uint32_t pid = (uint32_t)__shfl_up((int)idlast, 1, kWave);
+  const T carry = __shfl_up(run_lanes, 1, kWave);
+  const bool carried = l > 0 && pid == first && key[0] != kSmallPad;
+  T run = T();
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (j >= ep) break;
+    if (key[j] == kSmallPad) break;
+    const uint32_t id = key[j] >> kSmallSlotBits;
+    const T x = wvals[key[j] & (kSmallMaxFlops - 1)];
+    if (j == 0) run = carried ? SR::add(carry, x) : x;
+    else run = id == (key[j - 1] >> kSmallSlotBits) ? SR::add(run, x) : x;
+    if ((tails >> j) & 1u) {
+      gstore(O.idx + pos, (int32_t)id);
+      gstore((T *)O.val + pos, run);
+      ++pos;
     }
   }
 }
@@ -1542,11 +1552,14 @@ __global__ void __launch_bounds__(1024) k_tiny(Plan P) {
 // numeric pass walks entry records where the plan has them).
 template <int K, bool COUNT, bool RECS>
 __global__ void __launch_bounds__(1024) k_small(Plan P) {
+  typedef typename Sr<K>::T T;
+  extern __shared__ uint32_t lds[];  // kSmallMaxFlops values per wavefront (numeric pass)
+  T *wvals = (T *)lds + (threadIdx.x / kWave) * kSmallMaxFlops;
   const int64_t nm = P.counters[kCtMid];
   const int64_t n = P.counters[kCtSmall];
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t i = wave; i < n; i += nwaves) small_vector<K, COUNT, RECS>(P, uload(P.small_list + i), nm + i);
+  for (int64_t i = wave; i < n; i += nwaves) small_vector<K, COUNT, RECS>(P, uload(P.small_list + i), nm + i, wvals);
 }
 
 template <int K>

@@ -48,7 +48,7 @@ def test_status_strings_and_defaults():
         assert 4096 <= t.lds_bytes <= 160 * 1024
         assert t.heavy_threads % 64 == 0 and 64 <= t.heavy_threads <= 1024
         assert 4096 <= t.heavy_lds_bytes <= 160 * 1024
-        assert 0 <= t.small_max_flops <= 512
+        assert 0 <= t.small_max_flops <= 1024
 
 
 def _fake(fmt, nrows, ncols, nvec, nnz, with_val=True):
