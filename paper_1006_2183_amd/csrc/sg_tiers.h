@@ -391,8 +391,9 @@ __device__ __forceinline__ void for_products(const Plan &P, int64_t v, int b0, i
 // batches as wavefronts, the batches are dealt to the wavefronts round robin
 // and each takes all products of its own batches, so the chains of record
 // and gather loads run side by side instead of one batch after another;
-// with fewer, every wavefront walks every batch and takes its slice of the
-// batch's products.
+// with fewer (but more than one), each batch is shared by the wavefronts
+// whose index it is modulo the batch count; with one, every wavefront takes
+// its slice of it.
 template <class SR, class Act>
 __device__ __forceinline__ void for_products_recs(const Plan &P, int64_t rb, int32_t nrec, int wid, int nw,
                                                   Act &act) {
@@ -401,6 +402,32 @@ __device__ __forceinline__ void for_products_recs(const Plan &P, int64_t rb, int
   const int uw = uni(wid);
   const int64_t nbatch = ((int64_t)nrec + kWave - 1) / kWave;
   const bool many = nbatch >= nw;
+  if (!many && nbatch > 1) {
+    // fewer batches than wavefronts: each wavefront takes one batch (b =
+    // its index mod nbatch) and its slice of that batch's products, so every
+    // wavefront reads one level of records instead of one per batch
+    const int b = uw % (int)nbatch;
+    const int sid = uw / (int)nbatch, sn = (nw - b + (int)nbatch - 1) / (int)nbatch;
+    const int64_t x = rb + (int64_t)b * kWave + lane();
+    const bool ok = (int64_t)b * kWave + lane() < nrec;
+    const int len = ok ? gload(P.rec_len + x) : 0;
+    const int64_t gi = ok ? gload(P.rec_gi + x) : 0;
+    const int64_t gv = (SR::kVal && ok) ? gload(P.rec_gv + x) : 0;
+    const T sv = (SR::kVal && ok) ? gload((const T *)P.rec_sv + x) : T();
+    const int incl = wave_incl_scan(len);
+    const int tot = read_lane(incl, kWave - 1);
+    if (tot == 0) return;
+    const int f0 = (int)((int64_t)tot * sid / sn);
+    const int f1 = (int)((int64_t)tot * (sid + 1) / sn);
+    const int st = incl - len;
+    const int a = st > f0 ? st : f0;
+    const int e = incl < f1 ? incl : f1;
+    const int len2 = e > a ? e - a : 0;
+    const int64_t skip = a > st ? a - st : 0;
+    flat_walk<SR, Act, true>(len2, gi + skip * (int64_t)sizeof(int32_t), gv + skip * (int64_t)sizeof(T), sv, nullptr,
+                             nullptr, act);
+    return;
+  }
   const int sid = many ? 0 : uw, sn = many ? 1 : nw;
   const int64_t step = (many ? nw : 1) * (int64_t)kWave;
   // the next batch's records are requested before this batch's gathers, so
