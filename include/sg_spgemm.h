@@ -270,6 +270,28 @@ sg_status sg_spgemm_symbolic(const sg_semiring *sr, int32_t nprod,
                              sg_sym_info *info, void *stream);
 
 /*
+ * Search of the tuning knobs for one product shape (the arguments of
+ * sg_spgemm_symbolic), by timing whole runs on the device: coordinate
+ * descent from *tuning over a built-in table of settings, most influential
+ * knob first, keeping a change that is at least 2% faster. form 0 times
+ * symbolic + sg_spgemm_numeric per run, form 1 symbolic + sg_spgemm_batched,
+ * form 2 (a plan whose numeric phase is replayed) sg_spgemm_batched alone on
+ * one plan, and then searches the entry-record budget and the tier
+ * thresholds. Each time is the median of `reps` runs after one warm-up, host
+ * clock around a stream synchronisation. Every candidate computes the same
+ * product (the tiers are exact); settings the library refuses for this shape
+ * are skipped. The call allocates and frees the workspace and the outputs of
+ * every candidate itself (device memory for the largest one must be free),
+ * leaves the operands unchanged and synchronises `stream`. On return *tuning
+ * holds the best setting, *best_ms its time and *start_ms (may be NULL) the
+ * time of the setting passed in. Errors: INVALID_ARG, and those of the first
+ * (starting) run.
+ */
+sg_status sg_autotune(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B,
+                      const int32_t *group, int32_t ngroup, int32_t out_fmt, int32_t form, int32_t reps,
+                      sg_tuning *tuning, double *best_ms, double *start_ms, void *stream);
+
+/*
  * Output mask of one group (Section 6.2.2's breadth-first search removes the
  * vertices already visited from each new frontier). bits is a DEVICE bitmap:
  * bit (i, j) for output vector j (the major id: a column of column-major C)

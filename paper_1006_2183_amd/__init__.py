@@ -26,4 +26,5 @@ from .binding import (  # noqa: F401
     Mask,
     mask_set,
     chain_symbolic,
+    autotune_native,
 )

@@ -29,7 +29,7 @@ EXPORTS = ["sg_tuning_default", "sg_status_string", "sg_last_error", "sg_spgemm_
            "sg_validate", "sg_build_aux", "sg_plan_check", "sg_build_checked", "sg_coo_workspace_size",
            "sg_coo_compress", "sg_coo_emit", "sg_convert_workspace_size", "sg_convert", "sg_spgemm_symbolic_masked",
            "sg_mask_set", "sg_chain_workspace_size", "sg_chain_symbolic", "sg_convert_static",
-           "sg_convert_static_bytes"]
+           "sg_convert_static_bytes", "sg_autotune"]
 
 
 class SgError(RuntimeError):
@@ -171,6 +171,10 @@ def load_library(path: Optional[str] = None):
                                       ctypes.c_void_p]
     lib.sg_convert_static.restype = ctypes.c_int
     lib.sg_convert_static.argtypes = [P(sg_semiring), P(sg_mat), ctypes.c_int32, P(sg_mat_out), P(i64), vp]
+    lib.sg_autotune.restype = ctypes.c_int
+    lib.sg_autotune.argtypes = [P(sg_semiring), ctypes.c_int32, P(sg_mat), P(sg_mat), vp, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(sg_tuning), P(ctypes.c_double),
+                                P(ctypes.c_double), vp]
     lib.sg_convert_static_bytes.restype = ctypes.c_size_t
     lib.sg_convert_static_bytes.argtypes = []
     lib.sg_mask_set.restype = ctypes.c_int
@@ -653,3 +657,23 @@ def convert_into(semiring: str, M: DevMat, out: DevMat, static: bool = False, st
                           ctypes.byref(nv), _stream(stream)), "sg_convert")
     out._keep = ws
     return int(nv.value)
+
+
+TUNE_FORMS = {"numeric": 0, "batched": 1, "numeric_reuse": 2}
+
+
+def autotune_native(semiring: str, As: Sequence[DevMat], Bs: Sequence[DevMat], group=None, ngroup=None,
+                    out_fmt: Optional[str] = None, form: str = "numeric", reps: int = 3, tuning=None, stream=None):
+    """The library's own search (sg_autotune): returns (sg_tuning, best_ms, start_ms).
+    form as in autotune.autotune: "numeric", "batched" or "numeric_reuse"."""
+    lib = load_library()
+    sr = sg_semiring(SEMIRINGS[semiring])
+    group, ngroup = _groups(group, ngroup, len(As))
+    out_fmt = out_fmt or As[0].fmt
+    t = tuning if tuning is not None else default_tuning(semiring)
+    t = sg_tuning.from_buffer_copy(t)
+    a, b = _descs(As), _descs(Bs)
+    best, start = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib.sg_autotune(ctypes.byref(sr), len(As), a, b, group, ngroup, FORMATS[out_fmt], TUNE_FORMS[form], reps,
+                           ctypes.byref(t), ctypes.byref(best), ctypes.byref(start), _stream(stream)), "sg_autotune")
+    return t, best.value, start.value

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <type_traits>
 #include <cstdio>
 #include <cstdlib>
@@ -1319,6 +1320,146 @@ sg_status sg_plan_kernel_times(sg_plan *pl, double *out_ms, int32_t n) {
     SG_HIP(hipEventElapsedTime(&ms, pl->ev[2 * i], pl->ev[2 * i + 1]));
     out_ms[i] = ms;
   }
+  return SG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One timed run of a candidate setting: its plan, workspace and outputs are
+// allocated here and released before the next candidate.
+struct TuneCase {
+  const sg_semiring *sr;
+  int32_t nprod;
+  const sg_mat *A, *B;
+  const int32_t *group;
+  int32_t ngroup, out_fmt, form, reps;
+  hipStream_t st;
+};
+
+void free_outs(std::vector<sg_mat_out> &outs) {
+  for (sg_mat_out &o : outs) {
+    (void)hipFree(o.ptr);
+    (void)hipFree(o.vid);
+    (void)hipFree(o.idx);
+    (void)hipFree(o.val);
+  }
+  outs.clear();
+}
+
+double host_ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Median milliseconds of `reps` runs after one warm-up: symbolic plus the
+// numeric or persistent launch per run (forms 0 and 1), or the persistent
+// launch alone on one plan (form 2). A setting the library refuses returns
+// its error status and no time.
+sg_status tune_time(const TuneCase &c, const sg_tuning &t, double *ms) {
+  size_t wsb = 0;
+  SG_TRY(sg_spgemm_workspace_size(c.sr, c.nprod, c.A, c.B, c.group, c.ngroup, c.out_fmt, &t, &wsb));
+  void *ws = nullptr;
+  SG_HIP(hipMalloc(&ws, std::max<size_t>(wsb, 256)));
+  std::vector<sg_sym_info> info(c.ngroup > 0 ? c.ngroup : c.nprod);
+  std::vector<sg_mat_out> outs;
+  std::vector<double> times;
+  sg_plan *pl = nullptr;
+  sg_status rc = SG_OK;
+  const int32_t ng = (int32_t)info.size();
+  const int32_t vb = slot_bytes(c.sr->kind);
+  for (int r = 0; r <= c.reps && rc == SG_OK; ++r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!pl || c.form != 2) {
+      if (pl) (void)sg_plan_destroy(pl);
+      pl = nullptr;
+      rc = sg_spgemm_symbolic(c.sr, c.nprod, c.A, c.B, c.group, c.ngroup, c.out_fmt, &t, ws, wsb, &pl, info.data(), c.st);
+      if (rc != SG_OK) break;
+    }
+    if (outs.empty()) {
+      outs.resize(ng);
+      for (int32_t g = 0; g < ng && rc == SG_OK; ++g) {
+        int32_t p = 0;
+        while (p < c.nprod && (c.group ? c.group[p] : p) != g) ++p;
+        sg_mat_out &o = outs[g];
+        o = sg_mat_out{};
+        o.fmt = c.out_fmt;
+        o.nrows = c.A[p].nrows;
+        o.ncols = c.B[p].ncols;
+        o.cap_nnz = info[g].nnz;
+        o.cap_vec = info[g].nvec;
+        if (hipMalloc((void **)&o.ptr, sizeof(int64_t) * (size_t)(info[g].nvec + 1)) != hipSuccess ||
+            hipMalloc((void **)&o.idx, sizeof(int32_t) * (size_t)std::max<int64_t>(1, info[g].nnz)) != hipSuccess ||
+            (vb && hipMalloc(&o.val, (size_t)vb * (size_t)std::max<int64_t>(1, info[g].nnz)) != hipSuccess) ||
+            (doubly(c.out_fmt) &&
+             hipMalloc((void **)&o.vid, sizeof(int32_t) * (size_t)std::max<int64_t>(1, info[g].nvec)) != hipSuccess))
+          rc = SG_ERR_HIP;
+      }
+      if (rc != SG_OK) break;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    rc = c.form == 0 ? sg_spgemm_numeric(pl, outs.data(), c.st) : sg_spgemm_batched(pl, outs.data(), c.st);
+    if (rc == SG_OK && hipStreamSynchronize(c.st) != hipSuccess) rc = SG_ERR_HIP;
+    if (r > 0) times.push_back(host_ms_since(c.form == 2 ? t1 : t0));
+  }
+  if (pl) (void)sg_plan_destroy(pl);
+  (void)hipStreamSynchronize(c.st);
+  free_outs(outs);
+  (void)hipFree(ws);
+  if (rc != SG_OK) return rc;
+  std::sort(times.begin(), times.end());
+  *ms = times[times.size() / 2];
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_autotune(const sg_semiring *sr, int32_t nprod, const sg_mat *A, const sg_mat *B, const int32_t *group,
+                      int32_t ngroup, int32_t out_fmt, int32_t form, int32_t reps, sg_tuning *tuning, double *best_ms,
+                      double *start_ms, void *stream) {
+  if (!sr || !A || !B || !tuning || form < 0 || form > 2 || reps < 1) return SG_ERR_INVALID_ARG;
+  const TuneCase c{sr, nprod, A, B, group, ngroup, out_fmt, form, reps, (hipStream_t)stream};
+  struct Knob {
+    int32_t sg_tuning::*field;
+    std::vector<int32_t> values;
+  };
+  // most influential knob first; the replayed form searches the record
+  // budget and the tier thresholds, the others the launch shapes too
+  const std::vector<Knob> knobs =
+      form == 2 ? std::vector<Knob>{{&sg_tuning::entry_mb, {0, 256, 1024}},
+                                    {&sg_tuning::small_max_flops, {0, 512, 1024}},
+                                    {&sg_tuning::mid_max_ub, {1024, 2048, 65535}},
+                                    {&sg_tuning::tiny_max_flops, {32, 64}},
+                                    {&sg_tuning::bitmap_mb, {0, 4096}}}
+                : std::vector<Knob>{{&sg_tuning::heavy_lds_bytes, {78848, 131072, 159744}},
+                                    {&sg_tuning::heavy_threads, {512, 1024}},
+                                    {&sg_tuning::lds_bytes, {32768, 49152, 65536, 78848, 98304, 131072}},
+                                    {&sg_tuning::blocks_per_cu, {1, 2, 3, 4}},
+                                    {&sg_tuning::block_threads, {256, 512}},
+                                    {&sg_tuning::mid_max_ub, {4096, 16384, 65535}},
+                                    {&sg_tuning::tiny_max_flops, {16, 32, 64}},
+                                    {&sg_tuning::small_max_flops, {0, 512, 1024}}};
+  sg_tuning best = *tuning;
+  double best_t = 0.0;
+  SG_TRY(tune_time(c, best, &best_t));
+  if (start_ms) *start_ms = best_t;
+  for (const Knob &k : knobs) {
+    for (int32_t v : k.values) {
+      if (best.*(k.field) == v) continue;
+      sg_tuning cand = best;
+      cand.*(k.field) = v;
+      double t = 0.0;
+      if (tune_time(c, cand, &t) != SG_OK) continue;  // a setting the library refuses for this shape
+      if (t < best_t * 0.98) {
+        best = cand;
+        best_t = t;
+      }
+    }
+  }
+  *tuning = best;
+  if (best_ms) *best_ms = best_t;
   return SG_OK;
 }
 

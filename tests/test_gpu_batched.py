@@ -208,6 +208,22 @@ def test_autotune_keeps_results(sg, tmp_path):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("form", ["numeric", "batched", "numeric_reuse"])
+def test_native_autotune(sg, form):
+    """The library's own search (sg_autotune, through the C ABI): it returns a
+    setting no slower than the one it started from, and that setting computes
+    the oracle's product."""
+    semiring = "plus_times_f64"
+    _say(f"case native autotune {form}")
+    A = W.rmat_matrix(11, 16, semiring, "csr", seed=3)
+    dA = sg.DevMat.from_host(A, "cuda", semiring)
+    R, _ = oracle.spgemm(semiring, A, A)
+    t, best, start = sg.autotune_native(semiring, [dA], [dA], form=form, reps=1)
+    assert 0.0 < best <= start
+    C = sg.spgemm(semiring, dA, dA, tuning=t, batched=form != "numeric").to_host()
+    assert_same(C, R, semiring, 1e-12, f"native autotune {form}")
+
+
 def test_autotune_replay_presets_keep_results(sg):
     """The replayed-form search (presets first, then the record budget and tier
     thresholds) on a small SUMMA share: the chosen setting computes the
