@@ -120,3 +120,23 @@ def test_binding_has_no_cpu_fallback():
         if f.endswith(".py"):
             src = open(os.path.join(pkg, f)).read()
             assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_autotune_argument_checks():
+    """sg_autotune refuses bad arguments before touching the device."""
+    from paper_1006_2183_amd import binding
+    lib = _lib()
+    A = (binding.sg_mat * 1)(_fake("csr", 100, 80, 100, 500))
+    B = (binding.sg_mat * 1)(_fake("csr", 80, 60, 80, 400))
+    sr = binding.sg_semiring(0)
+    t = binding.default_tuning("plus_times_f64")
+    best, start = ctypes.c_double(0.0), ctypes.c_double(0.0)
+
+    def call(form=0, reps=1, tuning=True, semiring=True):
+        return lib.sg_autotune(ctypes.byref(sr) if semiring else None, 1, A, B, None, 1, 0, form, reps,
+                               ctypes.byref(t) if tuning else None, ctypes.byref(best), ctypes.byref(start), None)
+    assert call(form=3) == -1
+    assert call(form=-1) == -1
+    assert call(reps=0) == -1
+    assert call(tuning=False) == -1
+    assert call(semiring=False) == -1
