@@ -703,6 +703,19 @@ def suite_bfs(sg, torch, W, count, qps_list, scale=20, seed=1, kmax=32, max_leve
             del done, reqs
         out["levels"].append(line)
     out["exact"] = f"{checked} served requests checked level by level against the oracle's BFS (bit-exact)"
+    # CPU baseline: the oracle's BFS (plain Python, one thread) on the first
+    # requests, as many as fit about 10 s
+    t0 = time.perf_counter()
+    nreq = nsrc = 0
+    while nreq < count and (nreq == 0 or time.perf_counter() - t0 < 10.0):
+        OB.bfs_levels(A, srcs[nreq], max_levels=max_levels)
+        nsrc += len(srcs[nreq])
+        nreq += 1
+    dt = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": round(nreq / dt, 4), "unit": "requests/s", "cores": 1, "kind": "oracle",
+                           "sources_per_s": round(nsrc / dt, 3), "host": host_info(),
+                           "sample": f"the first {nreq} requests ({nsrc} sources, depth {max_levels}), one "
+                                     f"level-set search per source in plain Python, {dt:.1f} s"}
     del dA
     torch.cuda.empty_cache()
     return out
