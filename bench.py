@@ -286,6 +286,15 @@ def suite_small(sg, torch, W, reps=50):
         plan.destroy()
         out[sr] = {"flops": info["flops"], "nnz_C": info["nnz"], "product_ms": round(ms, 4),
                    "graph_replay_ms": round(ms_graph, 4)}
+        # the oracle on the same product, one thread (median of 5)
+        import oracle
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            oracle.spgemm(sr, A, A)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        out[sr]["cpu_baseline"] = {"value": round(sorted(ts)[2], 4), "unit": "ms per product", "cores": 1,
+                                   "kind": "oracle", "sample": "the whole product, median of 5 runs"}
     return out
 
 
