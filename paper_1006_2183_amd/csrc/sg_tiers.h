@@ -1323,35 +1323,127 @@ __device__ __forceinline__ void mid_item(const Plan &P, int64_t m, uint32_t *lds
 constexpr uint32_t kSmallPad = 0xFFFFFFFFu;
 constexpr int kSmallSlotBits = 10;  // slots < kSmallMaxFlops
 
-// One stage across lanes: element e and e xor (LM * ep) compare-exchange,
-// ascending where e & k is 0.
-template <int E, int LM>
-__device__ __forceinline__ void small_xstage(uint32_t (&key)[E], int k, int ep) {
+// One stage across lanes: element e and e xor (LM * EP) compare-exchange,
+// ascending where e & k is 0 (the pair's lower element keeps the minimum).
+// EP, the registers in use, is a template argument so that every register
+// index is a constant: with a run-time count the compiler indexes the key
+// array through the register file and branches per compare.
+template <int EP, int LM>
+__device__ __forceinline__ void small_xstage(uint32_t (&key)[kSmallPerLane], int k) {
   const int l = lane();
   const bool low = (l & LM) == 0;
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    if (j >= ep) break;  // uniform: registers past ep hold padding only
+  for (int j = 0; j < EP; ++j) {
     const uint32_t pk = xor_lane(key[j], LM);
-    const bool up = ((l * ep + j) & k) == 0;
-    const bool take = low == up ? pk < key[j] : pk > key[j];
-    key[j] = take ? pk : key[j];
+    const bool up = ((l * EP + j) & k) == 0;
+    const uint32_t mn = pk < key[j] ? pk : key[j], mx = pk < key[j] ? key[j] : pk;
+    key[j] = low == up ? mn : mx;
   }
 }
 // One stage inside a lane: registers j and j + M.
-template <int E, int M>
-__device__ __forceinline__ void small_istage(uint32_t (&key)[E], int k, int ep) {
+template <int EP, int M>
+__device__ __forceinline__ void small_istage(uint32_t (&key)[kSmallPerLane], int k) {
   const int l = lane();
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
+  for (int j = 0; j < EP; ++j) {
     if (j & M) continue;
-    if (j >= ep) break;
     const int jp = j | M;
-    const bool up = ((l * ep + j) & k) == 0;
+    const bool up = ((l * EP + j) & k) == 0;
     const uint32_t a = key[j], b = key[jp];
-    const bool sw = up ? a > b : a < b;
-    key[j] = sw ? b : a;
-    key[jp] = sw ? a : b;
+    const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
+    key[j] = up ? mn : mx;
+    key[jp] = up ? mx : mn;
+  }
+}
+
+// Sort and emit of a small-list vector whose products fill EP registers per
+// lane: a bitonic sort of the EP x 64 packed keys into element order
+// e = EP lane + j, then run ends, their ranks and (numeric) the run sums.
+template <int K, bool COUNT, int EP>
+__device__ __forceinline__ void small_finish(const Plan &P, int64_t v, uint32_t (&key)[kSmallPerLane],
+                                             typename Sr<K>::T *wvals) {
+  typedef Sr<K> SR;
+  typedef typename SR::T T;
+  const int l = lane();
+#pragma unroll 1
+  for (int k = 2; k <= EP * kWave; k <<= 1) {
+#pragma unroll 1
+    for (int m = k >> 1; m >= EP; m >>= 1) {
+      switch (uni(m / EP)) {  // the lane distance, uniform: one code block per distance
+        case 1: small_xstage<EP, 1>(key, k); break;
+        case 2: small_xstage<EP, 2>(key, k); break;
+        case 4: small_xstage<EP, 4>(key, k); break;
+        case 8: small_xstage<EP, 8>(key, k); break;
+        case 16: small_xstage<EP, 16>(key, k); break;
+        default: small_xstage<EP, 32>(key, k); break;
+      }
+    }
+    if constexpr (EP > 8) if (k >= 16) small_istage<EP, 8>(key, k);
+    if constexpr (EP > 4) if (k >= 8) small_istage<EP, 4>(key, k);
+    if constexpr (EP > 2) if (k >= 4) small_istage<EP, 2>(key, k);
+    if constexpr (EP > 1) small_istage<EP, 1>(key, k);
+  }
+  // run ends: the next element (the next lane's first for the last register)
+  // has another id
+  const uint32_t first = key[0] >> kSmallSlotBits;
+  const uint32_t idlast = key[EP - 1] >> kSmallSlotBits;
+  const uint32_t nfirst = (uint32_t)__shfl_down((int)first, 1, kWave);
+  const MaskRef mk = mask_of(P, v);
+  uint32_t tails = 0;
+#pragma unroll
+  for (int j = 0; j < EP; ++j) {
+    const uint32_t id = key[j] >> kSmallSlotBits;
+    const uint32_t next = j + 1 < EP ? key[j + 1 < EP ? j + 1 : j] >> kSmallSlotBits
+                                     : (l + 1 < kWave ? nfirst : (kSmallPad >> kSmallSlotBits));
+    bool t = key[j] != kSmallPad && (next != id || (j + 1 == EP && l + 1 == kWave));
+    if (mk.on() && t) t = mk.keeps((int64_t)id);
+    tails |= (uint32_t)t << j;
+  }
+  const int cnt = __popc(tails);
+  const int incl = wave_incl_scan(cnt);
+  const int total = read_lane(incl, kWave - 1);
+  if (COUNT) {
+    if (l == 0) P.ov_cnt[v] = total;
+    return;
+  }
+  chk_count(P, l == 0 && (int64_t)total != gload(P.ov_cnt + v));
+  const OutDev O = uload(P.outs + uload(P.ov_group + v));
+  int64_t pos = out_offset(P, v) + (incl - cnt);
+  if (!SR::kVal) {
+#pragma unroll
+    for (int j = 0; j < EP; ++j)
+      if ((tails >> j) & 1u) gstore(O.idx + pos++, (int32_t)(key[j] >> kSmallSlotBits));
+    return;
+  }
+  __builtin_amdgcn_wave_barrier();  // the values were written by other lanes of this wavefront
+  // the lane's trailing run (slot order), then the same across lanes
+  T tail_sum = T();
+  bool have = false;
+#pragma unroll
+  for (int j = 0; j < EP; ++j) {
+    if (key[j] != kSmallPad && (key[j] >> kSmallSlotBits) == idlast) {
+      const T x = wvals[key[j] & (kSmallMaxFlops - 1)];
+      tail_sum = have ? SR::add(tail_sum, x) : x;
+      have = true;
+    }
+  }
+  const T run_lanes = seg_prefix<SR>((uint64_t)idlast, tail_sum);
+  const uint32_t pid = (uint32_t)__shfl_up((int)idlast, 1, kWave);
+  const T carry = __shfl_up(run_lanes, 1, kWave);
+  const bool carried = l > 0 && pid == first && key[0] != kSmallPad;
+  T run = T();
+#pragma unroll
+  for (int j = 0; j < EP; ++j) {
+    if (key[j] == kSmallPad) break;
+    const uint32_t id = key[j] >> kSmallSlotBits;
+    const T x = wvals[key[j] & (kSmallMaxFlops - 1)];
+    if (j == 0) run = carried ? SR::add(carry, x) : x;
+    else run = id == (key[j > 0 ? j - 1 : 0] >> kSmallSlotBits) ? SR::add(run, x) : x;
+    if ((tails >> j) & 1u) {
+      gstore(O.idx + pos, (int32_t)id);
+      gstore((T *)O.val + pos, run);
+      ++pos;
+    }
   }
 }
 
@@ -1460,99 +1552,19 @@ __device__ __forceinline__ void small_vector(const Plan &P, int64_t v, int64_t p
       }
     }
   }
-  // packed keys; registers in use: the vector's products fill ceil(filled / 64) of them
+  // packed keys
 #pragma unroll
   for (int j = 0; j < E; ++j)
     if (key[j] != kSmallPad) key[j] = (key[j] << kSmallSlotBits) | (uint32_t)(j * kWave + l);
+  // registers in use: the vector's products fill ceil(filled / 64) of them,
+  // rounded up to a power of two
   const int ep = filled <= kWave ? 1 : (filled <= 2 * kWave ? 2 : (filled <= 4 * kWave ? 4 : (filled <= 8 * kWave ? 8 : 16)));
-  // bitonic sort of the ep x 64 keys, element e = ep lane + j, ascending
-  for (int k = 2; k <= ep * kWave; k <<= 1) {
-    for (int m = k >> 1; m >= ep; m >>= 1) {
-      switch (uni(m / ep)) {  // the lane distance, uniform: one code block per distance
-        case 1: small_xstage<E, 1>(key, k, ep); break;
-        case 2: small_xstage<E, 2>(key, k, ep); break;
-        case 4: small_xstage<E, 4>(key, k, ep); break;
-        case 8: small_xstage<E, 8>(key, k, ep); break;
-        case 16: small_xstage<E, 16>(key, k, ep); break;
-        default: small_xstage<E, 32>(key, k, ep); break;
-      }
-    }
-    if (k >= 16 && ep > 8) small_istage<E, 8>(key, k, ep);
-    if (k >= 8 && ep > 4) small_istage<E, 4>(key, k, ep);
-    if (k >= 4 && ep > 2) small_istage<E, 2>(key, k, ep);
-    if (ep > 1) small_istage<E, 1>(key, k, ep);
-  }
-  // run ends: the next element (the next lane's first for the last register
-  // in use) has another id
-  const uint32_t first = key[0] >> kSmallSlotBits;
-  uint32_t klast = key[0];
-#pragma unroll
-  for (int j = 1; j < E; ++j)
-    if (j == ep - 1) klast = key[j];
-  const uint32_t idlast = klast >> kSmallSlotBits;
-  const uint32_t nfirst = (uint32_t)__shfl_down((int)first, 1, kWave);
-  const MaskRef mk = mask_of(P, v);
-  uint32_t tails = 0;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    if (j >= ep) break;
-    const uint32_t id = key[j] >> kSmallSlotBits;
-    const bool lastreg = j == ep - 1;
-    const uint32_t next = !lastreg ? key[j + 1 < E ? j + 1 : j] >> kSmallSlotBits
-                                   : (l + 1 < kWave ? nfirst : (kSmallPad >> kSmallSlotBits));
-    bool t = key[j] != kSmallPad && (next != id || (lastreg && l + 1 == kWave));
-    if (mk.on() && t) t = mk.keeps((int64_t)id);
-    tails |= (uint32_t)t << j;
-  }
-  const int cnt = __popc(tails);
-  const int incl = wave_incl_scan(cnt);
-  const int total = read_lane(incl, kWave - 1);
-  if (COUNT) {
-    if (l == 0) P.ov_cnt[v] = total;
-    return;
-  }
-  chk_count(P, l == 0 && (int64_t)total != gload(P.ov_cnt + v));
-  const OutDev O = uload(P.outs + uload(P.ov_group + v));
-  int64_t pos = out_offset(P, v) + (incl - cnt);
-  if (!SR::kVal) {
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      if (j >= ep) break;
-      if ((tails >> j) & 1u) gstore(O.idx + pos++, (int32_t)(key[j] >> kSmallSlotBits));
-    }
-    return;
-  }
-  __builtin_amdgcn_wave_barrier();  // the values were written by other lanes of this wavefront
-  // the lane's trailing run (slot order), then the same across lanes
-  T tail_sum = T();
-  bool have = false;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    if (j >= ep) break;
-    if (key[j] != kSmallPad && (key[j] >> kSmallSlotBits) == idlast) {
-      const T x = wvals[key[j] & (kSmallMaxFlops - 1)];
-      tail_sum = have ? SR::add(tail_sum, x) : x;
-      have = true;
-    }
-  }
-  const T run_lanes = seg_prefix<SR>((uint64_t)idlast, tail_sum);
-  const uint32_t pid = (uint32_t)__shfl_up((int)idlast, 1, kWave);
-  const T carry = __shfl_up(run_lanes, 1, kWave);
-  const bool carried = l > 0 && pid == first && key[0] != kSmallPad;
-  T run = T();
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    if (j >= ep) break;
-    if (key[j] == kSmallPad) break;
-    const uint32_t id = key[j] >> kSmallSlotBits;
-    const T x = wvals[key[j] & (kSmallMaxFlops - 1)];
-    if (j == 0) run = carried ? SR::add(carry, x) : x;
-    else run = id == (key[j - 1] >> kSmallSlotBits) ? SR::add(run, x) : x;
-    if ((tails >> j) & 1u) {
-      gstore(O.idx + pos, (int32_t)id);
-      gstore((T *)O.val + pos, run);
-      ++pos;
-    }
+  switch (uni(ep)) {
+    case 1: small_finish<K, COUNT, 1>(P, v, key, wvals); break;
+    case 2: small_finish<K, COUNT, 2>(P, v, key, wvals); break;
+    case 4: small_finish<K, COUNT, 4>(P, v, key, wvals); break;
+    case 8: small_finish<K, COUNT, 8>(P, v, key, wvals); break;
+    default: small_finish<K, COUNT, 16>(P, v, key, wvals); break;
   }
 }
 
