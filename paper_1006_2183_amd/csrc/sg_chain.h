@@ -95,13 +95,7 @@ __device__ __forceinline__ bool sort_merge64(int &key, T &val) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       const int pk = xor_lane(key, j);
       const T pv = SR::kVal ? xor_lane(val, j) : T();
-      const bool up = (l & k) == 0;
-      const bool low = (l & j) == 0;
-      const bool take = low ? (up ? pk < key : pk > key) : (up ? pk > key : pk < key);
-      if (take) {
-        key = pk;
-        val = pv;
-      }
+      cmp_exchange(key, val, pk, pv, ((l & k) == 0) == ((l & j) == 0));
     }
   }
   const uint64_t k64 = (uint64_t)(uint32_t)key;

@@ -382,6 +382,19 @@ __device__ __forceinline__ float xor_lane(float x, int j) {
   return __uint_as_float(xor_lane((uint32_t)__float_as_uint(x), j));
 }
 
+// One compare-exchange of a bitonic step across lanes: the lane keeps the
+// smaller of its key and its partner's key pk when keep_min, else the larger,
+// with the value that goes with it. The choice is two selects: written as a
+// branch on the divergent comparison, the compiler emits an exec-mask diamond
+// per step.
+template <class KT, class T>
+__device__ __forceinline__ void cmp_exchange(KT &key, T &val, KT pk, T pv, bool keep_min) {
+  const bool lt = pk < key, gt = key < pk;
+  const bool take = (keep_min & lt) | (!keep_min & gt);
+  key = take ? pk : key;
+  val = take ? pv : val;
+}
+
 // One DPP move of a 64-bit value (both halves with the same control);
 // lanes without a source lane, or in rows outside ROWS, get `old`.
 template <int CTRL, int ROWS>

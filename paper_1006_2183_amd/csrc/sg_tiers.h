@@ -513,13 +513,7 @@ __device__ __forceinline__ void tiny_vector(const Plan &P, int64_t v) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       const int pk = xor_lane(key, j);
       const T pv = SR::kVal ? xor_lane(val, j) : T();
-      const bool up = (l & k) == 0;
-      const bool low = (l & j) == 0;
-      const bool take = low ? (up ? pk < key : pk > key) : (up ? pk > key : pk < key);
-      if (take) {
-        key = pk;
-        val = pv;
-      }
+      cmp_exchange(key, val, pk, pv, ((l & k) == 0) == ((l & j) == 0));
     }
   }
   // segmented (+) of equal ids: the last lane of each run ends with its total
@@ -649,13 +643,7 @@ __device__ __forceinline__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1)
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
           const uint64_t pk = xor_lane(ck, jj);
           const T pv = SR::kVal ? xor_lane(val, jj) : T();
-          const bool up = (l & k) == 0;
-          const bool low = (l & jj) == 0;
-          const bool take = low ? (up ? pk < ck : pk > ck) : (up ? pk > ck : pk < ck);
-          if (take) {
-            ck = pk;
-            val = pv;
-          }
+          cmp_exchange(ck, val, pk, pv, ((l & k) == 0) == ((l & jj) == 0));
         }
       }
       // segmented (+) of equal keys: the last lane of each run holds its total
