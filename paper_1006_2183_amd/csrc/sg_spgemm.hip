@@ -1191,7 +1191,9 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
 
   // flops per output vector, then the tiers
   if (sh.nov_max > 0) {
-    const int64_t waves = std::min<int64_t>(sh.nov_max, (int64_t)pl->ncu * 64);
+    // up to 128 wavefronts per compute unit: where they outnumber the chunks
+    // of 64 vectors, the chunks' wavefront-summed vectors are shared out
+    const int64_t waves = std::min<int64_t>(sh.nov_max, (int64_t)pl->ncu * 128);
     BinParams bp{t.tiny_max_flops, t.mid_max_ub, t.force_tier, pl->small_max};
     hipLaunchKernelGGL(k_flops_bin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, P, bp, L.gstat, L.counters,
                        L.tiny, L.mid, L.heavy, L.small);

@@ -344,11 +344,18 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
     }
     acc_f = acc_ub = acc_max = 0;
   };
-  // chunks per batch: one while the chunks do not outnumber the wavefronts
+  // chunks per batch: one while the chunks do not outnumber the wavefronts.
+  // With r >= 2 wavefronts per chunk, each chunk is shared by r of them:
+  // sub-wave 0 takes the vectors its lanes sum alone, and the vectors summed
+  // by the whole wavefront are dealt round robin to the r sub-waves (R-MAT's
+  // first rows put dozens of such vectors in one chunk); every sub-wave bins
+  // the vectors it summed.
   const int64_t nchunks = (nov + kWave - 1) / kWave;
-  const int64_t nbq = nchunks / nwaves;
+  const int64_t r = nchunks >= nwaves ? 1 : nwaves / (nchunks > 0 ? nchunks : 1);
+  const int64_t sub = wave % r, wv = wave / r, nwv = nwaves / r;
+  const int64_t nbq = nchunks / nwv;
   const int nb = nbq < 1 ? 1 : (nbq > kBatch ? kBatch : (int)nbq);
-  for (int64_t c0 = wave * nb; c0 < nchunks; c0 += nwaves * nb) {
+  for (int64_t c0 = wv * nb; c0 < nchunks; c0 += nwv * nb) {
     int8_t tier_of[kBatch];
 #pragma unroll
     for (int i = 0; i < kBatch; ++i) {
@@ -374,16 +381,20 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
         if (p == p0) {
           const int64_t e0 = gload(d.s_ptr + t), e1 = gload(d.s_ptr + t + 1);
           if (e1 - e0 <= kSerial) {
-            f = entries_flops(d, e0, e1, 1);
+            if (sub == 0) f = entries_flops(d, e0, e1, 1);
             sent = e1 - e0;
             done = true;
           }
         }
       }
       uint64_t coop = __ballot(valid && !done);
+      bool own = valid && done && sub == 0;  // this sub-wave bins the lane's vector
+      int64_t q = 0;
       while (coop) {
         const int x = __ffsll((unsigned long long)coop) - 1;
         coop &= coop - 1ull;
+        if (q++ % r != sub) continue;  // uniform: another sub-wave sums vector x
+        if (l == x) own = true;
         const int64_t vx = v0 + x;
         int64_t fx = 0, sx = 0;
         const int64_t s0x = uload(P.ov_seg + vx), s1 = uload(P.ov_seg + vx + 1);
@@ -440,7 +451,7 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
       int32_t g = -1;
       int64_t minor = 0;
       int tier = -1;
-      if (valid) {
+      if (own) {
         gstore(P.ov_flops + v, f);
         g = gload(P.ov_group + v);
         const GroupDev &G = P.groups[g];
@@ -465,10 +476,10 @@ __global__ void k_flops_bin(Plan P, BinParams bp, int64_t *gstat, int64_t *count
       }
       // group totals: registers while the chunk stays in the current group
       const int64_t ub = f < minor ? f : minor;
-      uint64_t pend = __ballot(valid);
+      uint64_t pend = __ballot(own);
       while (pend) {
         const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
-        const bool mine = valid && g == gx;
+        const bool mine = own && g == gx;
         pend &= ~__ballot(mine);
         if (gx != cur_g) {
           flush_group();
