@@ -40,9 +40,14 @@ struct ChainDev {
 
 // Per output vector: stage-1 multiplications (ov_flops) and the unmerged
 // fused count sum_{(l, s)} sum_{k in G1(:, l)} nnz(G2(:, k)), an upper bound
-// of stage 2's (chain_bound); tiers by both. One lane per vector.
+// of stage 2's (chain_bound); tiers by both. One lane per vector; a lane
+// loads four S entries' G1 pointer pairs at a time and eight G1 ids' G2
+// pointer pairs at a time, so its chain of dependent loads is about two per
+// eight multiplications rather than two per multiplication. The group totals
+// are summed over the wavefront before their atomics.
 __global__ void k_chain_flops(Plan P, const ChainDev *chains, BinParams bp, int32_t mid_cap1, int32_t mid_cap2,
                               int64_t *bound, int64_t *gstat, int64_t *counters, int32_t *tiny, int32_t *mid) {
+  constexpr int kE = 4, kQ = 8;
   const int64_t nov = counters[kCtNov];
   for (int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave * kWave; v0 < nov;
        v0 += ((int64_t)gridDim.x * blockDim.x) / kWave * kWave) {
@@ -50,34 +55,74 @@ __global__ void k_chain_flops(Plan P, const ChainDev *chains, BinParams bp, int3
     const bool valid = v < nov;
     int64_t f1 = 0, fu = 0;
     int tier = -1;
-    int32_t g = 0;
+    int32_t g = -1;
+    int64_t ubv = 0;
     if (valid) {
       const int32_t p = gload(P.seg_prod + v), t = gload(P.seg_svec + v);
-      const ChainDev &C = chains[p];
-      g = C.group;
-      for (int64_t e = gload(C.s_ptr + t); e < gload(C.s_ptr + t + 1); ++e) {
-        const int32_t l = gload(C.s_idx + e);
-        if (l < 0 || l >= C.g1_nvec) continue;
-        const int64_t a0 = gload(C.g1_ptr + l), a1 = gload(C.g1_ptr + l + 1);
-        f1 += a1 - a0;
-        for (int64_t q = a0; q < a1; ++q) {
-          const int32_t k = gload(C.g1_idx + q);
-          if (k >= 0 && k < C.g2_nvec) fu += gload(C.g2_ptr + k + 1) - gload(C.g2_ptr + k);
+      const ChainDev *C = chains + p;
+      const int32_t *s_idx = gload(&C->s_idx);
+      const int64_t *g1_ptr = gload(&C->g1_ptr);
+      const int32_t *g1_idx = gload(&C->g1_idx);
+      const int64_t *g2_ptr = gload(&C->g2_ptr);
+      const int64_t g1_nvec = gload(&C->g1_nvec), g2_nvec = gload(&C->g2_nvec);
+      const int64_t *s_ptr = gload(&C->s_ptr);
+      g = gload(&C->group);
+      const int64_t es = gload(s_ptr + t), ee = gload(s_ptr + t + 1);
+      for (int64_t e = es; e < ee; e += kE) {
+        int32_t li[kE];
+#pragma unroll
+        for (int j = 0; j < kE; ++j) li[j] = e + j < ee ? gload(s_idx + e + j) : -1;
+        int64_t a0[kE], a1[kE];
+#pragma unroll
+        for (int j = 0; j < kE; ++j) {
+          const bool ok = li[j] >= 0 && li[j] < g1_nvec;
+          a0[j] = ok ? gload(g1_ptr + li[j]) : 0;
+          a1[j] = ok ? gload(g1_ptr + li[j] + 1) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kE; ++j) {
+          f1 += a1[j] - a0[j];
+          for (int64_t q = a0[j]; q < a1[j]; q += kQ) {
+            int32_t k[kQ];
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) k[u] = q + u < a1[j] ? gload(g1_idx + q + u) : -1;
+            int64_t b0[kQ], b1[kQ];
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) {
+              const bool ok = k[u] >= 0 && k[u] < g2_nvec;
+              b0[u] = ok ? gload(g2_ptr + k[u]) : 0;
+              b1[u] = ok ? gload(g2_ptr + k[u] + 1) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) fu += b1[u] - b0[u];
+          }
         }
       }
       gstore(P.ov_flops + v, f1);
       gstore(bound + v, fu);
       const int64_t minor = P.groups[g].minor;
-      const int64_t ub1 = f1 < C.t_minor ? f1 : C.t_minor, ub2 = fu < minor ? fu : minor;
+      const int64_t t_minor = gload(&C->t_minor);
+      const int64_t ub1 = f1 < t_minor ? f1 : t_minor, ub2 = fu < minor ? fu : minor;
       if (fu == 0) tier = -1;
       else if (f1 <= bp.tiny_max && fu <= bp.tiny_max && bp.force != 1) tier = 0;
       else if (ub1 <= mid_cap1 && ub2 <= mid_cap2) tier = 1;
       else tier = 2;  // beyond the fused tiers: reported, the plan is refused
+      ubv = ub2;
     }
-    if (valid && tier == 2) atomicAdd((unsigned long long *)&counters[kCtBad], 1ull);
-    if (valid && tier >= 0) {
-      atomicAdd((unsigned long long *)&gstat[g * kStCount + kStUb], (unsigned long long)(fu < P.groups[g].minor ? fu : P.groups[g].minor));
-      atomicMax((unsigned long long *)&gstat[g * kStCount + kStMaxFlops], (unsigned long long)(f1 + fu));
+    const uint64_t bad = __ballot(valid && tier == 2);
+    if (bad && lane() == 0) atomicAdd((unsigned long long *)&counters[kCtBad], (unsigned long long)__popcll(bad));
+    // group totals, one atomic per group present in the wavefront
+    const bool counted = valid && tier >= 0;
+    uint64_t pend = __ballot(counted);
+    while (pend) {
+      const int32_t gx = __builtin_amdgcn_readlane(g, __ffsll((unsigned long long)pend) - 1);
+      const bool mine = counted && g == gx;
+      pend &= ~__ballot(mine);
+      const int64_t su = wave_sum64(mine ? ubv : 0), mx = wave_max64(mine ? f1 + fu : 0);
+      if (lane() == 0) {
+        atomicAdd((unsigned long long *)&gstat[gx * kStCount + kStUb], (unsigned long long)su);
+        atomicMax((unsigned long long *)&gstat[gx * kStCount + kStMaxFlops], (unsigned long long)mx);
+      }
     }
     append(valid && tier == 0, (int32_t)v, tiny, &counters[kCtTiny]);
     append(valid && tier == 1, (int32_t)v, mid, &counters[kCtMid]);
