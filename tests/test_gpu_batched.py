@@ -155,6 +155,51 @@ def test_graph_replay_tracks_values(sg):
     plan.destroy()
 
 
+@pytest.mark.parametrize("semiring", ["min_plus_i32", "or_and_bool"])
+def test_integer_results_bitwise_reproducible(sg, semiring):
+    """Integer and boolean semirings are exact, so every run of every form gives the same
+    bytes: eager numeric runs, persistent launches, graph replays (records and the small
+    list included), and the plain per-product path, equal to the oracle. (FP64 (+,*) is
+    not bitwise reproducible: its LDS-atomic sums follow the schedule; its runs agree to
+    the stated tolerance.)"""
+    import torch
+    from paper_1006_2183_amd import batched as BT
+    _say(f"case integer reproducibility {semiring}")
+    scale, grid = 15, 4  # 8192-wide blocks: the plan takes the small list too
+    a_blocks, b_blocks = W.summa_share(scale, 16, grid, (0, 0), semiring=semiring, seed=21)
+    dA = [sg.DevMat.from_host(x, "cuda", semiring) for x in a_blocks]
+    dB = [sg.DevMat.from_host(x, "cuda", semiring) for x in b_blocks]
+    b = (1 << scale) // grid
+    SA, SB = strips(a_blocks, b_blocks, b, grid, semiring)
+    R, _ = oracle.spgemm(semiring, SA, SB)
+    plan = BT.summa_share_plan(semiring, dA, dB, tuning=sg.make_tuning(semiring, entry_mb=64))
+    assert plan.infos[0]["n_small"] > 0
+    runs = []
+    for _ in range(2):
+        out = plan.alloc_outputs()
+        sg.spgemm_numeric(plan, out)
+        torch.cuda.synchronize()
+        runs.append(out[0].to_host())
+        out = plan.alloc_outputs()
+        sg.spgemm_batched(plan, out)
+        torch.cuda.synchronize()
+        runs.append(out[0].to_host())
+    G = BT.GraphedNumeric(plan)
+    for _ in range(3):
+        G.replay()
+        torch.cuda.synchronize()
+        runs.append(G.outputs[0].to_host())
+    runs.append(BT.summa_share(semiring, dA, dB, batched=False).to_host())
+    ref = runs[0]
+    assert_same(ref, R, semiring, 0.0, "first run vs oracle")
+    for i, c in enumerate(runs[1:]):
+        assert np.array_equal(c.ptr, ref.ptr) and np.array_equal(c.idx, ref.idx), f"run {i + 1} pattern"
+        assert np.array_equal(c.vid, ref.vid), f"run {i + 1} vector ids"
+        if ref.val is not None:
+            assert c.val.tobytes() == ref.val.tobytes(), f"run {i + 1} values"
+    plan.destroy()
+
+
 def test_galerkin_graph_chain_replay(sg):
     """A P then R (A P) captured in one graph: after scaling the operator by f,
     every replay gives R (f L_n) P = 4 f L_{n/2} exactly."""
