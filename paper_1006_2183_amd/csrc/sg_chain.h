@@ -129,25 +129,6 @@ __global__ void k_chain_flops(Plan P, const ChainDev *chains, BinParams bp, int3
   }
 }
 
-// Bitonic sort of (key, val) across the 64 lanes by key, then the segmented
-// add of equal keys: the last lane of each run holds the run's total.
-template <class SR, class T>
-__device__ __forceinline__ bool sort_merge64(int &key, T &val) {
-  const int l = lane();
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const int pk = xor_lane(key, j);
-      const T pv = SR::kVal ? xor_lane(val, j) : T();
-      cmp_exchange(key, val, pk, pv, ((l & k) == 0) == ((l & j) == 0));
-    }
-  }
-  const uint64_t k64 = (uint64_t)(uint32_t)key;
-  if (SR::kVal) val = seg_prefix<SR>(k64, val);
-  return key != INT32_MAX && next_lane_key(k64) != k64;
-}
-
 // Tiny chain vector: one wavefront, both stages in registers.
 template <int K, bool COUNT>
 __device__ void chain_tiny(const Plan &P, const ChainDev *chains, int64_t v, int64_t *gstat) {
@@ -188,7 +169,7 @@ __device__ void chain_tiny(const Plan &P, const ChainDev *chains, int64_t v, int
     }
     filled += tot;
   }
-  const bool t1 = sort_merge64<SR>(key, val);
+  const bool t1 = sort_merge64<SR>(key, val, C.t_minor < kPackMinor);
   // stage 2: every merged entry (k, t) of T streams G2(:, k)
   int len = 0;
   int64_t gb = 0;
@@ -207,7 +188,7 @@ __device__ void chain_tiny(const Plan &P, const ChainDev *chains, int64_t v, int
     key2 = gload(C.g2_idx + st + l);
     if (SR::kVal) val2 = SR::mul(so, gload((const T *)C.g2_val + st + l));
   }
-  const bool tail = sort_merge64<SR>(key2, val2);
+  const bool tail = sort_merge64<SR>(key2, val2, uload(&P.groups[C.group].minor) < kPackMinor);
   const uint64_t hm = __ballot(tail);
   if (COUNT) {
     if (l == 0) {

@@ -470,6 +470,51 @@ __device__ __forceinline__ int64_t out_offset(const Plan &P, int64_t v) {
 }
 
 // ---------------------------------------------------------------------------
+// Ids below kPackMinor - 1 pack with their 6-bit lane into one 32-bit key.
+constexpr int64_t kPackMinor = (int64_t)1 << 26;
+
+// Bitonic sort of (key, val) across the 64 lanes by key (INT32_MAX: empty
+// lane), then the segmented (+) of equal keys: the last lane of each run
+// holds the run's total, and the result says whether this lane is such a
+// last lane. With `pack` (every id of the vector's range below kPackMinor -
+// 1) only the 32-bit key id << 6 | lane moves through the network, as a min,
+// a max and a select per step, and each lane then reads its value from the
+// lane its key names; equal ids end up in lane order. Otherwise key and
+// value move together, by two selects per step. The tiny tiers spend most of
+// their instructions here, and the packed form takes about a third of them.
+template <class SR>
+__device__ __forceinline__ bool sort_merge64(int &key, typename SR::T &val, bool pack) {
+  typedef typename SR::T T;
+  const int l = lane();
+  if (pack) {
+    uint32_t kp = key == INT32_MAX ? 0xFFFFFFFFu : ((uint32_t)key << 6) | (uint32_t)l;
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const uint32_t pk = xor_lane(kp, j);
+        const uint32_t mn = pk < kp ? pk : kp, mx = pk < kp ? kp : pk;
+        kp = ((l & k) == 0) == ((l & j) == 0) ? mn : mx;
+      }
+    }
+    if (SR::kVal) val = __shfl(val, (int)(kp & (uint32_t)(kWave - 1)), kWave);
+    key = kp == 0xFFFFFFFFu ? INT32_MAX : (int)(kp >> 6);
+  } else {
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int pk = xor_lane(key, j);
+        const T pv = SR::kVal ? xor_lane(val, j) : T();
+        cmp_exchange(key, val, pk, pv, ((l & k) == 0) == ((l & j) == 0));
+      }
+    }
+  }
+  const uint64_t k64 = (uint64_t)(uint32_t)key;
+  if (SR::kVal) val = seg_prefix<SR>(k64, val);
+  return key != INT32_MAX && next_lane_key(k64) != k64;
+}
+
 // Tiny tier: one wavefront, at most 64 products.
 template <int K, bool COUNT>
 __device__ __forceinline__ void tiny_vector(const Plan &P, int64_t v) {
@@ -506,20 +551,9 @@ __device__ __forceinline__ void tiny_vector(const Plan &P, int64_t v) {
       filled += tot;
     }
   }
-  // bitonic sort of (key, val) across the 64 lanes, ascending key
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const int pk = xor_lane(key, j);
-      const T pv = SR::kVal ? xor_lane(val, j) : T();
-      cmp_exchange(key, val, pk, pv, ((l & k) == 0) == ((l & j) == 0));
-    }
-  }
-  // segmented (+) of equal ids: the last lane of each run ends with its total
-  const uint64_t k64 = (uint64_t)(uint32_t)key;
-  if (SR::kVal) val = seg_prefix<SR>(k64, val);
-  bool tail = key != INT32_MAX && next_lane_key(k64) != k64;
+  // sort by id and (+) of equal ids: the last lane of each run ends with its total
+  const int64_t minor = uload(&P.groups[uload(P.ov_group + v)].minor);
+  bool tail = sort_merge64<SR>(key, val, minor < kPackMinor);
   const MaskRef mk = mask_of(P, v);
   if (mk.on() && tail) tail = mk.keeps(key);
   const uint64_t hm = __ballot(tail);
