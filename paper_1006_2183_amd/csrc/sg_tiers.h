@@ -473,6 +473,21 @@ __device__ __forceinline__ int64_t out_offset(const Plan &P, int64_t v) {
 // Ids below kPackMinor - 1 pack with their 6-bit lane into one 32-bit key.
 constexpr int64_t kPackMinor = (int64_t)1 << 26;
 
+// Ascending bitonic sort of one 32-bit key per lane across the 64 lanes: a
+// lane exchange, a min, a max and a select per step.
+__device__ __forceinline__ void bitonic64_u32(uint32_t &kp) {
+  const int l = lane();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t pk = xor_lane(kp, j);
+      const uint32_t mn = pk < kp ? pk : kp, mx = pk < kp ? kp : pk;
+      kp = ((l & k) == 0) == ((l & j) == 0) ? mn : mx;
+    }
+  }
+}
+
 // Bitonic sort of (key, val) across the 64 lanes by key (INT32_MAX: empty
 // lane), then the segmented (+) of equal keys: the last lane of each run
 // holds the run's total, and the result says whether this lane is such a
@@ -488,15 +503,7 @@ __device__ __forceinline__ bool sort_merge64(int &key, typename SR::T &val, bool
   const int l = lane();
   if (pack) {
     uint32_t kp = key == INT32_MAX ? 0xFFFFFFFFu : ((uint32_t)key << 6) | (uint32_t)l;
-#pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        const uint32_t pk = xor_lane(kp, j);
-        const uint32_t mn = pk < kp ? pk : kp, mx = pk < kp ? kp : pk;
-        kp = ((l & k) == 0) == ((l & j) == 0) ? mn : mx;
-      }
-    }
+    bitonic64_u32(kp);
     if (SR::kVal) val = __shfl(val, (int)(kp & (uint32_t)(kWave - 1)), kWave);
     key = kp == 0xFFFFFFFFu ? INT32_MAX : (int)(kp >> 6);
   } else {
@@ -630,6 +637,8 @@ __device__ __forceinline__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1)
     const int fp = pack ? f : 0, np = pack ? ne : 0;
     const int Finc = wave_incl_scan(fp), Einc = wave_incl_scan(np);
     const OutDev O = uload(P.outs + d.group);
+    // (vector, id, lane) in one 32-bit sort key: 6 + 20 + 6 bits
+    const bool pack32 = uload(&P.groups[d.group].minor) < ((int64_t)1 << 20);
     const uint32_t *gmask = uload(&P.groups[d.group].mask);
     int64_t gstride = 0;
     int32_t gcomp = 0;
@@ -670,14 +679,24 @@ __device__ __forceinline__ void tiny_pack(const Plan &P, int64_t c0, int64_t c1)
         ck = ((uint64_t)tag_o << 32) | (uint32_t)gload(d.g_idx + g);
         if (SR::kVal) val = SR::mul(so, gload((const T *)d.g_val + g));
       }
-      // bitonic sort of (vector, id) across the 64 lanes
+      // bitonic sort of (vector, id) across the 64 lanes: packed keys with
+      // each lane's value read back from the lane its key names, or key and
+      // value moved together
+      if (pack32) {
+        uint32_t kp = l < ftot ? ((uint32_t)tag_o << 26) | ((uint32_t)ck << 6) | (uint32_t)l : 0xFFFFFFFFu;
+        bitonic64_u32(kp);
+        if (SR::kVal) val = __shfl(val, (int)(kp & (uint32_t)(kWave - 1)), kWave);
+        ck = kp == 0xFFFFFFFFu ? (((uint64_t)kWave << 32) | 0x7fffffffull)
+                               : (((uint64_t)(kp >> 26) << 32) | ((kp >> 6) & 0xFFFFFu));
+      } else {
 #pragma unroll
-      for (int k = 2; k <= kWave; k <<= 1) {
+        for (int k = 2; k <= kWave; k <<= 1) {
 #pragma unroll
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          const uint64_t pk = xor_lane(ck, jj);
-          const T pv = SR::kVal ? xor_lane(val, jj) : T();
-          cmp_exchange(ck, val, pk, pv, ((l & k) == 0) == ((l & jj) == 0));
+          for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            const uint64_t pk = xor_lane(ck, jj);
+            const T pv = SR::kVal ? xor_lane(val, jj) : T();
+            cmp_exchange(ck, val, pk, pv, ((l & k) == 0) == ((l & jj) == 0));
+          }
         }
       }
       // segmented (+) of equal keys: the last lane of each run holds its total
