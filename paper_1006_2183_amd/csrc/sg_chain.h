@@ -129,10 +129,14 @@ __global__ void k_chain_flops(Plan P, const ChainDev *chains, BinParams bp, int3
   }
 }
 
+// Groups whose count-pass multiplication totals a tiny-chain workgroup sums
+// in LDS before its global atomics.
+constexpr int kChainLdsGroups = 64;
+
 // Tiny chain vector: one wavefront, both stages in registers.
 template <int K, bool COUNT>
 __device__ __forceinline__ void chain_tiny(const Plan &P, const ChainDev *chains, int64_t v, int64_t *gstat,
-                                           int32_t &cur_g, int64_t &acc) {
+                                           unsigned long long *s_fl) {
   typedef Sr<K> SR;
   typedef typename SR::T T;
   const int l = lane();
@@ -192,16 +196,15 @@ __device__ __forceinline__ void chain_tiny(const Plan &P, const ChainDev *chains
   const bool tail = sort_merge64<SR>(key2, val2, uload(&P.groups[C.group].minor) < kPackMinor);
   const uint64_t hm = __ballot(tail);
   if (COUNT) {
-    if (l == 0) P.ov_cnt[v] = __popcll(hm);
-    // the group's multiplications, summed on the wavefront while its vectors
-    // stay in one group (one atomic per run of vectors, not per vector)
-    if (C.group != cur_g) {
-      if (cur_g >= 0 && acc && l == 0)
-        atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)acc);
-      cur_g = C.group;
-      acc = 0;
+    if (l == 0) {
+      P.ov_cnt[v] = __popcll(hm);
+      // the group's multiplications: into the workgroup's LDS total for the
+      // first kChainLdsGroups groups (one global atomic per group and
+      // workgroup at the end), straight to the global total beyond them
+      const unsigned long long fl = (unsigned long long)(filled + tot);
+      if (C.group < kChainLdsGroups) atomicAdd(&s_fl[C.group], fl);
+      else atomicAdd((unsigned long long *)&gstat[C.group * kStCount + kStFlops], fl);
     }
-    acc += filled + tot;
     return;
   }
   chk_count(P, l == 0 && (int64_t)__popcll(hm) != gload(P.ov_cnt + v));
@@ -381,11 +384,17 @@ __global__ void __launch_bounds__(256) k_chain_tiny(Plan P, const ChainDev *chai
   const int64_t n = P.counters[kCtTiny];
   const int64_t wave = uni((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  int32_t cur_g = -1;
-  int64_t acc = 0;
-  for (int64_t i = wave; i < n; i += nwaves) chain_tiny<K, COUNT>(P, chains, uload(P.tiny_list + i), gstat, cur_g, acc);
-  if (COUNT && cur_g >= 0 && acc && lane() == 0)
-    atomicAdd((unsigned long long *)&gstat[cur_g * kStCount + kStFlops], (unsigned long long)acc);
+  __shared__ unsigned long long s_fl[kChainLdsGroups];
+  if (COUNT) {
+    if (threadIdx.x < kChainLdsGroups) s_fl[threadIdx.x] = 0;
+    __syncthreads();
+  }
+  for (int64_t i = wave; i < n; i += nwaves) chain_tiny<K, COUNT>(P, chains, uload(P.tiny_list + i), gstat, s_fl);
+  if (COUNT) {
+    __syncthreads();
+    if (threadIdx.x < kChainLdsGroups && s_fl[threadIdx.x])
+      atomicAdd((unsigned long long *)&gstat[threadIdx.x * kStCount + kStFlops], s_fl[threadIdx.x]);
+  }
 }
 
 template <int K, bool COUNT>
