@@ -115,6 +115,100 @@ __global__ void k_coo_keys(const int32_t *rows, const int32_t *cols, int64_t n, 
   }
 }
 
+// Triple lists of at most kCooSmall entries are compressed by one workgroup
+// (a request's frontier, say): keys and their list positions packed into one
+// 64-bit LDS word, a bitonic sort in LDS, then run and vector heads and
+// their scans, written where the general path's sort, head and scan kernels
+// leave them. One launch instead of about fifteen.
+constexpr int kCooSmall = 4096;
+constexpr int kCooSmallBits = 12;  // list positions < kCooSmall
+constexpr int kCooSmallThreads = 1024;
+
+__global__ void __launch_bounds__(kCooSmallThreads) k_coo_small(const int32_t *rows, const int32_t *cols,
+                                                                const void *vals, int64_t n, int32_t row_major,
+                                                                int64_t nrows, int64_t ncols, int vb,
+                                                                uint64_t *keys_out, void *vals_out, int64_t *head,
+                                                                int64_t *vhead, int64_t *upos, int64_t *vpos,
+                                                                int64_t *bad) {
+  __shared__ uint64_t sk[kCooSmall];
+  __shared__ int64_t scratch[kMaxWaves + 1];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int64_t minor_dim = row_major ? ncols : nrows;
+  const uint64_t md = minor_dim > 0 ? (uint64_t)minor_dim : 1;  // for the vector heads
+  int np = 2;
+  while (np < n) np <<= 1;
+  // (key << 12 | position): equal keys keep their list order; padding sorts last
+  for (int i = t; i < np; i += nt) {
+    uint64_t e = ~0ull;
+    if (i < n) {
+      const int64_t r = gload(rows + i), c = gload(cols + i);
+      uint64_t key = 0;
+      if (r < 0 || r >= nrows || c < 0 || c >= ncols) {
+        atomicAdd((unsigned long long *)bad, 1ull);
+      } else {
+        const int64_t maj = row_major ? r : c, mnr = row_major ? c : r;
+        key = (uint64_t)(maj * minor_dim + mnr);
+      }
+      e = (key << kCooSmallBits) | (uint64_t)i;
+    }
+    sk[i] = e;
+  }
+  __syncthreads();
+  for (int k = 2; k <= np; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < np; i += nt) {
+        const int x = i ^ j;
+        if (x > i) {
+          const uint64_t a = sk[i], b = sk[x];
+          const bool up = (i & k) == 0;
+          if (up ? a > b : a < b) {
+            sk[i] = b;
+            sk[x] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // sorted keys and values, run heads and vector heads; thread t takes the
+  // consecutive positions [t * per, (t + 1) * per) for the scans
+  const int per = (int)((n + nt - 1) / nt);
+  const int i0 = t * per < n ? t * per : (int)n;
+  const int i1 = i0 + per < n ? i0 + per : (int)n;
+  int64_t nh = 0, nv = 0;
+  for (int i = i0; i < i1; ++i) {
+    const uint64_t e = sk[i];
+    const uint64_t key = e >> kCooSmallBits;
+    const int src = (int)(e & (uint64_t)(kCooSmall - 1));
+    gstore(keys_out + i, key);
+    if (vb == 8) gstore((uint64_t *)vals_out + i, gload((const uint64_t *)vals + src));
+    else if (vb == 4) gstore((uint32_t *)vals_out + i, gload((const uint32_t *)vals + src));
+    const uint64_t prev = i > 0 ? sk[i - 1] >> kCooSmallBits : ~0ull;
+    const bool h = i == 0 || key != prev;
+    const bool vh = h && (i == 0 || key / md != prev / md);
+    gstore(head + i, (int64_t)h);
+    gstore(vhead + i, (int64_t)vh);
+    nh += h;
+    nv += vh;
+  }
+  int64_t th, tv;
+  int64_t ph = block_excl_scan(nh, scratch, &th);
+  int64_t pv = block_excl_scan(nv, scratch, &tv);
+  for (int i = i0; i < i1; ++i) {
+    gstore(upos + i, ph);
+    gstore(vpos + i, pv);
+    const uint64_t key = sk[i] >> kCooSmallBits;
+    const uint64_t prev = i > 0 ? sk[i - 1] >> kCooSmallBits : ~0ull;
+    const bool h = i == 0 || key != prev;
+    ph += h;
+    pv += h && (i == 0 || key / md != prev / md);
+  }
+  if (t == 0) {
+    gstore(upos + n, th);
+    gstore(vpos + n, tv);
+  }
+}
+
 // Run heads of sorted keys (a new position) and vector heads (a new major).
 __global__ void k_key_heads(const uint64_t *keys, int64_t n, uint64_t minor_dim, int64_t *head, int64_t *vhead) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {

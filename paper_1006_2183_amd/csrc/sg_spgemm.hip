@@ -1943,6 +1943,13 @@ CooWs carve_coo(void *ws, int64_t n, int64_t major_dim, int vb) {
   return W;
 }
 
+// The ping-pong buffer that holds a triple list's sorted keys: the radix sort
+// ends in buffer (passes & 1); the one-workgroup path writes the same one.
+int coo_sort_buffer(int64_t nnz, uint64_t maxkey) {
+  const int passes = nnz <= 1 ? 0 : std::max(1, (bits_for(maxkey) + 7) / 8);
+  return passes & 1;
+}
+
 sg_status coo_args(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64_t nnz, int32_t fmt) {
   if (!sr || sr->kind < SG_PLUS_TIMES_F64 || sr->kind > SG_OR_AND_BOOL || !fmt_ok(fmt)) return SG_ERR_INVALID_ARG;
   if (nrows < 0 || ncols < 0 || nnz < 0) return SG_ERR_INVALID_ARG;
@@ -2057,7 +2064,20 @@ sg_status sg_coo_compress(const sg_semiring *sr, int64_t nrows, int64_t ncols, i
   CooWs W = carve_coo(ws, nnz, major_dim, vb);
   if (ws_bytes < W.bytes) return SG_ERR_WORKSPACE;
   int64_t h[3] = {0, 0, 0};
-  if (nnz > 0) {
+  const uint64_t maxkey = (uint64_t)std::max<int64_t>(1, major_dim) * (uint64_t)std::max<int64_t>(1, minor_dim) - 1;
+  if (nnz > 0 && nnz <= kCooSmall && bits_for(maxkey) + kCooSmallBits <= 63) {  // below the all-ones padding
+    // one workgroup; its output goes where sg_coo_emit reads the sorted list
+    SG_TRY(fill64(W.bad, 1, 0, st));
+    const int res = coo_sort_buffer(nnz, maxkey);
+    hipLaunchKernelGGL(k_coo_small, dim3(1), dim3(kCooSmallThreads), 0, st, rows, cols, vals, nnz, (int32_t)rm, nrows,
+                       ncols, vb, W.S.k[res], (void *)W.S.v[res], W.head, W.vhead, W.upos, W.vpos, W.bad);
+    SG_HIP(hipGetLastError());
+    SG_HIP(hipMemcpyAsync(&h[0], W.bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipMemcpyAsync(&h[1], W.upos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipMemcpyAsync(&h[2], W.vpos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    if (h[0] != 0) return SG_ERR_INVALID_ARG;
+  } else if (nnz > 0) {
     SG_TRY(fill64(W.bad, 1, 0, st));
     hipLaunchKernelGGL(k_coo_keys, dim3((unsigned)grid_for(nnz, kFillThreads)), dim3(kFillThreads), 0, st, rows, cols,
                        nnz, (int32_t)rm, nrows, ncols, W.S.k[0], W.bad);
@@ -2067,7 +2087,6 @@ sg_status sg_coo_compress(const sg_semiring *sr, int64_t nrows, int64_t ncols, i
     }
     SG_HIP(hipGetLastError());
     int res = 0;
-    const uint64_t maxkey = (uint64_t)std::max<int64_t>(1, major_dim) * (uint64_t)std::max<int64_t>(1, minor_dim) - 1;
     SG_TRY(radix_sort(W.S, vb, false, nnz, bits_for(maxkey), st, res));
     hipLaunchKernelGGL(k_key_heads, dim3((unsigned)grid_for(nnz, kFillThreads)), dim3(kFillThreads), 0, st, W.S.k[res],
                        nnz, (uint64_t)std::max<int64_t>(1, minor_dim), W.head, W.vhead);
@@ -2099,9 +2118,8 @@ sg_status sg_coo_emit(const sg_semiring *sr, int64_t nrows, int64_t ncols, int64
   const int32_t dbl = doubly(fmt) ? 1 : 0;
   if (!dbl) SG_TRY(fill64(W.cnt, major_dim + 1, 0, st));
   if (nnz > 0) {
-    const int passes = nnz <= 1 ? 0 : std::max(1, (bits_for((uint64_t)std::max<int64_t>(1, major_dim) *
-                                                                (uint64_t)std::max<int64_t>(1, minor_dim) - 1) + 7) / 8);
-    const int res = passes & 1;
+    const int res = coo_sort_buffer(nnz, (uint64_t)std::max<int64_t>(1, major_dim) *
+                                             (uint64_t)std::max<int64_t>(1, minor_dim) - 1);
     SG_TRY(dispatch<RunCooEmit>(sr->kind, W, res, nnz, (uint64_t)std::max<int64_t>(1, minor_dim), dbl, out, st));
   }
   if (dbl) {

@@ -84,6 +84,34 @@ def test_coo_to_sparse_repeated_positions(sg, semiring, fmt):
               40, 30, fmt, "empty")
 
 
+@pytest.mark.parametrize("semiring", SEMIRINGS)
+@pytest.mark.parametrize("fmt", FMTS)
+def test_coo_small_lists_both_paths(sg, semiring, fmt):
+    """Lists of at most 4096 triples are compressed by one workgroup (a sort of packed
+    (position, list index) keys in LDS); longer lists, and key ranges too wide to pack,
+    by the radix path. Both sides of each boundary, with repeated positions, against
+    the oracle (bit-exact: the same left fold in list order)."""
+    _say(f"case coo small {semiring} {fmt}")
+    rng = np.random.default_rng(17)
+    for n in (2, 63, 64, 65, 1000, 4095, 4096, 4097, 5000):
+        rows = rng.integers(0, 50, n)
+        cols = rng.integers(0, 70, n)
+        vals = W.random_values(rng, n, semiring)
+        _coo_case(sg, semiring, rows, cols, vals, 50, 70, fmt, f"repeats n={n}")
+        rows = rng.integers(0, 1 << 20, n)
+        cols = rng.integers(0, 600, n)
+        vals = W.random_values(rng, n, semiring)
+        _coo_case(sg, semiring, rows, cols, vals, 1 << 20, 600, fmt, f"frontier-like n={n}")
+    # a key range of 2^52 positions does not pack with 12 index bits: radix path
+    # (doubly compressed formats only: a plain pointer array of 2^26 vectors is large)
+    if fmt in ("dcsr", "dcsc"):
+        rows = rng.integers(0, 1 << 26, 300)
+        cols = rng.integers(0, 1 << 26, 300)
+        rows[1], cols[1] = rows[0], cols[0]
+        vals = W.random_values(rng, 300, semiring)
+        _coo_case(sg, semiring, rows, cols, vals, 1 << 26, 1 << 26, fmt, "wide keys")
+
+
 @pytest.mark.parametrize("semiring", ["plus_times_f64", "min_plus_i32"])
 def test_coo_matches_host_generator(sg, semiring):
     """The device build of an R-MAT matrix equals the host generator's (the same
