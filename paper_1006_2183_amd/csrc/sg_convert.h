@@ -206,6 +206,8 @@ __global__ void __launch_bounds__(kCooSmallThreads) k_coo_small(const int32_t *r
   if (t == 0) {
     gstore(upos + n, th);
     gstore(vpos + n, tv);
+    gstore(bad + 1, th);  // beside the bad-triple count, for one readback
+    gstore(bad + 2, tv);
   }
 }
 

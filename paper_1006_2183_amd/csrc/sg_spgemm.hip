@@ -622,6 +622,20 @@ sg_status launch_counts(sg_plan *pl, hipStream_t st) {
   return SG_OK;
 }
 
+// One readback of a plan's counters and its per-group statistics, which sit
+// next to each other in the workspace (the statistics from the next 256-byte
+// boundary on): every small device-to-host copy costs a copy launch of its
+// own. On return host_stats holds the span; the statistics start at word goff.
+sg_status read_stats(sg_plan *pl, const int64_t *counters, const int64_t *gstat, int64_t nstat, hipStream_t st,
+                     int64_t &goff) {
+  goff = (int64_t)(gstat - counters);
+  const size_t words = (size_t)(goff + nstat);
+  pl->host_stats.assign(words, 0);
+  SG_HIP(hipMemcpyAsync(pl->host_stats.data(), counters, sizeof(int64_t) * words, hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  return SG_OK;
+}
+
 sg_status mark(sg_plan *pl, int which, bool end, hipStream_t st) {
   if (!pl->profile) return SG_OK;
   SG_HIP(hipEventRecord(pl->ev[2 * which + (end ? 1 : 0)], st));
@@ -1252,15 +1266,12 @@ sg_status sg_spgemm_symbolic_masked(const sg_semiring *sr, int32_t nprod, const 
     SG_TRY(dispatch<RunMidRecs>(sr->kind, P, pl->ncu, st));
   }
 
-  SG_HIP(hipMemcpyAsync(pl->host_stats.data(), L.gstat, sizeof(int64_t) * (size_t)ngroup * kStCount,
-                        hipMemcpyDeviceToHost, st));
-  SG_HIP(hipMemcpyAsync(pl->host_stats.data() + (size_t)ngroup * kStCount, L.counters, sizeof(int64_t) * kCtNum,
-                        hipMemcpyDeviceToHost, st));
-  SG_HIP(hipStreamSynchronize(st));
+  int64_t goff = 0;
+  SG_TRY(read_stats(pl, L.counters, L.gstat, (int64_t)ngroup * kStCount, st, goff));
 
-  const int64_t *cnt = pl->host_stats.data() + (size_t)ngroup * kStCount;
+  const int64_t *cnt = pl->host_stats.data();
   for (int32_t g = 0; g < ngroup; ++g) {
-    const int64_t *s = pl->host_stats.data() + (size_t)g * kStCount;
+    const int64_t *s = pl->host_stats.data() + goff + (size_t)g * kStCount;
     sg_sym_info &I = pl->info[g];
     I.flops = s[kStFlops];
     I.nnz_ub = s[kStUb];
@@ -1765,12 +1776,9 @@ sg_status sg_chain_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat *
   hipLaunchKernelGGL(k_group_totals, dim3((unsigned)grid_for(nprod, 64)), dim3(64), 0, st, L.groups, nprod, L.ov_off,
                      L.nzpos, L.gstat);
   SG_HIP(hipGetLastError());
-  SG_HIP(hipMemcpyAsync(pl->host_stats.data(), L.gstat, sizeof(int64_t) * (size_t)nprod * kStCount,
-                        hipMemcpyDeviceToHost, st));
-  SG_HIP(hipMemcpyAsync(pl->host_stats.data() + (size_t)nprod * kStCount, L.counters, sizeof(int64_t) * kCtNum,
-                        hipMemcpyDeviceToHost, st));
-  SG_HIP(hipStreamSynchronize(st));
-  const int64_t *cnt = pl->host_stats.data() + (size_t)nprod * kStCount;
+  int64_t goff = 0;
+  SG_TRY(read_stats(pl, L.counters, L.gstat, (int64_t)nprod * kStCount, st, goff));
+  const int64_t *cnt = pl->host_stats.data();
   if (cnt[kCtBad] > 0) {
     snprintf(g_last_error, sizeof(g_last_error),
              "%lld output vectors need more than the fused tiers hold (%d entries per stage)", (long long)cnt[kCtBad],
@@ -1778,7 +1786,7 @@ sg_status sg_chain_symbolic(const sg_semiring *sr, int32_t nprod, const sg_mat *
     return SG_ERR_UNSUPPORTED;
   }
   for (int32_t g = 0; g < nprod; ++g) {
-    const int64_t *sg_ = pl->host_stats.data() + (size_t)g * kStCount;
+    const int64_t *sg_ = pl->host_stats.data() + goff + (size_t)g * kStCount;
     sg_sym_info &I = pl->info[g];
     I.flops = sg_[kStFlops];
     I.nnz_ub = sg_[kStUb];
@@ -2072,9 +2080,8 @@ sg_status sg_coo_compress(const sg_semiring *sr, int64_t nrows, int64_t ncols, i
     hipLaunchKernelGGL(k_coo_small, dim3(1), dim3(kCooSmallThreads), 0, st, rows, cols, vals, nnz, (int32_t)rm, nrows,
                        ncols, vb, W.S.k[res], (void *)W.S.v[res], W.head, W.vhead, W.upos, W.vpos, W.bad);
     SG_HIP(hipGetLastError());
-    SG_HIP(hipMemcpyAsync(&h[0], W.bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    SG_HIP(hipMemcpyAsync(&h[1], W.upos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    SG_HIP(hipMemcpyAsync(&h[2], W.vpos + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    // bad, nnz and nvec side by side: one readback
+    SG_HIP(hipMemcpyAsync(h, W.bad, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SG_HIP(hipStreamSynchronize(st));
     if (h[0] != 0) return SG_ERR_INVALID_ARG;
   } else if (nnz > 0) {
