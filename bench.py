@@ -634,6 +634,8 @@ def suite_serve(sg, torch, W, count, qps_list, scale=20, seed=1):
             sched = SV.Scheduler(ex, pool_entries=1 << 26, max_batch=mb, max_inflight=2 if mb > 1 else 1)
             done = sched.run(reqs)
             torch.cuda.synchronize()
+            if len(done) != count:
+                raise AssertionError(f"{name} server finished {len(done)} of {count} requests")
             st = SV.latency_stats(done)
             check([r for r in done if r.status == "done"])
             line[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}

@@ -120,9 +120,16 @@ class Scheduler:
                 self._complete(now)
             launched = False
             if self.waiting and len(self.inflight) < self.max_inflight:
+                if hasattr(self.ex, "between"):
+                    # the executor calls back between the host-blocking steps of
+                    # a launch, so batches already in flight are retired (and
+                    # their completion times taken) while the next one is planned
+                    self.ex.between = lambda: self._complete(self.clock() - self._t0) if self.inflight else None
                 batch = self._admit(self.clock() - self._t0)
                 if batch:
-                    self.inflight.append((self.ex.launch(batch), batch))
+                    # launch first: its callbacks may replace self.inflight
+                    handle = self.ex.launch(batch)
+                    self.inflight.append((handle, batch))
                     self.batches += 1
                     launched = True
             if not launched:
@@ -304,6 +311,7 @@ class FrontierBatchExecutor:
         self.next = 0
         self.timing = timing
         self.intervals = []
+        self.between = None  # called between a launch's host-blocking steps (set by the scheduler)
         torch.cuda.synchronize()
 
     def _build(self, fronts, s, si=0):
@@ -327,7 +335,11 @@ class FrontierBatchExecutor:
                 t0 = torch.cuda.Event(enable_timing=True)
                 t0.record(s)
             X, off = self._build([r.X for r in batch], s, si)
+            if self.between is not None:
+                self.between()
             plan = self.B.spgemm_symbolic("or_and_bool", [self.A], [X], out_fmt="csc", tuning=self.tuning, stream=s)
+            if self.between is not None:
+                self.between()
             (Y,) = plan.alloc_outputs(self.A.ptr.device)
             self.B.spgemm_batched(plan, [Y], s)
             ev = torch.cuda.Event(enable_timing=self.timing)

@@ -111,6 +111,37 @@ def test_continuous_batching_overlaps_batches():
     assert order == sorted(order)
 
 
+class CallbackExecutor(FakeExecutor):
+    """Calls the scheduler back in the middle of every launch, as the GPU executors
+    do between their host-blocking steps."""
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.between = None
+
+    def launch(self, batch):
+        self.clock.t += 3e-5  # planning time, during which earlier batches may end
+        if self.between is not None:
+            self.between()
+        return super().launch(batch)
+
+
+def test_callbacks_during_launch_lose_no_request():
+    """Batches retired from inside a launch's callback leave the new batch in flight:
+    every request completes exactly once."""
+    clock = FakeClock()
+    ex = CallbackExecutor(clock)
+
+    def idle():
+        clock.t += 5e-6
+
+    reqs = make_requests(400, 20000.0, seed=8)
+    done = Scheduler(ex, 1 << 30, max_batch=4, max_inflight=2, clock=clock, idle=idle).run(reqs)
+    assert len(done) == len(reqs) and all(r.status == "done" for r in done)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    assert not ex.inflight
+
+
 def test_deterministic_replay():
     a, ex_a, _ = run_fake(make_requests(200, 30000, 13), pool=50000)
     b, ex_b, _ = run_fake(make_requests(200, 30000, 13), pool=50000)
@@ -236,6 +267,7 @@ def test_gpu_frontier_servers_match_oracle():
     for ex, mb in ((FrontierBatchExecutor(dA), 16), (FrontierFifoExecutor(dA), 1)):
         reqs = [Request(i, float(arr[i]), f, frontier_bound(colcount, f)) for i, f in enumerate(fronts)]
         done = Scheduler(ex, pool_entries=1 << 24, max_batch=mb, max_inflight=2 if mb > 1 else 1).run(reqs)
+        assert len(done) == len(reqs)
         torch.cuda.synchronize()
         assert all(r.status == "done" for r in done)
         for r in done:
