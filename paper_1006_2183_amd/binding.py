@@ -517,7 +517,8 @@ def spgemm_grouped(semiring: str, As, Bs, group, ngroup, out_fmt=None, tuning=No
 
 def validate(M: DevMat, stream=None) -> bool:
     torch = _torch()
-    ws = torch.empty(64, dtype=torch.uint8, device=M.ptr.device)
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        ws = torch.empty(64, dtype=torch.uint8, device=M.ptr.device)  # on the stream the check runs on
     d = M.desc()
     st = load_library().sg_validate(ctypes.byref(d), ctypes.c_void_p(ws.data_ptr()), _stream(stream))
     if st == -3:
@@ -534,7 +535,8 @@ def build_aux(M: DevMat, stream=None):
     chunk = -(-maj // nvec) if nvec > 0 else max(maj, 1)
     chunk = max(chunk, 1)
     nchunks = -(-maj // chunk)
-    aux = torch.empty(nchunks + 1, dtype=torch.int32, device=M.ptr.device)
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        aux = torch.empty(nchunks + 1, dtype=torch.int32, device=M.ptr.device)  # on the stream that fills it
     n = ctypes.c_int64(0)
     d = M.desc()
     _check(load_library().sg_build_aux(ctypes.byref(d), ctypes.c_void_p(aux.data_ptr()), ctypes.byref(n),
