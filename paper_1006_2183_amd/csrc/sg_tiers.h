@@ -758,7 +758,7 @@ struct RankAcc {
   typedef typename SR::Slot Slot;
   static constexpr bool kFlat = true;
   static constexpr bool kSpread = false;  // consecutive ranks: consecutive banks
-  static constexpr int kRounds = 4;       // eight measured slower: more misses in flight only wait longer
+  static constexpr int kRounds = 5;       // 4: 1% slower; 8: slower, more misses in flight only wait longer
   uint32_t *words;  // 2 x uint32 per 32 ids: bits, prefix
   Slot *vals;
   int lo32;
