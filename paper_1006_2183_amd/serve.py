@@ -331,21 +331,22 @@ class FrontierBatchExecutor:
         s = self.streams[si]
         self.next += 1
         with torch.cuda.stream(s):
-            if self.timing:
-                t0 = torch.cuda.Event(enable_timing=True)
-                t0.record(s)
-            X, off = self._build([r.X for r in batch], s, si)
-            if self.between is not None:
-                self.between()
-            plan = self.B.spgemm_symbolic("or_and_bool", [self.A], [X], out_fmt="csc", tuning=self.tuning, stream=s)
-            if self.between is not None:
-                self.between()
-            (Y,) = plan.alloc_outputs(self.A.ptr.device)
-            self.B.spgemm_batched(plan, [Y], s)
-            ev = torch.cuda.Event(enable_timing=self.timing)
-            ev.record(s)
-            if self.timing:
-                self.intervals.append((si, t0, ev))
+                if self.timing:
+                    t0 = torch.cuda.Event(enable_timing=True)
+                    t0.record(s)
+                X, off = self._build([r.X for r in batch], s, si)
+                if self.between is not None:
+                    self.between()
+                plan = self.B.spgemm_symbolic("or_and_bool", [self.A], [X], out_fmt="csc", tuning=self.tuning,
+                                              stream=s)
+                if self.between is not None:
+                    self.between()
+                (Y,) = plan.alloc_outputs(self.A.ptr.device)
+                self.B.spgemm_batched(plan, [Y], s)
+                ev = torch.cuda.Event(enable_timing=self.timing)
+                ev.record(s)
+                if self.timing:
+                    self.intervals.append((si, t0, ev))
         plan.destroy()  # host only; X, Y and the workspace stay referenced until completion
         return (ev, [ColumnSlice(Y, off[i], off[i + 1]) for i in range(len(batch))], (X, plan))
 
@@ -364,13 +365,19 @@ class FrontierFifoExecutor(FrontierBatchExecutor):
         super().__init__(A, nstreams=1, tuning=tuning)
 
     def launch(self, batch: Sequence[Request]):
+        # the end of the launch is polled, as the batched server polls its
+        # events, so the two differ only in batching and overlap, not in how
+        # a finished launch is noticed
         out = []
         s = self.torch.cuda.current_stream()
         for r in batch:
             X, _ = self._build([r.X], s)
             Y = self.B.spgemm("or_and_bool", self.A, X, out_fmt="csc", stream=s)
             out.append(ColumnSlice(Y, 0, r.X.k))
-        self.torch.cuda.synchronize()
+        ev = self.torch.cuda.Event()
+        ev.record(s)
+        while not ev.query():
+            pass
         return out
 
     def poll(self, handle) -> bool:
